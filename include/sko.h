@@ -1,0 +1,194 @@
+/*
+ * sko.h -- C ABI of the MI355X (gfx950) sketched block-orthogonalisation library.
+ *
+ * Method: Yamazaki, Higgins, Boman, Szyld, "Random sketching to enhance the
+ * numerical stability of block orthogonalization algorithms for s-step GMRES",
+ * arXiv:2503.16717.  The library computes the block QR step [Q_j, R_j] = qr(Q, V_j)
+ * of Section 4 (Fig. 1 caption: Q R = V, Q^T Q = I, R upper triangular with a
+ * non-negative diagonal) by BCGS2 (Fig. 2c) with a CholQR2 (Section 5.1) or
+ * RandCholQR (Fig. 4, Section 5.2) first intra-block step, or by the two-stage
+ * scheme with RandBCGS2 pre-processing (Figs. 5, 6 and 8, Sections 6-7), and solves
+ * A x = b with restarted s-step GMRES (Fig. 1) on a CSR matrix (Section 10: A in
+ * CSR, the Krylov vectors column-major).
+ *
+ * Conventions for every entry point
+ *  - Tall arrays (n rows) are DEVICE memory owned by the caller, column-major with
+ *    a leading dimension (>= n).  Their element type is double for SKO_F64 and float
+ *    for SKO_MIXED_F32 (the basis is then stored in single precision; every small
+ *    matrix and every factorisation stays double).
+ *  - Small matrices (R factors, GMRES information) are HOST memory owned by the
+ *    caller, column-major.  Section 10: the small projected matrices live on the host.
+ *  - Work is ordered on the context's HIP stream.  A call returns after its host
+ *    outputs are valid (it synchronises that stream once, at its end).
+ *  - Nothing is thrown across the ABI; every function returns an sko_status.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef SKO_H
+#define SKO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sko_ctx_s* sko_ctx;
+
+typedef enum {
+    SKO_OK = 0,
+    SKO_EINVAL = 1,        /* bad argument: shape, leading dimension, option or NULL pointer */
+    SKO_EDEVICE = 2,       /* a HIP runtime call failed */
+    SKO_ENOMEM = 3,        /* device workspace could not be allocated */
+    SKO_EBREAKDOWN = 4,    /* non-positive / non-finite Cholesky pivot or zero Householder diagonal */
+    SKO_ENOCONV = 5,       /* GMRES reached maxiter without meeting the tolerance */
+    SKO_EUNSUPPORTED = 6   /* valid request outside what this build implements */
+} sko_status;
+
+typedef enum { SKO_F64 = 0, SKO_MIXED_F32 = 1 } sko_precision;
+typedef enum { SKO_SKETCH_GAUSSIAN = 0, SKO_SKETCH_SPARSE_SIGN = 1 } sko_sketch_kind;
+typedef enum { SKO_INTRA_CHOLQR2 = 0, SKO_INTRA_RANDCHOLQR = 1 } sko_intra;
+
+/*
+ * Random sketch Theta (n x k), applied as Theta^T X (Section 3).
+ *  SKO_SKETCH_GAUSSIAN: theta points to the caller's DEVICE array holding Theta,
+ *    column-major n x k with leading dimension ld_theta (Section 3: Theta = G/sqrt(k);
+ *    the caller draws and scales it).  zeta and seed are ignored.
+ *  SKO_SKETCH_SPARSE_SIGN: Theta has zeta nonzeros +-1/sqrt(zeta) per row and is
+ *    never stored (Section 5.2 Count sketch for zeta = 1).  Requires zeta | k,
+ *    k/zeta <= 128 and zeta <= 8.  Placement: with B = k/zeta, nonzero t of row i
+ *    sits in slot block [tB, (t+1)B); its byte b is bits [8t, 8t+8) of the 64-bit
+ *    output number i+1 of a SplitMix64 stream started at state `seed` (Steele, Lea,
+ *    Flood 2014); sign = -1 iff (b & 1), slot = tB + ((b >> 1) * B >> 7).
+ */
+typedef struct {
+    int32_t kind;          /* sko_sketch_kind */
+    int32_t k;             /* sketch rows, 1..256 */
+    int32_t zeta;          /* nonzeros per row of Theta (sparse-sign) */
+    int32_t reserved_;
+    uint64_t seed;         /* sparse-sign stream seed */
+    const double* theta;   /* Gaussian: device n x k, column-major */
+    int64_t ld_theta;
+} sko_sketch;
+
+/*
+ * Orthogonalisation options.
+ *  intra            first intra-block step of one-stage BCGS2 (Section 5).
+ *  two_stage        0: one-stage BCGS2 per block; 1: two-stage scheme (Fig. 6), whose
+ *                   pre-processing is RandBCGS2 (Fig. 8) and always uses the sketch.
+ *  panels_per_big   two-stage: blocks per big panel (s_hat / s).
+ *  reorth           two-stage: 1 runs the second BCGS + CholQR over each big panel
+ *                   (Fig. 5 Line 19); 0 skips it (valid when one big panel spans the
+ *                   whole basis, Section 7.3).
+ *  precision        SKO_F64, or SKO_MIXED_F32 (float storage of the tall arrays).
+ */
+typedef struct {
+    int32_t intra;
+    int32_t two_stage;
+    int32_t panels_per_big;
+    int32_t reorth;
+    int32_t precision;
+    int32_t reserved_;
+    sko_sketch sketch;
+} sko_orth_opts;
+
+/* CSR matrix in DEVICE memory: 0-based int32 row pointers (n+1) and column indices
+ * (sorted within each row), double values.  Section 10: A is stored in CSR. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int32_t* rowptr;
+    const int32_t* colind;
+    const double* val;
+} sko_csr;
+
+/*
+ * s-step GMRES options (Fig. 1; two-stage Fig. 5).
+ *  s, m           step size and restart length (s | m).
+ *  shat           two-stage big-panel size (s | shat, shat | m); ignored for one-stage.
+ *  two_stage      0 one-stage BCGS2 per s-step block; 1 two-stage with RandBCGS2.
+ *  precond        0 none, 1 right Jacobi (M = diag(A)).
+ *  intra, sketch  as for sko_orth_opts.
+ *  precision      SKO_F64, or SKO_MIXED_F32 (basis and MPK in float, x and the
+ *                 explicit residual in double).
+ *  tol            stop when ||b - A x||_2 / ||b||_2 <= tol (explicit, double).
+ *  maxiter        cap on generated basis vectors (0: 50000).
+ */
+typedef struct {
+    int32_t s, shat, m, two_stage;
+    int32_t precond;
+    int32_t intra;
+    int32_t precision;
+    int32_t reserved_;
+    sko_sketch sketch;
+    double tol;
+    int64_t maxiter;
+} sko_gmres_opts;
+
+typedef struct {
+    int32_t converged;       /* 1 when the explicit relative residual met tol */
+    int32_t breakdown_col;   /* 1-based basis column of a breakdown, 0 if none */
+    int64_t iters;           /* basis vectors generated (multiple of s, or of shat) */
+    int64_t restarts;        /* completed restart cycles */
+    double relres;           /* last explicit relative residual */
+    double relres_implicit;  /* last implicit (least-squares) relative residual */
+    double t_total;          /* seconds, measured with HIP events on the stream */
+} sko_gmres_info;
+
+/* Create a context on HIP device `device` that orders its work on `hip_stream`
+ * (a hipStream_t; NULL means the device's null stream).  The context owns a device
+ * workspace that grows on demand and is reused. */
+sko_status sko_create(int device, void* hip_stream, sko_ctx* out);
+sko_status sko_destroy(sko_ctx ctx);
+/* Re-target the context to another stream of the same device. */
+sko_status sko_set_stream(sko_ctx ctx, void* hip_stream);
+const char* sko_strerror(sko_status status);
+
+/*
+ * One BCGS2 block step (Fig. 2c): orthogonalise V (n x w) against the orthonormal
+ * columns of Q (n x p), giving Q_out (n x w, may alias V) with
+ *   V = Q * R_proj + Q_out * R_diag,   Q^T Q_out = 0,   Q_out^T Q_out = I.
+ * R_proj (p x w, ld p) and R_diag (w x w, ld w, upper, positive diagonal) are HOST
+ * arrays; either may be NULL.  Q may be NULL when p == 0.  opts->two_stage must be 0.
+ * w <= 16.  On SKO_EBREAKDOWN *breakdown_col (if not NULL) is the 1-based column of V.
+ */
+sko_status sko_orth_block(sko_ctx ctx, int64_t n, int32_t p, int32_t w,
+                          const void* Q, int64_t ldq, const void* V, int64_t ldv,
+                          void* Q_out, int64_t ldqo, double* R_proj, double* R_diag,
+                          const sko_orth_opts* opts, int32_t* breakdown_col);
+
+/*
+ * Orthogonalise all nb blocks of width w of V (n x nb*w) in order: one-stage BCGS2
+ * per block, or two-stage over big panels of panels_per_big blocks.  Result: Q
+ * (n x nb*w, may alias V) and the HOST upper-triangular R (N x N, N = nb*w, leading
+ * dimension ldr >= N; may be NULL) with V = Q R.  w <= 16; two-stage big panels are at
+ * most 64 columns wide.  On SKO_EBREAKDOWN *breakdown_col is the 1-based column.
+ */
+sko_status sko_orth_blocks(sko_ctx ctx, int64_t n, int32_t nb, int32_t w,
+                           const void* V, int64_t ldv, void* Q, int64_t ldq,
+                           double* R, int64_t ldr, const sko_orth_opts* opts,
+                           int32_t* breakdown_col);
+
+/*
+ * Restarted s-step GMRES (Fig. 1): solve A x = b with right preconditioning.
+ * b and x are DEVICE double vectors of length A->n; x holds x0 on entry and the
+ * last iterate on exit (also on SKO_ENOCONV).  info (HOST, may be NULL) is filled
+ * in every case.  The workspace holds the (m+1)-column basis.
+ */
+sko_status sko_gmres(sko_ctx ctx, const sko_csr* A, const double* b, double* x,
+                     const sko_gmres_opts* opts, sko_gmres_info* info);
+
+/*
+ * nsys independent systems solved together (same options; system i uses sketch
+ * seed opts->sketch.seed + i).  A, b, x, infos are HOST arrays of length nsys whose
+ * elements describe DEVICE data as in sko_gmres.  Returns SKO_OK when every system
+ * converged, otherwise the first failing status; infos[i] tells each system's fate.
+ */
+sko_status sko_gmres_batched(sko_ctx ctx, int32_t nsys, const sko_csr* A,
+                             const double* const* b, double* const* x,
+                             const sko_gmres_opts* opts, sko_gmres_info* infos);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKO_H */

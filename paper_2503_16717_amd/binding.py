@@ -1,0 +1,237 @@
+"""ctypes binding of libsko (include/sko.h): argument marshalling only.
+
+Every computation runs in the HIP library.  Device arrays are torch tensors on a
+ROCm device (torch supplies memory and streams, nothing else); tall matrices are
+column-major, i.e. 2-D tensors with stride (1, ld).  Importing this module loads
+libsko.so and raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsko.so")
+
+SKO_OK, SKO_EINVAL, SKO_EDEVICE, SKO_ENOMEM, SKO_EBREAKDOWN, SKO_ENOCONV, SKO_EUNSUPPORTED = range(7)
+SKO_F64, SKO_MIXED_F32 = 0, 1
+SKO_SKETCH_GAUSSIAN, SKO_SKETCH_SPARSE_SIGN = 0, 1
+SKO_INTRA_CHOLQR2, SKO_INTRA_RANDCHOLQR = 0, 1
+
+EXPORTED = ["sko_create", "sko_destroy", "sko_set_stream", "sko_strerror", "sko_orth_block",
+            "sko_orth_blocks", "sko_gmres", "sko_gmres_batched"]
+
+
+class sko_sketch(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("k", C.c_int32), ("zeta", C.c_int32), ("reserved_", C.c_int32),
+                ("seed", C.c_uint64), ("theta", C.c_void_p), ("ld_theta", C.c_int64)]
+
+
+class sko_orth_opts(C.Structure):
+    _fields_ = [("intra", C.c_int32), ("two_stage", C.c_int32), ("panels_per_big", C.c_int32),
+                ("reorth", C.c_int32), ("precision", C.c_int32), ("reserved_", C.c_int32),
+                ("sketch", sko_sketch)]
+
+
+class sko_csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p), ("colind", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class sko_gmres_opts(C.Structure):
+    _fields_ = [("s", C.c_int32), ("shat", C.c_int32), ("m", C.c_int32), ("two_stage", C.c_int32),
+                ("precond", C.c_int32), ("intra", C.c_int32), ("precision", C.c_int32),
+                ("reserved_", C.c_int32), ("sketch", sko_sketch), ("tol", C.c_double),
+                ("maxiter", C.c_int64)]
+
+
+class sko_gmres_info(C.Structure):
+    _fields_ = [("converged", C.c_int32), ("breakdown_col", C.c_int32), ("iters", C.c_int64),
+                ("restarts", C.c_int64), ("relres", C.c_double), ("relres_implicit", C.c_double),
+                ("t_total", C.c_double)]
+
+
+def load_library(path: str = _LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"libsko.so not built (expected at {path}); run paper_2503_16717_amd.build")
+    lib = C.CDLL(path)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    lib.sko_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+    lib.sko_destroy.argtypes = [vp]
+    lib.sko_set_stream.argtypes = [vp, vp]
+    lib.sko_strerror.argtypes = [C.c_int]
+    lib.sko_strerror.restype = C.c_char_p
+    lib.sko_orth_block.argtypes = [vp, i64, i32, i32, vp, i64, vp, i64, vp, i64, dp, dp,
+                                   C.POINTER(sko_orth_opts), C.POINTER(i32)]
+    lib.sko_orth_blocks.argtypes = [vp, i64, i32, i32, vp, i64, vp, i64, dp, i64,
+                                    C.POINTER(sko_orth_opts), C.POINTER(i32)]
+    lib.sko_gmres.argtypes = [vp, C.POINTER(sko_csr), vp, vp, C.POINTER(sko_gmres_opts),
+                              C.POINTER(sko_gmres_info)]
+    lib.sko_gmres_batched.argtypes = [vp, i32, C.POINTER(sko_csr), C.POINTER(vp), C.POINTER(vp),
+                                      C.POINTER(sko_gmres_opts), C.POINTER(sko_gmres_info)]
+    for name in EXPORTED:
+        if name != "sko_strerror":
+            getattr(lib, name).restype = C.c_int
+    return lib
+
+
+_lib = load_library()
+
+
+class SkoError(RuntimeError):
+    def __init__(self, status: int, where: str, col: int = 0):
+        msg = _lib.sko_strerror(status).decode()
+        super().__init__(f"{where}: {msg} (status {status}{', column %d' % col if col else ''})")
+        self.status, self.col = status, col
+
+
+def strerror(status: int) -> str:
+    return _lib.sko_strerror(status).decode()
+
+
+def _colmajor(t, name):
+    if t.dim() != 2 or t.stride(0) != 1:
+        raise ValueError(f"{name} must be a column-major 2-D tensor (stride(0) == 1)")
+    return t.data_ptr(), max(t.stride(1), t.shape[0])
+
+
+def make_sketch(kind: str = "sparse_sign", k: int = 64, zeta: int = 8, seed: int = 0, theta=None) -> sko_sketch:
+    """theta: column-major (n x k) float64 device tensor for the Gaussian sketch."""
+    sk = sko_sketch()
+    if kind == "sparse_sign":
+        sk.kind, sk.k, sk.zeta, sk.seed = SKO_SKETCH_SPARSE_SIGN, k, zeta, seed
+    elif kind == "gaussian":
+        ptr, ld = _colmajor(theta, "theta")
+        sk.kind, sk.k, sk.zeta, sk.seed, sk.theta, sk.ld_theta = SKO_SKETCH_GAUSSIAN, theta.shape[1], 0, 0, ptr, ld
+    else:
+        raise ValueError(kind)
+    return sk
+
+
+def orth_opts(intra="randcholqr", two_stage=False, panels_per_big=1, reorth=True, precision="f64",
+              sketch: sko_sketch | None = None) -> sko_orth_opts:
+    o = sko_orth_opts()
+    o.intra = SKO_INTRA_RANDCHOLQR if intra == "randcholqr" else SKO_INTRA_CHOLQR2
+    o.two_stage = int(bool(two_stage))
+    o.panels_per_big = int(panels_per_big)
+    o.reorth = int(bool(reorth))
+    o.precision = SKO_MIXED_F32 if precision == "mixed" else SKO_F64
+    o.sketch = sketch if sketch is not None else make_sketch()
+    return o
+
+
+class Context:
+    """Owns an sko_ctx bound to a device and a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = _lib.sko_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != SKO_OK:
+            raise SkoError(st, "sko_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.sko_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- raw entry points with the C names --------------------------------------------------
+    def sko_orth_blocks(self, n, nb, w, V_ptr, ldv, Q_ptr, ldq, R: np.ndarray | None, ldr, opts):
+        col = C.c_int32(0)
+        rp = R.ctypes.data_as(C.POINTER(C.c_double)) if R is not None else None
+        st = _lib.sko_orth_blocks(self.h, n, nb, w, V_ptr, ldv, Q_ptr, ldq, rp, ldr, C.byref(opts), C.byref(col))
+        return st, col.value
+
+    def sko_orth_block(self, n, p, w, Q_ptr, ldq, V_ptr, ldv, Qo_ptr, ldqo, Rp, Rd, opts):
+        col = C.c_int32(0)
+        rpp = Rp.ctypes.data_as(C.POINTER(C.c_double)) if Rp is not None else None
+        rdp = Rd.ctypes.data_as(C.POINTER(C.c_double)) if Rd is not None else None
+        st = _lib.sko_orth_block(self.h, n, p, w, Q_ptr, ldq, V_ptr, ldv, Qo_ptr, ldqo, rpp, rdp,
+                                 C.byref(opts), C.byref(col))
+        return st, col.value
+
+    def sko_gmres(self, A: sko_csr, b_ptr, x_ptr, opts: sko_gmres_opts):
+        info = sko_gmres_info()
+        st = _lib.sko_gmres(self.h, C.byref(A), b_ptr, x_ptr, C.byref(opts), C.byref(info))
+        return st, info
+
+    def sko_gmres_batched(self, As, b_ptrs, x_ptrs, opts: sko_gmres_opts):
+        ns = len(As)
+        Aarr = (sko_csr * ns)(*As)
+        barr = (C.c_void_p * ns)(*b_ptrs)
+        xarr = (C.c_void_p * ns)(*x_ptrs)
+        infos = (sko_gmres_info * ns)()
+        st = _lib.sko_gmres_batched(self.h, ns, Aarr, barr, xarr, C.byref(opts), infos)
+        return st, list(infos)
+
+    # -- tensor conveniences --------------------------------------------------------------
+    def orth_blocks(self, V, w: int, Q=None, R: bool = True, raise_on_error: bool = True, **opt_kw):
+        """Orthogonalise the column-major tensor V (n x nb*w).  Returns (Q, R, status, col)."""
+        import torch
+        n, N = V.shape
+        if N % w:
+            raise ValueError("columns must be a multiple of w")
+        if Q is None:
+            Q = torch.empty((N, n), dtype=V.dtype, device=V.device).t()
+        vp, ldv = _colmajor(V, "V")
+        qp, ldq = _colmajor(Q, "Q")
+        Rh = np.zeros((N, N), order="F") if R else None
+        opts = orth_opts(**opt_kw)
+        st, col = self.sko_orth_blocks(n, N // w, w, vp, ldv, qp, ldq, Rh, N, opts)
+        if raise_on_error and st not in (SKO_OK, SKO_EBREAKDOWN):
+            raise SkoError(st, "sko_orth_blocks", col)
+        return Q, Rh, st, col
+
+    def orth_block(self, Qprev, V, Qout=None, raise_on_error: bool = True, **opt_kw):
+        """One BCGS2 block step.  Returns (Qout, R_proj, R_diag, status, col)."""
+        import torch
+        n, w = V.shape
+        p = 0 if Qprev is None else Qprev.shape[1]
+        if Qout is None:
+            Qout = torch.empty((w, n), dtype=V.dtype, device=V.device).t()
+        vp, ldv = _colmajor(V, "V")
+        op, ldo = _colmajor(Qout, "Qout")
+        if p > 0:
+            qp, ldq = _colmajor(Qprev, "Q")
+        else:
+            qp, ldq = None, n
+        Rp = np.zeros((p, w), order="F") if p > 0 else None
+        Rd = np.zeros((w, w), order="F")
+        opts = orth_opts(**opt_kw)
+        st, col = self.sko_orth_block(n, p, w, qp, ldq, vp, ldv, op, ldo, Rp, Rd, opts)
+        if raise_on_error and st not in (SKO_OK, SKO_EBREAKDOWN):
+            raise SkoError(st, "sko_orth_block", col)
+        return Qout, Rp, Rd, st, col
+
+
+def colmajor_from_numpy(a: np.ndarray, device="cuda", dtype=None):
+    """Upload a host (n x m) array as a column-major device tensor."""
+    import torch
+    a = np.asarray(a)
+    t = torch.from_numpy(np.ascontiguousarray(a.T)).to(device)
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.t()
+
+
+def csr_to_device(A, device="cuda"):
+    """Upload a workloads.CSR; returns (sko_csr struct, tensors kept alive)."""
+    import torch
+    rp = torch.from_numpy(A.rowptr).to(device)
+    ci = torch.from_numpy(A.colind).to(device)
+    va = torch.from_numpy(A.val).to(device)
+    s = sko_csr()
+    s.n, s.nnz, s.rowptr, s.colind, s.val = A.n, A.nnz, rp.data_ptr(), ci.data_ptr(), va.data_ptr()
+    return s, (rp, ci, va)

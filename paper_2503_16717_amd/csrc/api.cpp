@@ -1,0 +1,90 @@
+// C ABI entry points of libsko (declared in include/sko.h).
+#include <hip/hip_runtime.h>
+
+#include "context.h"
+
+extern "C" {
+
+sko_status sko_create(int device, void* hip_stream, sko_ctx* out) {
+    if (!out) return SKO_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return SKO_EDEVICE;
+    if (device < 0 || device >= count) return SKO_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return SKO_EDEVICE;
+    sko_ctx c = new (std::nothrow) sko_ctx_s();
+    if (!c) return SKO_ENOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        delete c;
+        return SKO_EDEVICE;
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->status_host), 64, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return SKO_ENOMEM;
+    }
+    *out = c;
+    return SKO_OK;
+}
+
+sko_status sko_destroy(sko_ctx c) {
+    if (!c) return SKO_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->status_host) (void)hipHostFree(c->status_host);
+    delete c;
+    return SKO_OK;
+}
+
+sko_status sko_set_stream(sko_ctx c, void* hip_stream) {
+    if (!c) return SKO_EINVAL;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return SKO_OK;
+}
+
+const char* sko_strerror(sko_status s) {
+    switch (s) {
+        case SKO_OK: return "success";
+        case SKO_EINVAL: return "invalid argument";
+        case SKO_EDEVICE: return "HIP runtime error";
+        case SKO_ENOMEM: return "out of device memory";
+        case SKO_EBREAKDOWN: return "breakdown: non-positive Cholesky pivot or zero Householder diagonal";
+        case SKO_ENOCONV: return "GMRES did not converge within maxiter";
+        case SKO_EUNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+sko_status sko_orth_block(sko_ctx c, int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq, const void* V,
+                          int64_t ldv, void* Q_out, int64_t ldqo, double* R_proj, double* R_diag,
+                          const sko_orth_opts* opts, int32_t* breakdown_col) {
+    if (!c) return SKO_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;
+    return sko::orth_block_impl(c, n, p, w, Q, ldq, V, ldv, Q_out, ldqo, R_proj, R_diag, opts, breakdown_col);
+}
+
+sko_status sko_orth_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const void* V, int64_t ldv, void* Q,
+                           int64_t ldq, double* R, int64_t ldr, const sko_orth_opts* opts,
+                           int32_t* breakdown_col) {
+    if (!c) return SKO_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;
+    return sko::orth_blocks_impl(c, n, nb, w, V, ldv, Q, ldq, R, ldr, opts, breakdown_col);
+}
+
+sko_status sko_gmres(sko_ctx c, const sko_csr* A, const double* b, double* x, const sko_gmres_opts* opts,
+                     sko_gmres_info* info) {
+    if (!c) return SKO_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;
+    return sko::gmres_impl(c, A, b, x, opts, info);
+}
+
+sko_status sko_gmres_batched(sko_ctx c, int32_t nsys, const sko_csr* A, const double* const* b, double* const* x,
+                             const sko_gmres_opts* opts, sko_gmres_info* infos) {
+    if (!c) return SKO_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;
+    return sko::gmres_batched_impl(c, nsys, A, b, x, opts, infos);
+}
+
+}  // extern "C"

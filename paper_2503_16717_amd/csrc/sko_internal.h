@@ -1,0 +1,145 @@
+// Internal declarations shared by the HIP translation units of libsko.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstddef>
+
+#include "sko.h"
+
+namespace sko {
+
+// ---------------------------------------------------------------------------
+// Row-strip pass: one streaming sweep over n rows of a tall-skinny block.
+//
+// Per row (phase A, one thread per row):
+//   x = Y[row, 0:W]
+//   x -= Qu[row, 0:pu] * Cu                  (UPD: BCGS update V - Q C, Fig. 2a)
+//   x  = x * R1^{-1} [* R2^{-1}]             (NTRSM: row forward substitution, Fig. 4a)
+//   X[row, 0:W] = x                          (WRITE)
+// Per strip (phase B, lanes over rows, waves over reduction rows): one reduction
+//   RED_PROJ          Qp^T x       (Q^T V of BCGS, Fig. 2a)
+//   RED_GRAM          x^T x        (Gram of CholQR, Fig. 2b)
+//   RED_SKETCH_SPARSE Theta^T x    (sparse-sign sketch, hashed, Section 5.2)
+//   RED_SKETCH_DENSE  Theta^T x    (Gaussian sketch, stored Theta, Section 5.2)
+// Each workgroup writes its partial reduction to partials[blockIdx.x * part_stride + e],
+// e = row + col * part_rows_total; a reduce kernel sums the partials in a fixed order.
+// ---------------------------------------------------------------------------
+enum RedKind : int {
+    RED_NONE = 0,
+    RED_PROJ = 1,
+    RED_GRAM = 2,
+    RED_SKETCH_SPARSE = 3,
+    RED_SKETCH_DENSE = 4,
+};
+
+struct PassArgs {
+    int64_t n;
+    const void* Y;            // input block, W columns
+    int64_t ldy;
+    const void* Qu;           // UPD operand (pu columns)
+    int64_t ldqu;
+    const double* Cu;         // UPD coefficients, pu x W column-major (ld pu)
+    const double* R1;         // TRSM factors, W x W column-major, upper
+    const double* R2;
+    void* X;                  // WRITE target
+    int64_t ldx;
+    const void* Qp;           // PROJ operand, already offset to reduction row red_row0
+    int64_t ldqp;
+    const double* theta;      // dense sketch, n x k column-major, offset to red_row0
+    int64_t ldtheta;
+    double* partials;
+    int64_t part_stride;      // doubles between consecutive workgroups' partials
+    uint64_t sk_seed;
+    int32_t pu;
+    int32_t red_rows;         // reduction rows handled by this launch
+    int32_t red_row0;         // global index of the first of them
+    int32_t part_rows_total;  // rows of the whole reduction output
+    int32_t sk_k;
+    int32_t sk_zeta;
+};
+
+struct PassKey {
+    int W;
+    bool f32;          // storage type float (else double)
+    int red;
+    bool upd;
+    int ntrsm;
+    bool write;
+};
+
+// Launch one pass over all n rows with `grid` workgroups (grid <= pass_grid_cap()).
+hipError_t launch_pass(const PassKey& key, const PassArgs& args, int grid, hipStream_t stream);
+// Reduction rows one launch can produce for panel width W (rows per wave * waves).
+int pass_rows_per_launch(int W);
+// Largest useful grid for a pass variant on the current device (resident workgroups).
+int pass_grid_cap(const PassKey& key);
+constexpr int kPassThreads = 256;
+constexpr int kMaxPassW = 16;
+constexpr int kMaxUpdCoef = 4096;   // pu * W doubles staged in LDS by an update pass
+
+// ---------------------------------------------------------------------------
+// Reduction of pass partials + the small dense step that consumes it.
+// ---------------------------------------------------------------------------
+enum SmallOp : int {
+    OP_STORE = 0,        // reduced values are the result (e.g. C = Q^T V)
+    OP_HH = 1,           // Householder R of the k x w sketch (Fig. 4a Line 4), diag >= 0
+    OP_CHOL = 2,         // upper Cholesky factor of the w x w Gram matrix (Fig. 2b)
+    OP_SKETCH_BCGS2 = 3, // sketch-space BCGS2 with Householder (Fig. 8a)
+};
+
+struct SmallArgs {
+    int op;
+    int w;               // block width
+    int k;               // sketch rows (OP_HH / OP_SKETCH_BCGS2)
+    int col0;            // global 1-based column offset for breakdown reports
+    double* out;         // reduced values (count doubles); OP_HH/OP_SKETCH_BCGS2: k x w sketch
+    double* R;           // OP_HH / OP_CHOL / OP_SKETCH_BCGS2: w x w result (ld w)
+    int* status;         // first breakdown column (0 = none)
+    // OP_SKETCH_BCGS2
+    double* Yacc;        // k x cap, column-major (ld k): accumulated orthonormal sketches
+    int nacc;            // columns of Yacc orthogonalised against (the first nacc)
+    double* r;           // nacc x w coefficients (ld nacc), r1 + r2
+    // assembly after OP_CHOL (assemble != 0):
+    //   Rhat = Ra * Rb (w x w), Rdiag = R * Rhat, Rproj = C1 + C2 * Rhat (p x w)
+    int assemble;
+    const double* Ra;
+    const double* Rb;
+    const double* C1;
+    const double* C2;
+    int p;
+    double* Rout;        // destination of [Rproj; Rdiag] columns in a big R (ld ldr)
+    int64_t ldr;
+};
+
+struct ReduceArgs {
+    const double* partials;
+    int64_t stride;
+    int G;
+    int count;
+    double scale;
+    unsigned int* counter;
+    SmallArgs small;
+};
+
+hipError_t launch_reduce(const ReduceArgs& args, hipStream_t stream);
+
+// Small dense kernels used outside a reduction.
+// Big-panel helpers (two-stage): C = A^T B for tall A (n x ma), B (n x nb), ma, nb <= 64.
+hipError_t launch_skinny_gemm_tn(int64_t n, const void* A, int64_t lda, int ma,
+                                 const void* B, int64_t ldb, int nb, bool f32,
+                                 double* partials, int grid, hipStream_t stream);
+int skinny_gemm_grid_cap();
+
+// Row-wise X = (Y - Qu Cu) * R^{-1} for wide blocks (w <= 64); used by the big-panel
+// close of the two-stage scheme.
+hipError_t launch_wide_rowop(int64_t n, int W, bool f32, const void* Y, int64_t ldy,
+                             const void* Qu, int64_t ldqu, int pu, const double* Cu,
+                             const double* R, void* X, int64_t ldx, hipStream_t stream);
+
+// Small matrix helpers on the device (single workgroup).
+hipError_t launch_small_matmul_upper(int w, const double* A, const double* B, double* C,
+                                     hipStream_t stream);
+
+}  // namespace sko

@@ -1,0 +1,333 @@
+// Deterministic reduction of per-workgroup partials, followed by the small dense step
+// that consumes the reduced matrix (Householder QR of a sketch, Cholesky of a Gram
+// matrix, or the sketch-space BCGS2-HH step), run by the last workgroup to finish.
+//
+// Partials are summed in a fixed order (workgroup g in strides of 32, then the 32
+// part sums in order), so results are bitwise reproducible for a given grid.  All
+// small factorisations are in double precision regardless of the storage type.
+#include "sko_internal.h"
+
+#include <cmath>
+
+namespace sko {
+namespace {
+
+constexpr int RT = 256;          // threads of the reduce kernel
+constexpr int EPW = 8;           // reduced elements per workgroup
+constexpr int PARTS = RT / EPW;  // partial sums per element
+
+__device__ __forceinline__ double load_coherent(const double* p) {
+    unsigned long long bits =
+        __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double(static_cast<long long>(bits));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum NV per-thread values over the workgroup; results land in out[0..NV) (LDS),
+// visible to every thread on return.  Order: lanes by xor-butterfly, waves 0..3.
+template <int NVMAX>
+__device__ void block_sum(const double* vals, int nv, double* red /* LDS 4*NVMAX */, double* out) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int v = 0; v < nv; ++v) {
+        const double s = wave_sum(vals[v]);
+        if (lane == 0) red[wave * NVMAX + v] = s;
+    }
+    __syncthreads();
+    if (tid < nv) {
+        double s = 0.0;
+        for (int w = 0; w < RT / 64; ++w) s += red[w * NVMAX + tid];
+        out[tid] = s;
+    }
+    __syncthreads();
+}
+
+// Householder QR of the k x w matrix A (LDS, column-major, ld k), k <= 256 (one row per
+// thread), w <= 16.  On return A's upper triangle holds R (diag >= 0 after the sign
+// fix applied to R and, if E != nullptr, to the explicit thin Q formed in E (k x w)).
+// Reflector j is v = A[j:, j] (below-diagonal part kept in A) with v_0 in vhead[j].
+__device__ void householder_lds(double* A, int k, int w, double* E, double* R, int ldr,
+                                int* status, int col0, double* red, double* scal) {
+    const int tid = threadIdx.x;
+    double* vhead = scal;        // w
+    double* beta = scal + 16;    // w
+    double* dots = scal + 32;    // w (block_sum results)
+    double* sgn = scal + 48;     // w
+    double vals[16];
+    for (int j = 0; j < w; ++j) {
+        // ||A[j+1:k, j]||^2
+        vals[0] = (tid > j && tid < k) ? A[tid + j * k] * A[tid + j * k] : 0.0;
+        block_sum<16>(vals, 1, red, dots);
+        const double ss = dots[0];
+        const double x0 = A[j + j * k];
+        const double normx = sqrt(x0 * x0 + ss);
+        double alpha = 0.0, b = 0.0, v0 = 0.0;
+        if (normx != 0.0) {
+            alpha = -copysign(normx, x0);
+            v0 = x0 - alpha;
+            b = 2.0 / (v0 * v0 + ss);
+        }
+        // d_c = v^T A[j:, c] for the trailing columns
+        const int nt = w - j - 1;
+        for (int c = 0; c < nt; ++c) {
+            const int cc = j + 1 + c;
+            double vi = 0.0;
+            if (tid == j) vi = v0;
+            else if (tid > j && tid < k) vi = A[tid + j * k];
+            vals[c] = (tid >= j && tid < k) ? vi * A[tid + cc * k] : 0.0;
+        }
+        block_sum<16>(vals, nt, red, dots);
+        if (tid >= j && tid < k) {
+            const double vi = (tid == j) ? v0 : A[tid + j * k];
+            for (int c = 0; c < nt; ++c) {
+                const int cc = j + 1 + c;
+                A[tid + cc * k] -= b * dots[c] * vi;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            A[j + j * k] = alpha;
+            vhead[j] = v0;
+            beta[j] = b;
+        }
+        __syncthreads();
+    }
+    // R with non-negative diagonal; breakdown on an exactly zero diagonal.
+    if (tid < w) {
+        const double d = A[tid + tid * k];
+        sgn[tid] = d < 0.0 ? -1.0 : 1.0;
+        if (d == 0.0 && status) atomicCAS(status, 0, col0 + tid + 1);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < w * w; idx += RT) {
+        const int r = idx % w, c = idx / w;
+        R[r + c * ldr] = (r <= c) ? sgn[r] * A[r + c * k] : 0.0;
+    }
+    if (!E) {
+        __syncthreads();
+        return;
+    }
+    // Explicit thin Q: apply H_{w-1} ... H_0 in reverse to [I; 0].
+    for (int idx = tid; idx < k * w; idx += RT) {
+        const int r = idx % k, c = idx / k;
+        E[idx] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = w - 1; j >= 0; --j) {
+        const double v0 = vhead[j], b = beta[j];
+        for (int c = 0; c < w; ++c) {
+            double vi = 0.0;
+            if (tid == j) vi = v0;
+            else if (tid > j && tid < k) vi = A[tid + j * k];
+            vals[c] = (tid >= j && tid < k) ? vi * E[tid + c * k] : 0.0;
+        }
+        block_sum<16>(vals, w, red, dots);
+        if (tid >= j && tid < k) {
+            const double vi = (tid == j) ? v0 : A[tid + j * k];
+            for (int c = 0; c < w; ++c) E[tid + c * k] -= b * dots[c] * vi;
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < k * w; idx += RT) {
+        const int c = idx / k;
+        E[idx] *= sgn[c];
+    }
+    __syncthreads();
+}
+
+// Right-looking upper Cholesky of the w x w matrix G (LDS, column-major), w <= 64.
+__device__ void cholesky_lds(double* G, int w, double* R, int* status, int col0, double* scal) {
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < w * w; idx += RT) R[idx] = 0.0;
+    for (int j = 0; j < w; ++j) {
+        if (tid == 0) {
+            const double d = G[j + j * w];
+            if (!(d > 0.0) || !isfinite(d)) {
+                if (status) atomicCAS(status, 0, col0 + j + 1);
+            }
+            scal[0] = sqrt(d);
+        }
+        __syncthreads();
+        const double r = scal[0];
+        for (int c = j + tid; c < w; c += RT) {
+            const double v = (c == j) ? r : G[j + c * w] / r;
+            R[j + c * w] = v;
+            scal[8 + c] = v;  // row j of R for the trailing update
+        }
+        __syncthreads();
+        const int m = w - j - 1;
+        for (int idx = tid; idx < m * m; idx += RT) {
+            const int a = j + 1 + idx % m, c = j + 1 + idx / m;
+            if (a <= c) G[a + c * w] -= scal[8 + a] * scal[8 + c];
+        }
+        __syncthreads();
+    }
+}
+
+// Rhat = Ra * Rb (upper, w x w) -> rh (global); Rdiag = R * Rhat; Rproj = C1 + C2 * Rhat.
+// R and rh were written by this workgroup just before, so they are read coherently.
+__device__ void assemble(const SmallArgs& s, double* rh) {
+    const int tid = threadIdx.x;
+    const int w = s.w;
+    for (int idx = tid; idx < w * w; idx += RT) {
+        const int a = idx % w, c = idx / w;
+        double v = 0.0;
+        for (int t = a; t <= c; ++t) v += s.Ra[a + t * w] * s.Rb[t + c * w];
+        rh[idx] = (a <= c) ? v : 0.0;
+    }
+    __syncthreads();
+    if (s.Rout) {
+        for (int idx = tid; idx < w * w; idx += RT) {
+            const int a = idx % w, c = idx / w;
+            double v = 0.0;
+            for (int t = a; t <= c; ++t) v += load_coherent(s.R + a + t * w) * load_coherent(rh + t + c * w);
+            s.Rout[(s.p + a) + c * s.ldr] = (a <= c) ? v : 0.0;
+        }
+        for (int idx = tid; idx < s.p * w; idx += RT) {
+            const int a = idx % s.p, c = idx / s.p;
+            double v = s.C1 ? s.C1[a + c * s.p] : 0.0;
+            if (s.C2) {
+                double t2 = 0.0;
+                for (int t = 0; t <= c; ++t) t2 += s.C2[a + t * s.p] * load_coherent(rh + t + c * w);
+                v += t2;
+            }
+            s.Rout[a + c * s.ldr] = v;
+        }
+    }
+    __syncthreads();
+}
+
+// Sketch-space BCGS2 with Householder (Fig. 8a): y (k x w) against Yacc[:, 0:nacc].
+__device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* red, double* scal) {
+    const int tid = threadIdx.x;
+    const int k = s.k, w = s.w, na = s.nacc;
+    const double* Y = s.Yacc;
+    for (int idx = tid; idx < k * w; idx += RT) Z[idx] = load_coherent(s.out + idx);
+    __syncthreads();
+    if (na > 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+            // r_pass = Yacc^T z ; accumulate into s.r (pass 0 stores, pass 1 adds)
+            for (int idx = tid; idx < na * w; idx += RT) {
+                const int a = idx % na, c = idx / na;
+                double d = 0.0;
+                for (int i = 0; i < k; ++i) d += Y[i + (int64_t)a * k] * Z[i + c * k];
+                E[idx] = d;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < k * w; idx += RT) {
+                const int i = idx % k, c = idx / k;
+                double v = Z[idx];
+                for (int a = 0; a < na; ++a) v -= Y[i + (int64_t)a * k] * E[a + c * na];
+                Z[idx] = v;
+            }
+            for (int idx = tid; idx < na * w; idx += RT) s.r[idx] = (pass == 0) ? E[idx] : s.r[idx] + E[idx];
+            __syncthreads();
+        }
+    }
+    householder_lds(Z, k, w, E, s.R, w, s.status, s.col0, red, scal);
+    // append q to the accumulated sketches (replacing the boundary column at nacc)
+    for (int idx = tid; idx < k * w; idx += RT) s.Yacc[(int64_t)na * k + idx] = E[idx];
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(RT) reduce_kernel(const ReduceArgs a) {
+    extern __shared__ double lds[];
+    __shared__ double part[RT];
+    __shared__ double red[4 * 16];
+    __shared__ double scal[128];
+    __shared__ int s_last;
+    const int tid = threadIdx.x;
+    const int el = tid % EPW, pt = tid / EPW;
+    const int e = blockIdx.x * EPW + el;
+    double v = 0.0;
+    if (e < a.count) {
+        for (int g = pt; g < a.G; g += PARTS) v += a.partials[(int64_t)g * a.stride + e];
+    }
+    part[tid] = v;
+    __syncthreads();
+    if (tid < EPW) {
+        const int ee = blockIdx.x * EPW + tid;
+        if (ee < a.count) {
+            double s = 0.0;
+            for (int p = 0; p < PARTS; ++p) s += part[p * EPW + tid];
+            a.small.out[ee] = s * a.scale;
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned prev = atomicAdd(a.counter, 1u);
+        s_last = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+
+    const SmallArgs& s = a.small;
+    if (s.op == OP_HH) {
+        double* A = lds;
+        for (int idx = tid; idx < s.k * s.w; idx += RT) A[idx] = load_coherent(s.out + idx);
+        __syncthreads();
+        householder_lds(A, s.k, s.w, nullptr, s.R, s.w, s.status, s.col0, red, scal);
+    } else if (s.op == OP_CHOL) {
+        double* G = lds;
+        for (int idx = tid; idx < s.w * s.w; idx += RT) G[idx] = load_coherent(s.out + idx);
+        __syncthreads();
+        cholesky_lds(G, s.w, s.R, s.status, s.col0, scal);
+        __syncthreads();
+        if (s.assemble) {
+            __threadfence();
+            assemble(s, s.out);  // Rhat overwrites the consumed Gram matrix
+        }
+    } else if (s.op == OP_SKETCH_BCGS2) {
+        double* Z = lds;
+        double* E = lds + s.k * s.w;
+        sketch_bcgs2(s, Z, E, red, scal);
+    }
+    __threadfence();
+    if (tid == 0) *a.counter = 0u;
+}
+
+__global__ void matmul_upper_kernel(int w, const double* A, const double* B, double* C) {
+    for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
+        const int a = idx % w, c = idx / w;
+        double v = 0.0;
+        for (int t = a; t <= c; ++t) v += A[a + t * w] * B[t + c * w];
+        C[idx] = (a <= c) ? v : 0.0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream) {
+    if (a.count <= 0 || a.G <= 0) return hipErrorInvalidValue;
+    const SmallArgs& s = a.small;
+    size_t lds = 0;
+    if (s.op == OP_HH) {
+        if (s.k > RT || s.w > 16 || s.k < s.w) return hipErrorInvalidValue;
+        lds = sizeof(double) * (size_t)s.k * s.w;
+    } else if (s.op == OP_CHOL) {
+        if (s.w > 64) return hipErrorInvalidValue;
+        lds = sizeof(double) * (size_t)s.w * s.w;
+    } else if (s.op == OP_SKETCH_BCGS2) {
+        if (s.k > RT || s.w > 16 || s.k < s.w) return hipErrorInvalidValue;
+        const size_t e = (size_t)s.k * s.w > (size_t)s.nacc * s.w ? (size_t)s.k * s.w : (size_t)s.nacc * s.w;
+        lds = sizeof(double) * ((size_t)s.k * s.w + e);
+    }
+    if (lds > 60 * 1024) return hipErrorInvalidValue;
+    const int grid = (a.count + EPW - 1) / EPW;
+    hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(RT), lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_matmul_upper(int w, const double* A, const double* B, double* C, hipStream_t stream) {
+    hipLaunchKernelGGL(matmul_upper_kernel, dim3(1), dim3(256), 0, stream, w, A, B, C);
+    return hipGetLastError();
+}
+
+}  // namespace sko
