@@ -187,6 +187,26 @@ sko_status sko_gmres_batched(sko_ctx ctx, int32_t nsys, const sko_csr* A,
                              const double* const* b, double* const* x,
                              const sko_gmres_opts* opts, sko_gmres_info* infos);
 
+/*
+ * Kernel profiling (tracing subsystem).  When enabled, every tall-pass and reduction
+ * launch issued by the context is bracketed by HIP events on the context's stream,
+ * and per kernel kind the library accumulates the launch count, the summed event time
+ * and the algorithmic HBM bytes of those launches (each tall operand counted once per
+ * pass: columns read plus columns written, times n, times the element size).
+ * sko_profile_enable(ctx, 1) clears the counters and starts recording; 0 stops it.
+ * sko_profile_read copies up to max entries (sorted by total time, largest first) and
+ * returns the number of kinds recorded, or a negative sko_status on error.
+ */
+typedef struct {
+    char name[96];         /* kernel kind, e.g. "pass W=6 f64 red=proj upd=0 trsm=2 write=1" */
+    int64_t launches;
+    double total_ms;       /* summed event time of all launches */
+    double bytes;          /* summed algorithmic bytes of all launches */
+} sko_kernel_stat;
+
+sko_status sko_profile_enable(sko_ctx ctx, int enable);
+int32_t sko_profile_read(sko_ctx ctx, sko_kernel_stat* out, int32_t max);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ SKO_SKETCH_GAUSSIAN, SKO_SKETCH_SPARSE_SIGN = 0, 1
 SKO_INTRA_CHOLQR2, SKO_INTRA_RANDCHOLQR = 0, 1
 
 EXPORTED = ["sko_create", "sko_destroy", "sko_set_stream", "sko_strerror", "sko_orth_block",
-            "sko_orth_blocks", "sko_gmres", "sko_gmres_batched"]
+            "sko_orth_blocks", "sko_gmres", "sko_gmres_batched", "sko_profile_enable", "sko_profile_read"]
 
 
 class sko_sketch(C.Structure):
@@ -52,6 +52,11 @@ class sko_gmres_info(C.Structure):
                 ("t_total", C.c_double)]
 
 
+class sko_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 96), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("bytes", C.c_double)]
+
+
 def load_library(path: str = _LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"libsko.so not built (expected at {path}); run paper_2503_16717_amd.build")
@@ -70,6 +75,8 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
                               C.POINTER(sko_gmres_info)]
     lib.sko_gmres_batched.argtypes = [vp, i32, C.POINTER(sko_csr), C.POINTER(vp), C.POINTER(vp),
                                       C.POINTER(sko_gmres_opts), C.POINTER(sko_gmres_info)]
+    lib.sko_profile_enable.argtypes = [vp, C.c_int]
+    lib.sko_profile_read.argtypes = [vp, C.POINTER(sko_kernel_stat), i32]
     for name in EXPORTED:
         if name != "sko_strerror":
             getattr(lib, name).restype = C.c_int
@@ -119,6 +126,23 @@ def orth_opts(intra="randcholqr", two_stage=False, panels_per_big=1, reorth=True
     o.precision = SKO_MIXED_F32 if precision == "mixed" else SKO_F64
     o.sketch = sketch if sketch is not None else make_sketch()
     return o
+
+
+def gmres_opts(s=5, m=30, shat=0, two_stage=False, precond=0, intra="randcholqr", precision="f64",
+               sketch: sko_sketch | None = None, tol=1e-10, maxiter=0) -> sko_gmres_opts:
+    o = sko_gmres_opts()
+    o.s, o.m, o.shat, o.two_stage = int(s), int(m), int(shat), int(bool(two_stage))
+    o.precond = int(precond)
+    o.intra = SKO_INTRA_RANDCHOLQR if intra == "randcholqr" else SKO_INTRA_CHOLQR2
+    o.precision = SKO_MIXED_F32 if precision == "mixed" else SKO_F64
+    o.sketch = sketch if sketch is not None else make_sketch()
+    o.tol = float(tol)
+    o.maxiter = int(maxiter)
+    return o
+
+
+def info_dict(inf: sko_gmres_info) -> dict:
+    return {f: getattr(inf, f) for f, _ in sko_gmres_info._fields_}
 
 
 class Context:
@@ -176,6 +200,21 @@ class Context:
         st = _lib.sko_gmres_batched(self.h, ns, Aarr, barr, xarr, C.byref(opts), infos)
         return st, list(infos)
 
+    def sko_profile_enable(self, enable: bool):
+        st = _lib.sko_profile_enable(self.h, int(bool(enable)))
+        if st != SKO_OK:
+            raise SkoError(st, "sko_profile_enable")
+
+    def sko_profile_read(self):
+        """List of dicts (name, launches, total_ms, bytes), largest total time first."""
+        cnt = _lib.sko_profile_read(self.h, None, 0)
+        if cnt < 0:
+            raise SkoError(-cnt, "sko_profile_read")
+        arr = (sko_kernel_stat * max(cnt, 1))()
+        _lib.sko_profile_read(self.h, arr, cnt)
+        return [dict(name=a.name.decode(), launches=a.launches, total_ms=a.total_ms, bytes=a.bytes)
+                for a in arr[:cnt]]
+
     # -- tensor conveniences --------------------------------------------------------------
     def orth_blocks(self, V, w: int, Q=None, R: bool = True, raise_on_error: bool = True, **opt_kw):
         """Orthogonalise the column-major tensor V (n x nb*w).  Returns (Q, R, status, col)."""
@@ -214,6 +253,32 @@ class Context:
         if raise_on_error and st not in (SKO_OK, SKO_EBREAKDOWN):
             raise SkoError(st, "sko_orth_block", col)
         return Qout, Rp, Rd, st, col
+
+
+def _gmres_method(self, A, b, x0=None, raise_on_error=False, **opt_kw):
+    """Solve A x = b (A: workloads.CSR or (sko_csr, keep-alive) from csr_to_device; b: host
+    array or device float64 tensor).  Returns (x device tensor, info dict, status)."""
+    import torch
+    if isinstance(A, tuple):
+        Ad, keep = A
+    else:
+        Ad, keep = csr_to_device(A, "cuda:%d" % self.device)
+    bt = b if isinstance(b, torch.Tensor) else torch.from_numpy(np.asarray(b, dtype=np.float64)).to(
+        "cuda:%d" % self.device)
+    if x0 is None:
+        x = torch.zeros_like(bt)
+    else:
+        x = (x0 if isinstance(x0, torch.Tensor) else torch.from_numpy(np.asarray(x0, dtype=np.float64)).to(
+            bt.device)).clone()
+    opts = gmres_opts(**opt_kw)
+    st, inf = self.sko_gmres(Ad, bt.data_ptr(), x.data_ptr(), opts)
+    if raise_on_error and st not in (SKO_OK, SKO_ENOCONV):
+        raise SkoError(st, "sko_gmres", inf.breakdown_col)
+    del keep
+    return x, info_dict(inf), st
+
+
+Context.gmres = _gmres_method
 
 
 def colmajor_from_numpy(a: np.ndarray, device="cuda", dtype=None):

@@ -1,6 +1,12 @@
 // C ABI entry points of libsko (declared in include/sko.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
 #include "context.h"
 
 extern "C" {
@@ -34,6 +40,8 @@ sko_status sko_destroy(sko_ctx c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->ws) (void)hipFree(c->ws);
     if (c->status_host) (void)hipHostFree(c->status_host);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->prof.release();
     delete c;
     return SKO_OK;
 }
@@ -85,6 +93,31 @@ sko_status sko_gmres_batched(sko_ctx c, int32_t nsys, const sko_csr* A, const do
     if (!c) return SKO_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;
     return sko::gmres_batched_impl(c, nsys, A, b, x, opts, infos);
+}
+
+sko_status sko_profile_enable(sko_ctx c, int enable) {
+    if (!c) return SKO_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return SKO_EDEVICE;
+    c->prof.flush();
+    if (enable) c->prof.stats.clear();
+    c->prof.on = enable != 0;
+    return SKO_OK;
+}
+
+int32_t sko_profile_read(sko_ctx c, sko_kernel_stat* out, int32_t max) {
+    if (!c || max < 0 || (max > 0 && !out)) return -SKO_EINVAL;
+    std::vector<std::pair<std::string, sko::Profiler::Stat>> v(c->prof.stats.begin(), c->prof.stats.end());
+    std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.second.ms > b.second.ms; });
+    const int32_t cnt = (int32_t)v.size();
+    for (int32_t i = 0; i < cnt && i < max; ++i) {
+        std::memset(&out[i], 0, sizeof(sko_kernel_stat));
+        std::strncpy(out[i].name, v[i].first.c_str(), sizeof(out[i].name) - 1);
+        out[i].launches = v[i].second.launches;
+        out[i].total_ms = v[i].second.ms;
+        out[i].bytes = v[i].second.bytes;
+    }
+    return cnt;
 }
 
 }  // extern "C"

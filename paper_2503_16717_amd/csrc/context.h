@@ -5,10 +5,81 @@
 
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "sko.h"
 #include "sko_internal.h"
+
+namespace sko {
+
+// Event-timed per-kernel-kind statistics (sko_profile_enable / sko_profile_read).
+struct Profiler {
+    struct Stat {
+        int64_t launches = 0;
+        double ms = 0.0;
+        double bytes = 0.0;
+    };
+    struct Pending {
+        std::string name;
+        double bytes;
+        hipEvent_t e0, e1;
+    };
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    std::map<std::string, Stat> stats;
+
+    hipEvent_t take() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // Bracket one launch: begin() before it, end() after it.
+    int begin(const std::string& name, double bytes, hipStream_t st) {
+        if (!on) return -1;
+        Pending p{name, bytes, take(), take()};
+        if (!p.e0 || !p.e1 || hipEventRecord(p.e0, st) != hipSuccess) return -1;
+        pending.push_back(p);
+        return (int)pending.size() - 1;
+    }
+    void end(int idx, hipStream_t st) {
+        if (idx >= 0) (void)hipEventRecord(pending[idx].e1, st);
+    }
+    // After the stream has been synchronised: fold the pending launches into stats.
+    void flush() {
+        for (Pending& p : pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+                Stat& s = stats[p.name];
+                s.launches += 1;
+                s.ms += ms;
+                s.bytes += p.bytes;
+            }
+            pool.push_back(p.e0);
+            pool.push_back(p.e1);
+        }
+        pending.clear();
+    }
+    void release() {
+        for (Pending& p : pending) {
+            pool.push_back(p.e0);
+            pool.push_back(p.e1);
+        }
+        pending.clear();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+};
+
+}  // namespace sko
 
 struct sko_ctx_s {
     int device = 0;
@@ -17,6 +88,10 @@ struct sko_ctx_s {
     void* ws = nullptr;        // device workspace
     size_t ws_bytes = 0;
     int* status_host = nullptr;  // pinned host word for the breakdown status
+    void* pinned = nullptr;      // pinned staging for small results copied to the host
+    size_t pinned_bytes = 0;
+    sko::Profiler prof;
+    unsigned tickets = 0;        // reduce-kernel arrivals on the workspace counter since it was zeroed
 };
 
 namespace sko {
@@ -56,6 +131,23 @@ inline sko_status ensure_workspace(sko_ctx c, size_t bytes) {
         return SKO_ENOMEM;
     }
     c->ws_bytes = want;
+    return SKO_OK;
+}
+
+// Grow the pinned host staging buffer to at least `bytes`.
+inline sko_status ensure_pinned(sko_ctx c, size_t bytes) {
+    if (c->pinned_bytes >= bytes) return SKO_OK;
+    if (c->pinned) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return SKO_EDEVICE;
+        (void)hipHostFree(c->pinned);
+        c->pinned = nullptr;
+        c->pinned_bytes = 0;
+    }
+    if (hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+        c->pinned = nullptr;
+        return SKO_ENOMEM;
+    }
+    c->pinned_bytes = bytes;
     return SKO_OK;
 }
 

@@ -1,0 +1,178 @@
+// Launch orchestration shared by the block-orthogonalisation and GMRES drivers.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <initializer_list>
+#include <string>
+
+#include "context.h"
+
+namespace sko {
+
+inline const void* offset_elems(const void* p, int64_t elems, bool f32) {
+    return static_cast<const char*>(p) + elems * (f32 ? 4 : 8);
+}
+inline void* offset_elems(void* p, int64_t elems, bool f32) {
+    return static_cast<char*>(p) + elems * (f32 ? 4 : 8);
+}
+
+struct Engine {
+    sko_ctx c;
+    hipStream_t st;
+    int64_t n;
+    int W;
+    bool f32;
+    sko_sketch sk;
+    int64_t nstrips;
+    // workspace
+    double* partials = nullptr;
+    int64_t part_stride = 0;
+    int gmax = 0;
+    int* status = nullptr;
+    unsigned* counter = nullptr;
+
+    Engine(sko_ctx c_, int64_t n_, int W_, bool f32_, const sko_sketch& sk_)
+        : c(c_), st(c_->stream), n(n_), W(W_), f32(f32_), sk(sk_) {
+        nstrips = (n + kPassThreads - 1) / kPassThreads;
+    }
+
+    int grid_for(std::initializer_list<PassKey> keys) const {
+        int cap = gmax;
+        for (const PassKey& k : keys) cap = std::min(cap, std::max(1, pass_grid_cap(k)));
+        return (int)std::max<int64_t>(1, std::min<int64_t>(nstrips, cap));
+    }
+
+    // One reduction: `first` pass (may update/solve/write), then identity passes over
+    // Xsrc for the remaining reduction rows, then the reduce kernel with `small`.
+    sko_status reduction(PassKey first, PassArgs a, int rows_total, const void* Xsrc, int64_t ldxs,
+                         const void* Qp, int64_t ldqp, SmallArgs small, double scale) {
+        const int rpl = pass_rows_per_launch(W);
+        PassKey rest{W, f32, first.red, false, 0, false};
+        const int G = (rows_total > rpl) ? grid_for({first, rest}) : grid_for({first});
+        a.partials = partials;
+        a.part_stride = part_stride;
+        a.part_rows_total = rows_total;
+        a.n = n;
+        a.sk_k = sk.k;
+        a.sk_zeta = sk.zeta;
+        a.sk_seed = sk.seed;
+        for (int r0 = 0; r0 < rows_total; r0 += rpl) {
+            PassArgs b = a;
+            PassKey key = first;
+            if (r0 > 0) {
+                key = rest;
+                b.Y = Xsrc;
+                b.ldy = ldxs;
+            }
+            b.red_row0 = r0;
+            b.red_rows = std::min(rpl, rows_total - r0);
+            if (first.red == RED_PROJ) {
+                b.Qp = offset_elems(Qp, (int64_t)r0 * ldqp, f32);
+                b.ldqp = ldqp;
+            } else if (first.red == RED_SKETCH_DENSE) {
+                b.theta = sk.theta + (int64_t)r0 * sk.ld_theta;
+                b.ldtheta = sk.ld_theta;
+            }
+            const int ev = c->prof.begin(pass_name(key), pass_bytes(key, b), st);
+            SKO_HIP(launch_pass(key, b, G, st));
+            c->prof.end(ev, st);
+        }
+        ReduceArgs ra{};
+        ra.partials = partials;
+        ra.stride = part_stride;
+        ra.G = G;
+        ra.count = rows_total * W;
+        ra.scale = scale;
+        ra.counter = counter;
+        ra.ticket0 = c->tickets;
+        c->tickets += (unsigned)reduce_grid(ra.count);
+        ra.rows = ra.count;
+        ra.ldo = ra.count;
+        ra.small = small;
+        ra.small.status = status;
+        const int ev = c->prof.begin("reduce+small", 8.0 * G * ra.count, st);
+        SKO_HIP(launch_reduce(ra, st));
+        c->prof.end(ev, st);
+        return SKO_OK;
+    }
+
+    // C = A^T B (ma, nb <= 64) reduced into out (placed with leading dimension ldo) and
+    // handed to `small`.
+    sko_status gemm_reduction(const void* A, int64_t lda, int ma, const void* B, int64_t ldb, int nbc,
+                              SmallArgs small, int64_t ldo) {
+        const int64_t ns32 = (n + 31) / 32;
+        const int G = (int)std::max<int64_t>(1, std::min<int64_t>(ns32, skinny_gemm_grid_cap()));
+        const int ev = c->prof.begin(std::string("wide_gemm_tn ") + (A == B ? "gram" : "proj") + " f" +
+                                         (f32 ? "32" : "64"),
+                                     (double)n * (A == B ? ma : ma + nbc) * (f32 ? 4.0 : 8.0), st);
+        SKO_HIP(launch_skinny_gemm_tn(n, A, lda, ma, B, ldb, nbc, f32, partials, G, st));
+        c->prof.end(ev, st);
+        ReduceArgs ra{};
+        ra.partials = partials;
+        ra.stride = (int64_t)ma * nbc;
+        ra.G = G;
+        ra.count = ma * nbc;
+        ra.scale = 1.0;
+        ra.counter = counter;
+        ra.ticket0 = c->tickets;
+        c->tickets += (unsigned)reduce_grid(ra.count);
+        ra.rows = ma;
+        ra.ldo = ldo;
+        ra.small = small;
+        ra.small.status = status;
+        const int ev2 = c->prof.begin("reduce+small", 8.0 * G * ra.count, st);
+        SKO_HIP(launch_reduce(ra, st));
+        c->prof.end(ev2, st);
+        return SKO_OK;
+    }
+
+    sko_status rowop(int Wd, const void* Y, int64_t ldy, const void* Qu, int64_t ldqu, int pu, const double* Cu,
+                     const double* R, void* X, int64_t ldx) {
+        const int ev = c->prof.begin(std::string("wide_rowop f") + (f32 ? "32" : "64") + (pu > 0 ? " upd" : "") +
+                                         (R ? " trsm" : ""),
+                                     (double)n * (2 * Wd + pu) * (f32 ? 4.0 : 8.0), st);
+        SKO_HIP(launch_wide_rowop(n, Wd, f32, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx, st));
+        c->prof.end(ev, st);
+        return SKO_OK;
+    }
+
+    sko_status plain(PassKey key, PassArgs a) {
+        a.n = n;
+        const int ev = c->prof.begin(pass_name(key), pass_bytes(key, a), st);
+        SKO_HIP(launch_pass(key, a, grid_for({key}), st));
+        c->prof.end(ev, st);
+        return SKO_OK;
+    }
+
+    static std::string pass_name(const PassKey& k) {
+        static const char* reds[] = {"none", "proj", "gram", "sketch_sparse", "sketch_dense"};
+        char buf[96];
+        snprintf(buf, sizeof buf, "pass W=%d %s red=%s upd=%d trsm=%d write=%d", k.W, k.f32 ? "f32" : "f64",
+                 reds[k.red], (int)k.upd, k.ntrsm, (int)k.write);
+        return buf;
+    }
+    // Algorithmic HBM bytes of one launch: every tall operand once (read or written).
+    double pass_bytes(const PassKey& k, const PassArgs& a) const {
+        const double eb = f32 ? 4.0 : 8.0;
+        double cols = W + (k.write ? W : 0) + (k.upd ? a.pu : 0) + (k.red == RED_PROJ ? a.red_rows : 0);
+        double per_row = cols * eb + (k.red == RED_SKETCH_DENSE ? 8.0 * a.red_rows : 0.0);
+        return per_row * (double)n;
+    }
+};
+
+struct BlockBufs {
+    double *C1, *C2, *Ysk, *G2, *G3, *R1, *R2, *R3;
+};
+
+// One-stage BCGS2 block (Fig. 2c): V (n x W) against Q (n x p) -> Qo (may alias V);
+// [R_proj; R_diag] assembled at Rcol (device, rows 0..p+W-1, leading dimension ldr).
+sko_status one_stage_block(Engine& e, const BlockBufs& b, int intra, int p, const void* Q, int64_t ldq,
+                           const void* V, int64_t ldv, void* Qo, int64_t ldqo, double* Rcol, int64_t ldr,
+                           int col0);
+
+bool sketch_ok(const sko_sketch& sk, int64_t n);
+
+}  // namespace sko

@@ -1,0 +1,68 @@
+// Internal declarations of the s-step GMRES kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "sko_internal.h"
+
+namespace sko {
+
+// CSR operand: structure + FP64 values of A (explicit residual) and the values used by
+// the matrix-powers kernel (A D^{-1} in double or float, or A itself).
+struct CsrView {
+    int64_t n;
+    int64_t nnz;
+    const int32_t* rowptr;
+    const int32_t* colind;
+    const double* val;     // A, double
+    const void* val_op;    // MPK operator values (double or float)
+};
+
+hipError_t launch_spmv(const CsrView& A, bool f32, const void* x, void* y, int grid_cap, hipStream_t st);
+int residual_grid(int64_t n, int grid_cap);
+hipError_t launch_residual(const CsrView& A, const double* x, const double* b, bool f32, void* r, double* partials,
+                           int grid, hipStream_t st);
+hipError_t launch_update(int64_t n, bool f32, const void* Q, int64_t ldq, int k, const double* y,
+                         const double* dinv, double* x, hipStream_t st);
+hipError_t launch_csr_check(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind, int* bad,
+                            hipStream_t st);
+hipError_t launch_jacobi_setup(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                               const double* val, double* dinv, int* status, hipStream_t st);
+hipError_t launch_scale_values(int64_t nnz, const int32_t* colind, const double* val, const double* dinv, bool f32,
+                               void* out, hipStream_t st);
+
+enum GmOp : int {
+    GM_INIT = 0,      // T_in = T_out = 0, g = beta e_1
+    GM_BLOCK = 1,     // rewrite the boundary vector kk, store an s-step block, optional LSQ
+    GM_BIGCLOSE = 2,  // express the closed big panel in the final basis, then LSQ
+};
+
+struct GmSmallArgs {
+    int op;
+    int m, s;
+    int kk;            // GM_BLOCK: basis index of the block's start vector
+    int k0;            // two-stage: first column of the current big panel
+    int two_stage;
+    int do_lsq;
+    int Wb, kend;      // GM_BIGCLOSE: big-panel width and the basis size after it
+    double* Tin;       // (m+1) x m
+    double* Tout;      // (m+1) x m
+    double* g;         // m+1
+    double* gw;        // m+1 scratch
+    double* H;         // (m+1) x m scratch
+    double* y;         // m
+    double* res;       // 1: implicit residual norm
+    const double* beta;  // GM_INIT
+    double* coef;      // (m+1) x (s+1) block coefficients (ld m+1)
+    const double* Cpan;  // two-stage: k0 x (s+1) projection coefficients of the panel
+    const double* Rh;  // GM_BIGCLOSE: Wb x Wb
+    const double* Rt;  // GM_BIGCLOSE: Wb x Wb or null (identity)
+    const double* C2;  // GM_BIGCLOSE: k0 x Wb or null
+};
+
+hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st);
+
+}  // namespace sko

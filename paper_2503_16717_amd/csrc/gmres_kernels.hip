@@ -1,0 +1,396 @@
+// Device kernels of restarted s-step GMRES (Fig. 1, Fig. 5):
+//   * CSR SpMV for the matrix-powers kernel (MPK), L lanes per row, FP64 accumulation,
+//     double or float vectors and values;
+//   * explicit residual r = b - A x (FP64) written into the first basis column, with
+//     per-workgroup partial sums of r^2;
+//   * solution update x += D^{-1} Q y;
+//   * Jacobi set-up: D^{-1} and the column-scaled values of A D^{-1};
+//   * the small Hessenberg bookkeeping (T_in / T_out, Givens least squares).
+#include <cmath>
+
+#include "gmres_internal.h"
+
+namespace sko {
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T>
+__device__ __forceinline__ double ld_(const T* p) {
+    return static_cast<double>(*p);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// y = A x with L lanes per row (grid-stride over groups of NT/L rows).
+template <int L, typename TV, typename TX, typename TY>
+__global__ void __launch_bounds__(NT) spmv_kernel(int64_t n, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colind, const TV* __restrict__ val,
+                                                  const TX* __restrict__ x, TY* __restrict__ y) {
+    const int tid = threadIdx.x;
+    const int sub = tid % L;
+    const int64_t rows_per_block = NT / L;
+    for (int64_t base = (int64_t)blockIdx.x * rows_per_block; base < n; base += (int64_t)gridDim.x * rows_per_block) {
+        const int64_t row = base + tid / L;
+        double sum = 0.0;
+        if (row < n) {
+            const int32_t e0 = rowptr[row], e1 = rowptr[row + 1];
+            for (int32_t e = e0 + sub; e < e1; e += L) sum += ld_(val + e) * ld_(x + colind[e]);
+        }
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (sub == 0 && row < n) y[row] = static_cast<TY>(sum);
+    }
+}
+
+// r = b - A x (double), stored into R (type T); partials[blockIdx.x] = sum of r^2.
+template <int L, typename T>
+__global__ void __launch_bounds__(NT) residual_kernel(int64_t n, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colind,
+                                                      const double* __restrict__ val, const double* __restrict__ x,
+                                                      const double* __restrict__ b, T* __restrict__ r,
+                                                      double* __restrict__ partials) {
+    __shared__ double red[NT / 64];
+    const int tid = threadIdx.x;
+    const int sub = tid % L;
+    const int64_t rows_per_block = NT / L;
+    double acc = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * rows_per_block; base < n; base += (int64_t)gridDim.x * rows_per_block) {
+        const int64_t row = base + tid / L;
+        double sum = 0.0;
+        if (row < n) {
+            const int32_t e0 = rowptr[row], e1 = rowptr[row + 1];
+            for (int32_t e = e0 + sub; e < e1; e += L) sum += val[e] * x[colind[e]];
+        }
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (sub == 0 && row < n) {
+            const double rv = b[row] - sum;
+            r[row] = static_cast<T>(rv);
+            acc += rv * rv;
+        }
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+        partials[blockIdx.x] = s;
+    }
+}
+
+// x[row] += dinv[row] * sum_a Q[row, a] y[a]
+template <typename T>
+__global__ void __launch_bounds__(NT) update_kernel(int64_t n, const T* __restrict__ Q, int64_t ldq, int k,
+                                                    const double* __restrict__ y, const double* __restrict__ dinv,
+                                                    double* __restrict__ x) {
+    extern __shared__ double sy[];
+    for (int i = threadIdx.x; i < k; i += NT) sy[i] = y[i];
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (row >= n) return;
+    double s = 0.0;
+    for (int a = 0; a < k; ++a) s += ld_(Q + row + (int64_t)a * ldq) * sy[a];
+    x[row] += dinv ? dinv[row] * s : s;
+}
+
+// CSR structure check; touches rowptr[0..n] and colind[0..nnz) only by their own indices.
+__global__ void csr_check_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,
+                                 const int32_t* __restrict__ colind, int* bad) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i <= n) {
+        const int32_t r = rowptr[i];
+        if (r < 0 || r > nnz || (i == 0 && r != 0) || (i == n && r != nnz)) atomicOr(bad, 1);
+        if (i < n && rowptr[i + 1] < r) atomicOr(bad, 1);
+    }
+    for (int64_t e = i; e < nnz; e += (int64_t)gridDim.x * NT) {
+        const int32_t c = colind[e];
+        if (c < 0 || c >= n) atomicOr(bad, 1);
+    }
+}
+
+__global__ void diag_inv_kernel(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                                const double* __restrict__ val, double* __restrict__ dinv, int* status) {
+    const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (row >= n) return;
+    double d = 0.0;
+    for (int32_t e = rowptr[row]; e < rowptr[row + 1]; ++e)
+        if (colind[e] == row) d = val[e];
+    if (d == 0.0) atomicCAS(status, 0, -1);  // zero diagonal: Jacobi undefined
+    dinv[row] = 1.0 / d;
+}
+
+template <typename TV>
+__global__ void scale_values_kernel(int64_t nnz, const int32_t* __restrict__ colind, const double* __restrict__ val,
+                                    const double* __restrict__ dinv, TV* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= nnz) return;
+    const double v = dinv ? val[e] * dinv[colind[e]] : val[e];
+    out[e] = static_cast<TV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// Hessenberg bookkeeping (one workgroup).  Column-major (m+1) x m arrays Tin, Tout;
+// g (m+1); scratch H ((m+1) x m).
+// ---------------------------------------------------------------------------
+__device__ void replace_row(const GmSmallArgs& a, int row, const double* sub) {
+    // Old basis vector `row` = sum_{i <= row} sub[i] * new vector i: rewrite every stored
+    // coefficient vector (columns < row of T_in and T_out, and g).
+    const int ld = a.m + 1;
+    for (int c = threadIdx.x; c < 2 * row + 1; c += NT) {
+        double* col;
+        if (c < row)
+            col = a.Tin + (int64_t)c * ld;
+        else if (c < 2 * row)
+            col = a.Tout + (int64_t)(c - row) * ld;
+        else
+            col = a.g;
+        const double t = col[row];
+        if (t != 0.0) {
+            for (int i = 0; i < row; ++i) col[i] += t * sub[i];
+            col[row] = t * sub[row];
+        }
+    }
+    __syncthreads();
+}
+
+__device__ void store_block(const GmSmallArgs& a, int kk, const double* coef) {
+    // inputs coef[:, 0..s-1] -> T_in[:, kk..kk+s-1]; outputs coef[:, 1..s] -> T_out
+    const int ld = a.m + 1;
+    const int rows = kk + a.s + 1;
+    for (int idx = threadIdx.x; idx < ld * a.s; idx += NT) {
+        const int r = idx % ld, i = idx / ld;
+        a.Tin[r + (int64_t)(kk + i) * ld] = r < rows ? coef[r + (int64_t)i * ld] : 0.0;
+        a.Tout[r + (int64_t)(kk + i) * ld] = r < rows ? coef[r + (int64_t)(i + 1) * ld] : 0.0;
+    }
+    __syncthreads();
+}
+
+// H = T_out T_in^{-1} on the leading k columns, Givens least squares, y and residual.
+__device__ void lsq(const GmSmallArgs& a, int k) {
+    const int ld = a.m + 1;
+    double* H = a.H;
+    __shared__ double cs[2];
+    // H[r, c] = (T_out[r, c] - sum_{q<c} H[r, q] T_in[q, c]) / T_in[c, c]
+    for (int r = threadIdx.x; r <= k; r += NT) {
+        for (int c = 0; c < k; ++c) {
+            double v = a.Tout[r + (int64_t)c * ld];
+            for (int q = 0; q < c; ++q) v -= H[r + (int64_t)q * ld] * a.Tin[q + (int64_t)c * ld];
+            H[r + (int64_t)c * ld] = v / a.Tin[c + (int64_t)c * ld];
+        }
+    }
+    __syncthreads();
+    double* g = a.gw;
+    for (int i = threadIdx.x; i <= k; i += NT) g[i] = a.g[i];
+    __syncthreads();
+    for (int i = 0; i < k; ++i) {
+        if (threadIdx.x == 0) {
+            const double x = H[i + (int64_t)i * ld], z = H[i + 1 + (int64_t)i * ld];
+            const double rad = hypot(x, z);
+            cs[0] = rad == 0.0 ? 1.0 : x / rad;
+            cs[1] = rad == 0.0 ? 0.0 : z / rad;
+        }
+        __syncthreads();
+        const double c = cs[0], sn = cs[1];
+        for (int j = i + threadIdx.x; j < k; j += NT) {
+            const double top = H[i + (int64_t)j * ld], bot = H[i + 1 + (int64_t)j * ld];
+            H[i + (int64_t)j * ld] = c * top + sn * bot;
+            H[i + 1 + (int64_t)j * ld] = -sn * top + c * bot;
+        }
+        if (threadIdx.x == 0) {
+            const double gi = g[i], gj = g[i + 1];
+            g[i] = c * gi + sn * gj;
+            g[i + 1] = -sn * gi + c * gj;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int i = k - 1; i >= 0; --i) {
+            double v = g[i];
+            for (int j = i + 1; j < k; ++j) v -= H[i + (int64_t)j * ld] * a.y[j];
+            a.y[i] = v / H[i + (int64_t)i * ld];
+        }
+        a.res[0] = fabs(g[k]);
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(NT) gm_small_kernel(const GmSmallArgs a) {
+    const int ld = a.m + 1;
+    __shared__ double sub[256];
+    if (a.op == GM_INIT) {
+        for (int idx = threadIdx.x; idx < ld * a.m; idx += NT) {
+            a.Tin[idx] = 0.0;
+            a.Tout[idx] = 0.0;
+        }
+        for (int i = threadIdx.x; i < ld; i += NT) a.g[i] = (i == 0) ? a.beta[0] : 0.0;
+        return;
+    }
+    if (a.op == GM_BLOCK) {
+        const int kk = a.kk;
+        // coefficient rows 0..k0-1 of a two-stage panel come from the projection buffer
+        if (a.Cpan) {
+            for (int idx = threadIdx.x; idx < a.k0 * (a.s + 1); idx += NT) {
+                const int r = idx % a.k0, c = idx / a.k0;
+                a.coef[r + (int64_t)c * ld] = a.Cpan[idx];
+            }
+        } else if (a.two_stage) {
+            for (int idx = threadIdx.x; idx < a.k0 * (a.s + 1); idx += NT) {
+                const int r = idx % a.k0, c = idx / a.k0;
+                a.coef[r + (int64_t)c * ld] = 0.0;
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i <= kk; i += NT) sub[i] = a.coef[i];
+        __syncthreads();
+        replace_row(a, kk, sub);
+        store_block(a, kk, a.coef);
+        if (a.do_lsq) lsq(a, kk + a.s);
+        return;
+    }
+    if (a.op == GM_BIGCLOSE) {
+        // rows k0..k0+W-1 of every stored vector refer to the pre-processed big panel:
+        // t[:k0] += C2 Rh t[k0:], t[k0:] = Rt Rh t[k0:]  (Rt = I without the second pass)
+        const int k0 = a.k0, W = a.Wb, kend = a.kend;
+        for (int c = threadIdx.x; c < 2 * kend + 1; c += NT) {
+            double* col;
+            if (c < kend)
+                col = a.Tin + (int64_t)c * ld;
+            else if (c < 2 * kend)
+                col = a.Tout + (int64_t)(c - kend) * ld;
+            else
+                col = a.g;
+            double u[64];
+            for (int i = 0; i < W; ++i) {
+                double v = 0.0;
+                for (int j = i; j < W; ++j) v += a.Rh[i + j * W] * col[k0 + j];
+                u[i] = v;
+            }
+            if (a.C2) {
+                for (int r = 0; r < k0; ++r) {
+                    double v = 0.0;
+                    for (int j = 0; j < W; ++j) v += a.C2[r + (int64_t)j * k0] * u[j];
+                    col[r] += v;
+                }
+            }
+            for (int i = 0; i < W; ++i) {
+                double v;
+                if (a.Rt) {
+                    v = 0.0;
+                    for (int j = i; j < W; ++j) v += a.Rt[i + j * W] * u[j];
+                } else {
+                    v = u[i];
+                }
+                col[k0 + i] = v;
+            }
+        }
+        __syncthreads();
+        lsq(a, kend);
+        return;
+    }
+}
+
+template <typename TV, typename TX, typename TY>
+hipError_t spmv_dispatch(int64_t n, double avg, const int32_t* rp, const int32_t* ci, const TV* v, const TX* x, TY* y,
+                         int grid_cap, hipStream_t st) {
+    const int L = avg > 4.0 ? 8 : 4;
+    const int64_t groups = (n + NT / L - 1) / (NT / L);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, grid_cap));
+    if (L == 8)
+        hipLaunchKernelGGL((spmv_kernel<8, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+    else
+        hipLaunchKernelGGL((spmv_kernel<4, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_spmv(const CsrView& A, bool f32, const void* x, void* y, int grid_cap, hipStream_t st) {
+    const double avg = (double)A.nnz / (double)std::max<int64_t>(1, A.n);
+    if (f32)
+        return spmv_dispatch<float, float, float>(A.n, avg, A.rowptr, A.colind, static_cast<const float*>(A.val_op),
+                                                  static_cast<const float*>(x), static_cast<float*>(y), grid_cap, st);
+    return spmv_dispatch<double, double, double>(A.n, avg, A.rowptr, A.colind, static_cast<const double*>(A.val_op),
+                                                 static_cast<const double*>(x), static_cast<double*>(y), grid_cap, st);
+}
+
+int residual_grid(int64_t n, int grid_cap) {
+    const int64_t groups = (n + NT / 8 - 1) / (NT / 8);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(groups, grid_cap));
+}
+
+hipError_t launch_residual(const CsrView& A, const double* x, const double* b, bool f32, void* r, double* partials,
+                           int grid, hipStream_t st) {
+    const double avg = (double)A.nnz / (double)std::max<int64_t>(1, A.n);
+    const bool l8 = avg > 4.0;
+    if (f32) {
+        if (l8)
+            hipLaunchKernelGGL((residual_kernel<8, float>), dim3(grid), dim3(NT), 0, st, A.n, A.rowptr, A.colind, A.val,
+                               x, b, static_cast<float*>(r), partials);
+        else
+            hipLaunchKernelGGL((residual_kernel<4, float>), dim3(grid), dim3(NT), 0, st, A.n, A.rowptr, A.colind, A.val,
+                               x, b, static_cast<float*>(r), partials);
+    } else {
+        if (l8)
+            hipLaunchKernelGGL((residual_kernel<8, double>), dim3(grid), dim3(NT), 0, st, A.n, A.rowptr, A.colind,
+                               A.val, x, b, static_cast<double*>(r), partials);
+        else
+            hipLaunchKernelGGL((residual_kernel<4, double>), dim3(grid), dim3(NT), 0, st, A.n, A.rowptr, A.colind,
+                               A.val, x, b, static_cast<double*>(r), partials);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update(int64_t n, bool f32, const void* Q, int64_t ldq, int k, const double* y, const double* dinv,
+                         double* x, hipStream_t st) {
+    if (k < 1) return hipSuccess;
+    const int grid = (int)((n + NT - 1) / NT);
+    const size_t lds = sizeof(double) * (size_t)k;
+    if (f32)
+        hipLaunchKernelGGL((update_kernel<float>), dim3(grid), dim3(NT), lds, st, n, static_cast<const float*>(Q), ldq,
+                           k, y, dinv, x);
+    else
+        hipLaunchKernelGGL((update_kernel<double>), dim3(grid), dim3(NT), lds, st, n, static_cast<const double*>(Q),
+                           ldq, k, y, dinv, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_check(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind, int* bad,
+                            hipStream_t st) {
+    const unsigned grid = (unsigned)((n + 1 + NT - 1) / NT);
+    hipLaunchKernelGGL(csr_check_kernel, dim3(grid), dim3(NT), 0, st, n, nnz, rowptr, colind, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_setup(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                               const double* val, double* dinv, int* status, hipStream_t st) {
+    hipLaunchKernelGGL(diag_inv_kernel, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, n, rowptr, colind, val,
+                       dinv, status);
+    (void)nnz;
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_values(int64_t nnz, const int32_t* colind, const double* val, const double* dinv, bool f32,
+                               void* out, hipStream_t st) {
+    const unsigned grid = (unsigned)((nnz + NT - 1) / NT);
+    if (f32)
+        hipLaunchKernelGGL((scale_values_kernel<float>), dim3(grid), dim3(NT), 0, st, nnz, colind, val, dinv,
+                           static_cast<float*>(out));
+    else
+        hipLaunchKernelGGL((scale_values_kernel<double>), dim3(grid), dim3(NT), 0, st, nnz, colind, val, dinv,
+                           static_cast<double*>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st) {
+    if (a.m + 1 > 256 || a.Wb > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gm_small_kernel, dim3(1), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace sko

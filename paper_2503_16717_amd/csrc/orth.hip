@@ -18,102 +18,16 @@
 // With p = 0 the projections vanish: P2 reads V directly, P4 accumulates G3 = Qh^T Qh.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
 #include <vector>
 
-#include "context.h"
+#include "engine.h"
 
 namespace sko {
-namespace {
 
-inline const void* offset_elems(const void* p, int64_t elems, bool f32) {
-    return static_cast<const char*>(p) + elems * (f32 ? 4 : 8);
-}
-inline void* offset_elems(void* p, int64_t elems, bool f32) {
-    return static_cast<char*>(p) + elems * (f32 ? 4 : 8);
-}
 
-struct Engine {
-    sko_ctx c;
-    hipStream_t st;
-    int64_t n;
-    int W;
-    bool f32;
-    sko_sketch sk;
-    int64_t nstrips;
-    // workspace
-    double* partials = nullptr;
-    int64_t part_stride = 0;
-    int gmax = 0;
-    int* status = nullptr;
-    unsigned* counter = nullptr;
-
-    Engine(sko_ctx c_, int64_t n_, int W_, bool f32_, const sko_sketch& sk_)
-        : c(c_), st(c_->stream), n(n_), W(W_), f32(f32_), sk(sk_) {
-        nstrips = (n + kPassThreads - 1) / kPassThreads;
-    }
-
-    int grid_for(std::initializer_list<PassKey> keys) const {
-        int cap = gmax;
-        for (const PassKey& k : keys) cap = std::min(cap, std::max(1, pass_grid_cap(k)));
-        return (int)std::max<int64_t>(1, std::min<int64_t>(nstrips, cap));
-    }
-
-    // One reduction: `first` pass (may update/solve/write), then identity passes over
-    // Xsrc for the remaining reduction rows, then the reduce kernel with `small`.
-    sko_status reduction(PassKey first, PassArgs a, int rows_total, const void* Xsrc, int64_t ldxs,
-                         const void* Qp, int64_t ldqp, SmallArgs small, double scale) {
-        const int rpl = pass_rows_per_launch(W);
-        PassKey rest{W, f32, first.red, false, 0, false};
-        const int G = (rows_total > rpl) ? grid_for({first, rest}) : grid_for({first});
-        a.partials = partials;
-        a.part_stride = part_stride;
-        a.part_rows_total = rows_total;
-        a.n = n;
-        a.sk_k = sk.k;
-        a.sk_zeta = sk.zeta;
-        a.sk_seed = sk.seed;
-        for (int r0 = 0; r0 < rows_total; r0 += rpl) {
-            PassArgs b = a;
-            PassKey key = first;
-            if (r0 > 0) {
-                key = rest;
-                b.Y = Xsrc;
-                b.ldy = ldxs;
-            }
-            b.red_row0 = r0;
-            b.red_rows = std::min(rpl, rows_total - r0);
-            if (first.red == RED_PROJ) {
-                b.Qp = offset_elems(Qp, (int64_t)r0 * ldqp, f32);
-                b.ldqp = ldqp;
-            } else if (first.red == RED_SKETCH_DENSE) {
-                b.theta = sk.theta + (int64_t)r0 * sk.ld_theta;
-                b.ldtheta = sk.ld_theta;
-            }
-            SKO_HIP(launch_pass(key, b, G, st));
-        }
-        ReduceArgs ra{};
-        ra.partials = partials;
-        ra.stride = part_stride;
-        ra.G = G;
-        ra.count = rows_total * W;
-        ra.scale = scale;
-        ra.counter = counter;
-        ra.small = small;
-        ra.small.status = status;
-        SKO_HIP(launch_reduce(ra, st));
-        return SKO_OK;
-    }
-
-    sko_status plain(PassKey key, PassArgs a) {
-        a.n = n;
-        SKO_HIP(launch_pass(key, a, grid_for({key}), st));
-        return SKO_OK;
-    }
-};
-
-struct BlockBufs {
-    double *C1, *C2, *Ysk, *G2, *G3, *R1, *R2, *R3;
-};
 
 // One-stage BCGS2 block: V (n x W) against Q (n x p) -> Qo; R columns assembled at
 // Rcol (device, rows 0..p+W-1, leading dimension ldr).
@@ -272,6 +186,8 @@ bool sketch_ok(const sko_sketch& sk, int64_t n) {
     return false;
 }
 
+namespace {
+
 // Workspace sizing shared by the one-stage entry points.
 struct OneStageLayout {
     size_t partials, small, rfull, status, total;
@@ -314,6 +230,7 @@ BlockBufs carve(sko_ctx c, const OneStageLayout& L, int pmax, int k, int W) {
 sko_status finish(sko_ctx c, int* status_dev, int32_t* breakdown_col) {
     SKO_HIP(hipMemcpyAsync(c->status_host, status_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     SKO_HIP(hipStreamSynchronize(c->stream));
+    c->prof.flush();
     const int col = *c->status_host;
     if (breakdown_col) *breakdown_col = col;
     return col ? SKO_EBREAKDOWN : SKO_OK;
@@ -337,9 +254,9 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     if (!o->two_stage && o->intra != SKO_INTRA_RANDCHOLQR && o->intra != SKO_INTRA_CHOLQR2) return SKO_EINVAL;
     if (rand && !sketch_ok(o->sketch, n)) return SKO_EINVAL;
     if (rand && o->sketch.k < w) return SKO_EINVAL;
-    if ((int64_t)(N - w) * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
     if (w > pass_rows_per_launch(w)) return SKO_EUNSUPPORTED;
     if (o->two_stage) return two_stage_blocks(c, n, nb, w, V, ldv, Q, ldq, R, ldr, o, breakdown_col);
+    if ((int64_t)(N - w) * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
 
     const bool f32 = o->precision == SKO_MIXED_F32;
     const int k = rand ? o->sketch.k : w;
@@ -355,6 +272,7 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
     double* Rfull = ar.at<double>(L.rfull);
     SKO_HIP(hipMemsetAsync(e.status, 0, 256, c->stream));
+    c->tickets = 0;
     SKO_HIP(hipMemsetAsync(Rfull, 0, sizeof(double) * (size_t)N * N, c->stream));
     BlockBufs bb = carve(c, L, N - w, k, w);
     for (int j = 0; j < nb; ++j) {
@@ -364,11 +282,16 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
         s = one_stage_block(e, bb, o->intra, p, Q, ldq, Vj, ldv, Qj, ldq, Rfull + (int64_t)p * N, N, p);
         if (s) return s;
     }
+    double* Rh = nullptr;
     if (R) {
-        SKO_HIP(hipMemcpy2DAsync(R, sizeof(double) * ldr, Rfull, sizeof(double) * N, sizeof(double) * N, N,
-                                 hipMemcpyDeviceToHost, c->stream));
+        if ((s = ensure_pinned(c, sizeof(double) * (size_t)N * N))) return s;
+        Rh = static_cast<double*>(c->pinned);
+        SKO_HIP(hipMemcpyAsync(Rh, Rfull, sizeof(double) * (size_t)N * N, hipMemcpyDeviceToHost, c->stream));
     }
-    return finish(c, e.status, breakdown_col);
+    if ((s = finish(c, e.status, breakdown_col)) && s != SKO_EBREAKDOWN) return s;
+    if (R)
+        for (int jc = 0; jc < N; ++jc) std::memcpy(R + (int64_t)jc * ldr, Rh + (int64_t)jc * N, sizeof(double) * N);
+    return s;
 }
 
 sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq, const void* V,
@@ -399,21 +322,221 @@ sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const voi
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
     double* Rcol = ar.at<double>(L.rfull);  // (p + w) x w, ld p + w
     SKO_HIP(hipMemsetAsync(e.status, 0, 256, c->stream));
+    c->tickets = 0;
     BlockBufs bb = carve(c, L, p, k, w);
     s = one_stage_block(e, bb, o->intra, p, Q, ldq, V, ldv, Qo, ldqo, Rcol, N, 0);
     if (s) return s;
-    if (Rp && p > 0)
-        SKO_HIP(hipMemcpy2DAsync(Rp, sizeof(double) * p, Rcol, sizeof(double) * N, sizeof(double) * p, w,
-                                 hipMemcpyDeviceToHost, c->stream));
-    if (Rd)
-        SKO_HIP(hipMemcpy2DAsync(Rd, sizeof(double) * w, Rcol + p, sizeof(double) * N, sizeof(double) * w, w,
-                                 hipMemcpyDeviceToHost, c->stream));
-    return finish(c, e.status, breakdown_col);
+    if ((s = ensure_pinned(c, sizeof(double) * (size_t)N * w))) return s;
+    double* Rh = static_cast<double*>(c->pinned);
+    SKO_HIP(hipMemcpyAsync(Rh, Rcol, sizeof(double) * (size_t)N * w, hipMemcpyDeviceToHost, c->stream));
+    if ((s = finish(c, e.status, breakdown_col)) && s != SKO_EBREAKDOWN) return s;
+    for (int jc = 0; jc < w; ++jc) {
+        if (Rp && p > 0) std::memcpy(Rp + (int64_t)jc * p, Rh + (int64_t)jc * N, sizeof(double) * p);
+        if (Rd) std::memcpy(Rd + (int64_t)jc * w, Rh + (int64_t)jc * N + p, sizeof(double) * w);
+    }
+    return s;
 }
 
-sko_status two_stage_blocks(sko_ctx, int64_t, int32_t, int32_t, const void*, int64_t, void*, int64_t, double*,
-                            int64_t, const sko_orth_opts*, int32_t*) {
-    return SKO_EUNSUPPORTED;
+sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const void* V, int64_t ldv, void* Q,
+                            int64_t ldq, double* R, int64_t ldr, const sko_orth_opts* o, int32_t* breakdown_col) {
+    const int ppb = o->panels_per_big;
+    if (ppb < 1 || nb % ppb) return SKO_EINVAL;
+    const int Wb = ppb * w;
+    if (Wb > 64) return SKO_EUNSUPPORTED;
+    if (o->sketch.k < Wb) return SKO_EINVAL;  // the big panel must embed into the sketch space
+    const bool f32 = o->precision == SKO_MIXED_F32;
+    const int N = nb * w;
+    const int k = o->sketch.k;
+    const int pmax = N - Wb;  // largest previous-basis width
+    if ((int64_t)pmax * Wb * 8 + (int64_t)Wb * Wb * 8 > 60 * 1024) return SKO_EUNSUPPORTED;
+    if ((int64_t)(Wb - w) * w > kMaxUpdCoef || (int64_t)pmax * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
+
+    // workspace
+    Arena ar(c);
+    const int64_t nstrips = (n + kPassThreads - 1) / kPassThreads;
+    const int gmax = (int)std::min<int64_t>(nstrips, (int64_t)std::max(1, c->cus) * 8);
+    const int64_t rows = std::max({(int64_t)pmax, (int64_t)k, (int64_t)w});
+    const int64_t part_stride = ((rows * w + 31) / 32) * 32;
+    const size_t part_doubles =
+        std::max<size_t>((size_t)part_stride * gmax, (size_t)64 * 64 * std::max(1, skinny_gemm_grid_cap()));
+    const size_t o_part = ar.reserve(sizeof(double) * part_doubles);
+    const int64_t pw = std::max<int64_t>(1, (int64_t)pmax * Wb);
+    const size_t o_C = ar.reserve(sizeof(double) * pw);
+    const size_t o_C2 = ar.reserve(sizeof(double) * pw);
+    const size_t o_Y = ar.reserve(sizeof(double) * (size_t)k * w);
+    const size_t o_Yacc = ar.reserve(sizeof(double) * (size_t)k * Wb);
+    const size_t o_r = ar.reserve(sizeof(double) * (size_t)Wb * w);
+    const size_t o_rho = ar.reserve(sizeof(double) * (size_t)w * w);
+    const size_t o_Rbar = ar.reserve(sizeof(double) * (size_t)Wb * Wb);
+    const size_t o_G = ar.reserve(sizeof(double) * (size_t)Wb * Wb);
+    const size_t o_Rh = ar.reserve(sizeof(double) * (size_t)Wb * Wb);
+    const size_t o_Rt = ar.reserve(sizeof(double) * (size_t)Wb * Wb);
+    const size_t o_Rf = ar.reserve(sizeof(double) * (size_t)N * N);
+    const size_t o_st = ar.reserve(256);
+    sko_status s = ensure_workspace(c, ar.used());
+    if (s) return s;
+    Engine e(c, n, w, f32, o->sketch);
+    e.partials = ar.at<double>(o_part);
+    e.part_stride = part_stride;
+    e.gmax = gmax;
+    e.status = ar.at<int>(o_st);
+    e.counter = reinterpret_cast<unsigned*>(e.status + 16);
+    double* C = ar.at<double>(o_C);
+    double* C2 = ar.at<double>(o_C2);
+    double* Ysk = ar.at<double>(o_Y);
+    double* Yacc = ar.at<double>(o_Yacc);
+    double* rt = ar.at<double>(o_r);
+    double* rho = ar.at<double>(o_rho);
+    double* Rbar = ar.at<double>(o_Rbar);
+    double* Gb = ar.at<double>(o_G);
+    double* Rh = ar.at<double>(o_Rh);
+    double* Rt = ar.at<double>(o_Rt);
+    double* Rfull = ar.at<double>(o_Rf);
+    SKO_HIP(hipMemsetAsync(e.status, 0, 256, c->stream));
+    c->tickets = 0;
+    SKO_HIP(hipMemsetAsync(Rfull, 0, sizeof(double) * (size_t)N * N, c->stream));
+
+    const int red_sk = o->sketch.kind == SKO_SKETCH_SPARSE_SIGN ? RED_SKETCH_SPARSE : RED_SKETCH_DENSE;
+    const double sk_scale =
+        o->sketch.kind == SKO_SKETCH_SPARSE_SIGN ? 1.0 / std::sqrt((double)o->sketch.zeta) : 1.0;
+    const bool reorth = o->reorth != 0;
+
+    for (int big = 0; big < nb / ppb; ++big) {
+        const int p_old = big * Wb;
+        void* Qb = offset_elems(Q, (int64_t)p_old * ldq, f32);
+        SKO_HIP(hipMemsetAsync(Rbar, 0, sizeof(double) * (size_t)Wb * Wb, c->stream));
+        // ---- first stage: pre-process panel by panel (Fig. 5 Lines 10, 12; Fig. 8)
+        for (int i = 0; i < ppb; ++i) {
+            const int col = p_old + i * w;
+            const void* Vi = offset_elems(V, (int64_t)col * ldv, f32);
+            void* Qi = offset_elems(Q, (int64_t)col * ldq, f32);
+            const void* Vh = Vi;
+            int64_t ldvh = ldv;
+            double* Ci = C + (int64_t)i * w * p_old;
+            if (p_old > 0) {
+                PassArgs a{};
+                a.Y = Vi;
+                a.ldy = ldv;
+                SmallArgs sm{};
+                sm.op = OP_STORE;
+                sm.w = w;
+                sm.out = Ci;
+                if ((s = e.reduction({w, f32, RED_PROJ, false, 0, false}, a, p_old, Vi, ldv, Q, ldq, sm, 1.0)))
+                    return s;
+            }
+            {
+                PassArgs a{};
+                a.Y = Vi;
+                a.ldy = ldv;
+                PassKey key{w, f32, red_sk, false, 0, false};
+                if (p_old > 0) {
+                    key.upd = true;
+                    key.write = true;
+                    a.Qu = Q;
+                    a.ldqu = ldq;
+                    a.pu = p_old;
+                    a.Cu = Ci;
+                    a.X = Qi;
+                    a.ldx = ldq;
+                    Vh = Qi;
+                    ldvh = ldq;
+                }
+                SmallArgs sm{};
+                sm.op = OP_SKETCH_BCGS2;
+                sm.w = w;
+                sm.k = k;
+                sm.col0 = col;
+                sm.out = Ysk;
+                sm.R = rho;
+                sm.Yacc = Yacc;
+                sm.nacc = i * w;
+                sm.r = rt;
+                sm.Rbar = Rbar;
+                sm.ldrbar = Wb;
+                sm.rbar_col0 = i * w;
+                if ((s = e.reduction(key, a, k, Vh, ldvh, nullptr, 0, sm, sk_scale))) return s;
+            }
+            {   // Q_bar_i = (V_hat_i - Q_bar_prev r) rho^{-1}
+                PassArgs a{};
+                a.Y = Vh;
+                a.ldy = ldvh;
+                a.R1 = rho;
+                a.X = Qi;
+                a.ldx = ldq;
+                PassKey key{w, f32, RED_NONE, false, 1, true};
+                if (i > 0) {
+                    key.upd = true;
+                    a.Qu = Qb;
+                    a.ldqu = ldq;
+                    a.pu = i * w;
+                    a.Cu = rt;
+                }
+                if ((s = e.plain(key, a))) return s;
+            }
+        }
+        // ---- second stage: CholQR of the big panel (Line 15), BCGS + CholQR (Line 19)
+        {
+            SmallArgs sm{};
+            sm.op = OP_CHOL;
+            sm.w = Wb;
+            sm.col0 = p_old;
+            sm.out = Gb;
+            sm.R = Rh;
+            if (!reorth) {
+                sm.assemble = 1;
+                sm.r_identity = 1;
+                sm.Ra = Rh;
+                sm.Rb = Rbar;
+                sm.C1 = p_old > 0 ? C : nullptr;
+                sm.p = p_old;
+                sm.Rout = Rfull + (int64_t)p_old * N;
+                sm.ldr = N;
+            }
+            if ((s = e.gemm_reduction(Qb, ldq, Wb, Qb, ldq, Wb, sm, Wb))) return s;
+            if ((s = e.rowop(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rh, Qb, ldq))) return s;
+        }
+        if (reorth) {
+            if (p_old > 0) {
+                for (int a0 = 0; a0 < p_old; a0 += 64) {
+                    const int ma = std::min(64, p_old - a0);
+                    SmallArgs sm{};
+                    sm.op = OP_STORE;
+                    sm.w = Wb;
+                    sm.out = C2 + a0;
+                    if ((s = e.gemm_reduction(offset_elems(Q, (int64_t)a0 * ldq, f32), ldq, ma, Qb, ldq, Wb, sm, p_old)))
+                        return s;
+                }
+                if ((s = e.rowop(Wb, Qb, ldq, Q, ldq, p_old, C2, nullptr, Qb, ldq))) return s;
+            }
+            SmallArgs sm{};
+            sm.op = OP_CHOL;
+            sm.w = Wb;
+            sm.col0 = p_old;
+            sm.out = Gb;
+            sm.R = Rt;
+            sm.assemble = 1;
+            sm.Ra = Rh;
+            sm.Rb = Rbar;
+            sm.C1 = p_old > 0 ? C : nullptr;
+            sm.C2 = p_old > 0 ? C2 : nullptr;
+            sm.p = p_old;
+            sm.Rout = Rfull + (int64_t)p_old * N;
+            sm.ldr = N;
+            if ((s = e.gemm_reduction(Qb, ldq, Wb, Qb, ldq, Wb, sm, Wb))) return s;
+            if ((s = e.rowop(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rt, Qb, ldq))) return s;
+        }
+    }
+    double* Rhost = nullptr;
+    if (R) {
+        if ((s = ensure_pinned(c, sizeof(double) * (size_t)N * N))) return s;
+        Rhost = static_cast<double*>(c->pinned);
+        SKO_HIP(hipMemcpyAsync(Rhost, Rfull, sizeof(double) * (size_t)N * N, hipMemcpyDeviceToHost, c->stream));
+    }
+    if ((s = finish(c, e.status, breakdown_col)) && s != SKO_EBREAKDOWN) return s;
+    if (R)
+        for (int jc = 0; jc < N; ++jc)
+            std::memcpy(R + (int64_t)jc * ldr, Rhost + (int64_t)jc * N, sizeof(double) * N);
+    return s;
 }
 
 }  // namespace sko

@@ -101,9 +101,15 @@ struct SmallArgs {
     double* Yacc;        // k x cap, column-major (ld k): accumulated orthonormal sketches
     int nacc;            // columns of Yacc orthogonalised against (the first nacc)
     double* r;           // nacc x w coefficients (ld nacc), r1 + r2
+    // OP_SKETCH_BCGS2: optional copy of [r; rho] into columns rbar_col0.. of Rbar (ld ldrbar)
+    double* Rbar;
+    int ldrbar;
+    int rbar_col0;
     // assembly after OP_CHOL (assemble != 0):
     //   Rhat = Ra * Rb (w x w), Rdiag = R * Rhat, Rproj = C1 + C2 * Rhat (p x w)
+    // (r_identity != 0: the R of this reduction is replaced by the identity in Rdiag)
     int assemble;
+    int r_identity;
     const double* Ra;
     const double* Rb;
     const double* C1;
@@ -119,9 +125,20 @@ struct ReduceArgs {
     int G;
     int count;
     double scale;
+    // Arrival ticket: the counter is zeroed once per call and never reset; the launch
+    // whose workgroups arrive with tickets [ticket0, ticket0 + grid) elects the one that
+    // draws ticket0 + grid - 1 as the last workgroup.
     unsigned int* counter;
+    unsigned int ticket0;
+    // Placement of reduced element e (= r + c * rows): small.out[r + c * ldo].  OP_STORE
+    // may write into a sub-block of a larger matrix; the other ops need ldo == rows.
+    int rows;
+    int64_t ldo;
     SmallArgs small;
 };
+
+// Number of workgroups launch_reduce uses for `count` reduced values.
+int reduce_grid(int count);
 
 hipError_t launch_reduce(const ReduceArgs& args, hipStream_t stream);
 

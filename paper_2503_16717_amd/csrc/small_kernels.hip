@@ -185,7 +185,10 @@ __device__ void assemble(const SmallArgs& s, double* rh) {
         for (int idx = tid; idx < w * w; idx += RT) {
             const int a = idx % w, c = idx / w;
             double v = 0.0;
-            for (int t = a; t <= c; ++t) v += load_coherent(s.R + a + t * w) * load_coherent(rh + t + c * w);
+            if (s.r_identity)
+                v = load_coherent(rh + a + c * w);
+            else
+                for (int t = a; t <= c; ++t) v += load_coherent(s.R + a + t * w) * load_coherent(rh + t + c * w);
             s.Rout[(s.p + a) + c * s.ldr] = (a <= c) ? v : 0.0;
         }
         for (int idx = tid; idx < s.p * w; idx += RT) {
@@ -232,6 +235,18 @@ __device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* r
     householder_lds(Z, k, w, E, s.R, w, s.status, s.col0, red, scal);
     // append q to the accumulated sketches (replacing the boundary column at nacc)
     for (int idx = tid; idx < k * w; idx += RT) s.Yacc[(int64_t)na * k + idx] = E[idx];
+    if (s.Rbar) {
+        __syncthreads();
+        for (int idx = tid; idx < (na + w) * w; idx += RT) {
+            const int a = idx % (na + w), c = idx / (na + w);
+            double v;
+            if (a < na)
+                v = load_coherent(s.r + a + c * na);
+            else
+                v = load_coherent(s.R + (a - na) + c * w);
+            s.Rbar[a + (int64_t)(s.rbar_col0 + c) * s.ldrbar] = v;
+        }
+    }
     __syncthreads();
 }
 
@@ -255,14 +270,14 @@ __global__ void __launch_bounds__(RT) reduce_kernel(const ReduceArgs a) {
         if (ee < a.count) {
             double s = 0.0;
             for (int p = 0; p < PARTS; ++p) s += part[p * EPW + tid];
-            a.small.out[ee] = s * a.scale;
+            a.small.out[(ee % a.rows) + (int64_t)(ee / a.rows) * a.ldo] = s * a.scale;
         }
     }
     __threadfence();
     __syncthreads();
     if (tid == 0) {
         const unsigned prev = atomicAdd(a.counter, 1u);
-        s_last = (prev == gridDim.x - 1) ? 1 : 0;
+        s_last = (prev == a.ticket0 + gridDim.x - 1) ? 1 : 0;
     }
     __syncthreads();
     if (!s_last) return;
@@ -289,8 +304,6 @@ __global__ void __launch_bounds__(RT) reduce_kernel(const ReduceArgs a) {
         double* E = lds + s.k * s.w;
         sketch_bcgs2(s, Z, E, red, scal);
     }
-    __threadfence();
-    if (tid == 0) *a.counter = 0u;
 }
 
 __global__ void matmul_upper_kernel(int w, const double* A, const double* B, double* C) {
@@ -303,6 +316,8 @@ __global__ void matmul_upper_kernel(int w, const double* A, const double* B, dou
 }
 
 }  // namespace
+
+int reduce_grid(int count) { return (count + EPW - 1) / EPW; }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream) {
     if (a.count <= 0 || a.G <= 0) return hipErrorInvalidValue;
@@ -320,7 +335,7 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream) {
         lds = sizeof(double) * ((size_t)s.k * s.w + e);
     }
     if (lds > 60 * 1024) return hipErrorInvalidValue;
-    const int grid = (a.count + EPW - 1) / EPW;
+    const int grid = reduce_grid(a.count);
     hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(RT), lds, stream, a);
     return hipGetLastError();
 }

@@ -123,32 +123,47 @@ def convdiff_3d(N: int, wind=(10.0, 20.0, 30.0)) -> CSR:
 
 
 def _orthonormal_factor(g: np.ndarray) -> np.ndarray:
-    # Orthonormal basis of a random Gaussian matrix (input generation only).
-    q, _ = np.linalg.qr(g)
+    # Orthonormal basis of a random Gaussian matrix (input generation only; LAPACK
+    # Householder QR on the Fortran-ordered copy).
+    import scipy.linalg as sla
+    q, _ = sla.qr(np.asfortranarray(g), mode="economic", overwrite_a=True, check_finite=False)
     return q
 
 
 def glued_block(n: int, w: int, log10_cond: float, j: int, dtype=np.float64,
                 out: np.ndarray | None = None) -> np.ndarray:
-    """Block j of ``glued_blocks``: U diag(sigma) W^T, column-major (Fortran) n x w."""
+    """Block j of ``glued_blocks``: U diag(sigma) W^T, column-major (Fortran) n x w.
+
+    U and W are the orthonormal factors of default_rng([2, j]) and default_rng([3, j])
+    standard normal draws of shape (n, w) and (w, w)."""
     u = _orthonormal_factor(np.random.default_rng([2, j]).standard_normal((n, w)))
     wm = _orthonormal_factor(np.random.default_rng([3, j]).standard_normal((w, w)))
     if w > 1:
         sigma = 10.0 ** (-float(log10_cond) * np.arange(w) / (w - 1))
     else:
         sigma = np.ones(1)
-    blk = (u * sigma) @ wm.T
+    blk = u @ (sigma[:, None] * wm.T)
     if out is None:
         out = np.empty((n, w), dtype=dtype, order="F")
     out[:, :] = blk
     return out
 
 
-def glued_blocks(n: int, nb: int, w: int, log10_cond: float = 12.0, dtype=np.float64) -> np.ndarray:
+def glued_blocks(n: int, nb: int, w: int, log10_cond: float = 12.0, dtype=np.float64,
+                 threads: int = 1) -> np.ndarray:
     """n x (nb*w) column-major matrix of nb independent blocks of condition 10^log10_cond."""
     V = np.empty((n, nb * w), dtype=dtype, order="F")
-    for j in range(nb):
+
+    def one(j):
         glued_block(n, w, log10_cond, j, dtype=dtype, out=V[:, j * w:(j + 1) * w])
+
+    if threads > 1 and nb > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, range(nb)))
+    else:
+        for j in range(nb):
+            one(j)
     return V
 
 

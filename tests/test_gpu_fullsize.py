@@ -1,0 +1,73 @@
+"""Full-size checks in the benchmark's launch configuration: n = 2^24 rows, 12 blocks of 6
+columns, kappa = 1e12 per block, one-stage RandCholQR-BCGS2 with the sparse-sign sketch
+(k = 64, zeta = 8).
+
+At this size the oracle recomputes what it can one piece at a time: the first block's R
+factor (a full-length oracle run on n x 6), and the properties that hold at any size --
+||I - Q^T Q||_2 <= 1e-13 and ||V - Q R||_F / ||V||_F <= 1e-14 measured by the oracle's
+compensated metrics on the downloaded Q -- plus bitwise repeatability of the GPU result.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import metrics, orth  # noqa: E402
+from oracle.sketch import Sketch  # noqa: E402
+from paper_2503_16717_amd import workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+N_ROWS, NB, W, E = 1 << 24, 12, 6, 12.0
+
+
+@pytest.fixture(scope="module")
+def full():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_16717_amd import binding as B
+    V = wl.glued_blocks(N_ROWS, NB, W, E, threads=min(12, os.cpu_count() or 1))
+    Vd = B.colmajor_from_numpy(V, "cuda")
+    ctx = B.Context(0)
+    sk = B.make_sketch("sparse_sign", 64, 8, 0)
+    outs = []
+    for _ in range(3):
+        Q, R, st, col = ctx.orth_blocks(Vd, W, intra="randcholqr", sketch=sk)
+        torch.cuda.synchronize()
+        assert st == B.SKO_OK, (st, col)
+        outs.append((Q, R))
+    ctx.close()
+    return V, outs
+
+
+def test_fullsize_repeatable(full):
+    V, outs = full
+    (Q0, R0) = outs[0]
+    for Q, R in outs[1:]:
+        assert np.array_equal(R, R0)
+        assert torch.equal(Q, Q0)
+
+
+def test_fullsize_properties(full):
+    V, outs = full
+    Q, R = outs[-1]
+    assert np.allclose(np.tril(R, -1), 0.0, atol=0.0)
+    assert np.all(np.diag(R) > 0)
+    Qh = Q.cpu().numpy()
+    oe = metrics.orth_error(Qh)[0]
+    be = metrics.backward_error(V, Qh, R)
+    print(f"n=2^24: ||I-Q^TQ||_2 = {oe:.3e}, backward error = {be:.3e}")
+    assert oe <= 1e-13
+    assert be <= 1e-14
+
+
+def test_fullsize_first_block_against_oracle(full):
+    V, outs = full
+    _, R = outs[-1]
+    ref = orth.orth_blocks_one_stage(np.asfortranarray(V[:, :W]), W, "randcholqr", Sketch.sparse_sign(64, 8, 0))
+    assert ref.info == 0
+    rd = metrics.rel_diff(R[:W, :W], ref.R)
+    print(f"first block R rel diff {rd:.3e}")
+    assert rd <= max(1e-12, 10 * 10.0 ** E * U)

@@ -1,0 +1,109 @@
+"""HIP two-stage block orthogonalisation (Fig. 6 with RandBCGS2 pre-processing, Fig. 8)
+vs the CPU oracle on the same seeded inputs, through the C ABI.  Tolerances as in
+test_gpu_orth.py (R within max(1e-12, 10 kappa u); orthogonality 1e-13; backward 1e-14)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import metrics, orth  # noqa: E402
+from oracle.sketch import Sketch  # noqa: E402
+from paper_2503_16717_amd import workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def tol_r(e):
+    return max(1e-12, 10.0 * 10.0 ** e * U)
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_16717_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def run(B, ctx, V, w, ppb, reorth=True, k=64, seed=0, dtype=torch.float64, **kw):
+    Vd = B.colmajor_from_numpy(V, "cuda", dtype=dtype)
+    Q, R, st, col = ctx.orth_blocks(Vd, w, two_stage=True, panels_per_big=ppb, reorth=reorth, raise_on_error=False,
+                                    sketch=B.make_sketch("sparse_sign", k, 8, seed), **kw)
+    torch.cuda.synchronize()
+    return Q.double().cpu().numpy(), R, st, col
+
+
+@pytest.mark.parametrize("ppb", [1, 2, 3, 6])
+@pytest.mark.parametrize("e", [4, 10])
+@pytest.mark.parametrize("n", [700, 40000])
+def test_two_stage_matches_oracle(B, ctx, ppb, e, n):
+    w, nb = 6, 6
+    V = wl.glued_blocks(n, nb, w, e)
+    Q, R, st, col = run(B, ctx, V, w, ppb)
+    assert st == B.SKO_OK, (st, col)
+    ref = orth.orth_blocks_two_stage(V, w, ppb, Sketch.sparse_sign(64, 8, 0))
+    assert ref.info == 0
+    assert np.all(np.diag(R) > 0)
+    assert metrics.rel_diff(R, ref.R) <= tol_r(e)
+    assert metrics.orth_error(Q)[0] <= 1e-13
+    assert metrics.backward_error(V, Q, R) <= 1e-14
+    if e <= 6:
+        assert np.max(np.abs(Q - ref.Q)) <= max(1e-12, 100 * 10.0 ** e * U)
+
+
+def test_two_stage_without_reorth_single_big_panel(B, ctx):
+    """One big panel spanning the basis: the second pass (Fig. 5 Line 19) is skipped."""
+    n, w, nb = 30000, 5, 12
+    V = wl.glued_blocks(n, nb, w, 8)
+    Q, R, st, col = run(B, ctx, V, w, 12, reorth=False, k=128)
+    assert st == B.SKO_OK
+    ref = orth.orth_blocks_two_stage(V, w, 12, Sketch.sparse_sign(128, 8, 0), reorth=False)
+    assert metrics.rel_diff(R, ref.R) <= tol_r(8)
+    assert metrics.orth_error(Q)[0] <= 1e-13
+
+
+def test_two_stage_width11(B, ctx):
+    n, w, nb = 20000, 11, 4
+    V = wl.glued_blocks(n, nb, w, 9)
+    Q, R, st, col = run(B, ctx, V, w, 2, k=64)
+    assert st == B.SKO_OK
+    ref = orth.orth_blocks_two_stage(V, w, 2, Sketch.sparse_sign(64, 8, 0))
+    assert metrics.rel_diff(R, ref.R) <= tol_r(9)
+    assert metrics.orth_error(Q)[0] <= 1e-13
+
+
+def test_two_stage_config2_shape_reduced_rows(B, ctx):
+    """Config-2 shape (12 blocks of 6, s_hat = 30 -> 6 blocks per big panel, W = 36) at n = 2^17."""
+    n, w, nb = 1 << 17, 6, 12
+    V = wl.glued_blocks(n, nb, w, 12)
+    Q, R, st, col = run(B, ctx, V, w, 6)
+    assert st == B.SKO_OK
+    ref = orth.orth_blocks_two_stage(V, w, 6, Sketch.sparse_sign(64, 8, 0))
+    assert metrics.rel_diff(R, ref.R) <= tol_r(12)
+    assert metrics.orth_error(Q)[0] <= 1e-13
+    assert metrics.backward_error(V, Q, R) <= 1e-14
+
+
+def test_two_stage_equals_one_stage_single_panel(B, ctx):
+    """s_hat = s: identical operations to one-stage RandCholQR-BCGS2 (oracle: bitwise equal);
+    the GPU paths agree to rounding."""
+    V = wl.glued_blocks(9000, 4, 6, 6)
+    Q2, R2, st2, _ = run(B, ctx, V, 6, 1)
+    Vd = B.colmajor_from_numpy(V, "cuda")
+    Q1, R1, st1, _ = ctx.orth_blocks(Vd, 6, intra="randcholqr", sketch=B.make_sketch("sparse_sign", 64, 8, 0))
+    assert st1 == st2 == B.SKO_OK
+    assert metrics.rel_diff(R2, R1) <= tol_r(6)
+
+
+def test_two_stage_rejects_small_sketch(B, ctx):
+    V = wl.glued_blocks(1000, 6, 6, 2)
+    _, _, st, _ = run(B, ctx, V, 6, 6, k=24)
+    assert st == B.SKO_EINVAL
