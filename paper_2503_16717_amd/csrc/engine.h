@@ -49,7 +49,7 @@ struct Engine {
     // Xsrc for the remaining reduction rows, then the reduce kernel with `small`.
     sko_status reduction(PassKey first, PassArgs a, int rows_total, const void* Xsrc, int64_t ldxs,
                          const void* Qp, int64_t ldqp, SmallArgs small, double scale) {
-        const int rpl = pass_rows_per_launch(W);
+        const int rpl = pass_rows_per_launch(W, first.red);
         PassKey rest{W, f32, first.red, false, 0, false};
         const int G = (rows_total > rpl) ? grid_for({first, rest}) : grid_for({first});
         a.partials = partials;

@@ -98,7 +98,7 @@ sko_status one_stage_block(Engine& e, const BlockBufs& b, int intra, int p, cons
         sm.R = b.R2;
         // later Gram chunks (W > rows per launch) recompute the solve from Vh: re-run the
         // same keyed pass rather than an identity pass, since Qb is not stored.
-        const int rpl = pass_rows_per_launch(W);
+        const int rpl = pass_rows_per_launch(W, RED_GRAM);
         if (W <= rpl) {
             if ((s = e.reduction({W, f32, RED_GRAM, false, 1, false}, a, W, nullptr, 0, nullptr, 0, sm, 1.0)))
                 return s;
@@ -254,7 +254,7 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     if (!o->two_stage && o->intra != SKO_INTRA_RANDCHOLQR && o->intra != SKO_INTRA_CHOLQR2) return SKO_EINVAL;
     if (rand && !sketch_ok(o->sketch, n)) return SKO_EINVAL;
     if (rand && o->sketch.k < w) return SKO_EINVAL;
-    if (w > pass_rows_per_launch(w)) return SKO_EUNSUPPORTED;
+    if (w > pass_rows_per_launch(w, RED_GRAM)) return SKO_EUNSUPPORTED;
     if (o->two_stage) return two_stage_blocks(c, n, nb, w, V, ldv, Q, ldq, R, ldr, o, breakdown_col);
     if ((int64_t)(N - w) * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
 
@@ -306,7 +306,7 @@ sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const voi
     const bool rand = o->intra == SKO_INTRA_RANDCHOLQR;
     if (rand && (!sketch_ok(o->sketch, n) || o->sketch.k < w)) return SKO_EINVAL;
     if ((int64_t)p * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
-    if (w > pass_rows_per_launch(w)) return SKO_EUNSUPPORTED;
+    if (w > pass_rows_per_launch(w, RED_GRAM)) return SKO_EUNSUPPORTED;
     const bool f32 = o->precision == SKO_MIXED_F32;
     const int k = rand ? o->sketch.k : w;
     const int N = p + w;

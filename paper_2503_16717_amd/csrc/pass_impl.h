@@ -1,29 +1,46 @@
 // Row-strip streaming pass kernel template for tall-skinny blocks on gfx950.
 //
-// One workgroup of 256 threads (4 waves of 64) walks strips of 256 consecutive rows
-// (grid-stride over strips).  Phase A gives each thread one row: the block row is
-// loaded with one coalesced 8-byte (or 4-byte) access per column, updated,
-// triangular-solved and written back; the result is staged in LDS column-major.
-// Phase B lets every lane own rows lane, lane+64, ... of the strip while each wave
-// owns a slice of the reduction's output rows, so every tall operand is read from HBM
-// exactly once and the per-lane accumulators stay in registers for the whole sweep.
-// The workgroup's partial sums are combined across lanes with shuffles at the end.
+// A workgroup (4 or 8 waves of 64) walks strips of NT consecutive rows (grid-stride over
+// strips).  Phase A gives each thread one row: the block row is loaded with one coalesced
+// access per column, updated, triangular-solved and written back; the result is staged in
+// LDS column-major (padded leading dimension, so column reads across lanes do not collide
+// in the LDS banks).  Phase B computes the pass's one reduction from the staged strip:
+//
+//  * projection Q^T x: FP64 MFMA (v_mfma_f64_16x16x4) tiles of 16 Q columns.  The waves
+//    split the strip's 16-row groups; per group every lane loads 4 consecutive rows of one
+//    Q column (one 32-byte piece; 16 lanes cover 16 columns, so each 128-byte line is used
+//    whole) and the matching 4 rows of x from LDS, and issues 4 MFMAs per tile.  A 16 x 16
+//    accumulator is 4 doubles per lane, so one launch covers up to 16 * MT columns of Q;
+//    the waves' tiles are summed through LDS once at the end.
+//  * Gram x^T x and the sketches Theta^T x: lanes own strip rows, waves own output rows,
+//    FP64 FMAs into register accumulators.
+//
+// Every tall operand is read from HBM once per pass; partial sums stay in registers for the
+// whole sweep and are written once per workgroup at the end.
 #pragma once
 #include "sko_internal.h"
 
 namespace sko {
 namespace passk {
 
-constexpr int NT = kPassThreads;
-constexpr int NWAVE = NT / 64;
-constexpr int RPL = NT / 64;  // strip rows per lane in phase B
+typedef double double4_t __attribute__((ext_vector_type(4)));
 
-// Reduction rows per wave: about 40 double accumulators (80 VGPRs), and never fewer
-// than needed for the W x W Gram matrix in one launch.
-template <int W>
-constexpr int maxa() {
-    return (40 / W) > (W + NWAVE - 1) / NWAVE ? (40 / W) : (W + NWAVE - 1) / NWAVE;
-}
+// Per-(width, reduction) launch configuration.
+template <int W, int RED>
+struct Cfg {
+    // sketch passes use 8 waves (more output rows per launch) while the strip fits LDS
+    static constexpr bool SK = RED == RED_SKETCH_SPARSE || RED == RED_SKETCH_DENSE;
+    static constexpr int NT = (SK && W <= 12) ? 512 : 256;
+    static constexpr int NWAVE = NT / 64;
+    static constexpr int LDX = NT + 1;  // padded LDS leading dimension of the strip
+    // vector reductions: output rows per wave (accumulators per lane = MAXA * W)
+    static constexpr int MAXA_GRAM = (40 / W) > (W + NWAVE - 1) / NWAVE ? (40 / W) : (W + NWAVE - 1) / NWAVE;
+    static constexpr int MAXA_SK = (64 / W) < 8 ? ((64 / W) < 1 ? 1 : (64 / W)) : 8;
+    static constexpr int MAXA = SK ? MAXA_SK : MAXA_GRAM;
+    // MFMA projection: 16-column tiles accumulated by every wave
+    static constexpr int MT = 8;
+    static constexpr int ROWS = RED == RED_PROJ ? 16 * MT : NWAVE * MAXA;
+};
 
 template <typename T>
 __device__ __forceinline__ double ldv(const T* p) {
@@ -49,12 +66,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <int W, typename T, int RED, bool UPD, int NTRSM, bool WRITE>
-__global__ void __launch_bounds__(NT) pass_kernel(const PassArgs a) {
-    constexpr int MAXA = maxa<W>();
+__global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs a) {
+    using C = Cfg<W, RED>;
+    constexpr int NT = C::NT;
+    constexpr int LDX = C::LDX;
+    constexpr int RPL = NT / 64;
+    constexpr int MAXA = C::MAXA;
+    constexpr int MT = C::MT;
     constexpr bool HAS_RED = RED != RED_NONE;
-    __shared__ double xs[HAS_RED ? W * NT : 1];
+    constexpr bool VEC_RED = HAS_RED && RED != RED_PROJ;
+    __shared__ double xs[HAS_RED ? W * LDX : 1];
     __shared__ uint64_t hs[RED == RED_SKETCH_SPARSE ? NT : 1];
     __shared__ double sR[NTRSM > 0 ? NTRSM * W * W : 1];
+    __shared__ double pred[RED == RED_PROJ ? 4 * 64 * C::NWAVE : 1];  // cross-wave tile sums
     extern __shared__ double sC[];  // UPD coefficients, pu * W doubles (dynamic LDS)
 
     const int tid = threadIdx.x;
@@ -81,15 +105,20 @@ __global__ void __launch_bounds__(NT) pass_kernel(const PassArgs a) {
             for (int c = 0; c < W; ++c) rinv[t * W + c] = 1.0 / sR[t * W * W + c * W + c];
     }
 
-    // Phase-B ownership: this wave accumulates reduction rows [a_lo, a_lo + MAXA).
+    // vector reductions: this wave accumulates output rows [a_lo, a_lo + MAXA)
     const int a_lo = wave * MAXA;
-    double acc[HAS_RED ? MAXA : 1][W];
+    double acc[VEC_RED ? MAXA : 1][W];
 #pragma unroll
-    for (int i = 0; i < (HAS_RED ? MAXA : 1); ++i)
+    for (int i = 0; i < (VEC_RED ? MAXA : 1); ++i)
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[i][c] = 0.0;
+    // MFMA projection accumulators: tile m covers Q columns 16m..16m+15 of this launch
+    double4_t dacc[RED == RED_PROJ ? MT : 1];
+    const int ntiles = (a.red_rows + 15) / 16;
+#pragma unroll
+    for (int m = 0; m < (RED == RED_PROJ ? MT : 1); ++m) dacc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
 
-    // Sparse sketch: slot block t and slot j of each owned reduction row (wave-uniform).
+    // Sparse sketch: slot block t and slot j of each owned output row (wave-uniform).
     int sk_shift[RED == RED_SKETCH_SPARSE ? MAXA : 1];
     int sk_slot[RED == RED_SKETCH_SPARSE ? MAXA : 1];
     int sk_B = 1;
@@ -165,70 +194,120 @@ __global__ void __launch_bounds__(NT) pass_kernel(const PassArgs a) {
             }
             if constexpr (HAS_RED) {
 #pragma unroll
-                for (int c = 0; c < W; ++c) xs[c * NT + tid] = x[c];
+                for (int c = 0; c < W; ++c) xs[c * LDX + tid] = x[c];
             }
         }
         if constexpr (HAS_RED) {
             __syncthreads();
-            // ---------------- phase B: lanes over rows, waves over output rows ----------------
+            if constexpr (RED == RED_PROJ) {
+                // ---------------- phase B, MFMA projection ----------------
+                const int g = lane >> 4, ci = lane & 15;
+                const T* Qp = static_cast<const T*>(a.Qp);
+                // 32-byte row pieces can be read as two 16-byte vectors when aligned
+                const bool vec = sizeof(T) == 8 && (a.ldqp % 4) == 0 && ((uintptr_t)Qp % 32) == 0;
+                for (int gam = wave; gam < NT / 16; gam += C::NWAVE) {
+                    const int r0 = gam * 16 + 4 * g;  // strip-local rows r0..r0+3 for this lane
+                    const bool full = base + r0 + 3 < n;
+                    double bv[4];
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                const int rr = r * 64 + lane;
-                const int64_t row = base + rr;
-                double x[W];
+                    for (int u = 0; u < 4; ++u) bv[u] = (ci < W) ? xs[ci * LDX + r0 + u] : 0.0;
 #pragma unroll
-                for (int c = 0; c < W; ++c) x[c] = xs[c * NT + rr];
-                if constexpr (RED == RED_PROJ) {
-                    const T* Qp = static_cast<const T*>(a.Qp) + row;
-                    double q[MAXA];
+                    for (int m = 0; m < MT; ++m) {
+                        if (m < ntiles) {
+                            const int col = 16 * m + ci;
+                            double av[4] = {0.0, 0.0, 0.0, 0.0};
+                            if (col < a.red_rows) {
+                                const T* q = Qp + (int64_t)col * a.ldqp + base + r0;
+                                if (vec && full) {
+                                    const double2 v0 = *reinterpret_cast<const double2*>(q);
+                                    const double2 v1 = *reinterpret_cast<const double2*>(q + 2);
+                                    av[0] = v0.x;
+                                    av[1] = v0.y;
+                                    av[2] = v1.x;
+                                    av[3] = v1.y;
+                                } else {
 #pragma unroll
-                    for (int i = 0; i < MAXA; ++i) {
-                        const int al = a_lo + i;
-                        q[i] = (al < a.red_rows && row < n) ? ldv(Qp + (int64_t)al * a.ldqp) : 0.0;
-                    }
+                                    for (int u = 0; u < 4; ++u) av[u] = (base + r0 + u < n) ? ldv(q + u) : 0.0;
+                                }
+                            }
 #pragma unroll
-                    for (int i = 0; i < MAXA; ++i)
-#pragma unroll
-                        for (int c = 0; c < W; ++c) acc[i][c] += q[i] * x[c];
-                } else if constexpr (RED == RED_GRAM) {
-#pragma unroll
-                    for (int i = 0; i < MAXA; ++i) {
-                        const int al = a_lo + i;
-                        if (al < a.red_rows) {
-                            const double xa = xs[(a.red_row0 + al) * NT + rr];
-#pragma unroll
-                            for (int c = 0; c < W; ++c) acc[i][c] += xa * x[c];
+                            for (int u = 0; u < 4; ++u)
+                                dacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], dacc[m], 0, 0, 0);
                         }
                     }
-                } else if constexpr (RED == RED_SKETCH_SPARSE) {
-                    const uint64_t h = hs[rr];
+                }
+            } else {
+                // ---------------- phase B, lanes over rows, waves over output rows ----------------
+#pragma unroll 2
+                for (int r = 0; r < RPL; ++r) {
+                    const int rr = r * 64 + lane;
+                    const int64_t row = base + rr;
+                    double x[W];
 #pragma unroll
-                    for (int i = 0; i < MAXA; ++i) {
-                        const unsigned b = (unsigned)(h >> sk_shift[i]) & 0xffu;
-                        const int slot = (int)(((b >> 1) * (unsigned)sk_B) >> 7);
-                        const double coef = (slot == sk_slot[i]) ? ((b & 1u) ? -1.0 : 1.0) : 0.0;
+                    for (int c = 0; c < W; ++c) x[c] = xs[c * LDX + rr];
+                    if constexpr (RED == RED_GRAM) {
 #pragma unroll
-                        for (int c = 0; c < W; ++c) acc[i][c] = fma(coef, x[c], acc[i][c]);
+                        for (int i = 0; i < MAXA; ++i) {
+                            const int al = a_lo + i;
+                            if (al < a.red_rows) {
+                                const double xa = xs[(a.red_row0 + al) * LDX + rr];
+#pragma unroll
+                                for (int c = 0; c < W; ++c) acc[i][c] += xa * x[c];
+                            }
+                        }
+                    } else if constexpr (RED == RED_SKETCH_SPARSE) {
+                        const uint64_t h = hs[rr];
+#pragma unroll
+                        for (int i = 0; i < MAXA; ++i) {
+                            const unsigned b = (unsigned)(h >> sk_shift[i]) & 0xffu;
+                            const int slot = (int)(((b >> 1) * (unsigned)sk_B) >> 7);
+                            const double coef = (slot == sk_slot[i]) ? ((b & 1u) ? -1.0 : 1.0) : 0.0;
+#pragma unroll
+                            for (int c = 0; c < W; ++c) acc[i][c] = fma(coef, x[c], acc[i][c]);
+                        }
+                    } else if constexpr (RED == RED_SKETCH_DENSE) {
+                        const double* th = a.theta + row;
+                        double tv[MAXA];
+#pragma unroll
+                        for (int i = 0; i < MAXA; ++i) {
+                            const int al = a_lo + i;
+                            tv[i] = (al < a.red_rows && row < n) ? th[(int64_t)al * a.ldtheta] : 0.0;
+                        }
+#pragma unroll
+                        for (int i = 0; i < MAXA; ++i)
+#pragma unroll
+                            for (int c = 0; c < W; ++c) acc[i][c] += tv[i] * x[c];
                     }
-                } else if constexpr (RED == RED_SKETCH_DENSE) {
-                    const double* th = a.theta + row;
-                    double tv[MAXA];
-#pragma unroll
-                    for (int i = 0; i < MAXA; ++i) {
-                        const int al = a_lo + i;
-                        tv[i] = (al < a.red_rows && row < n) ? th[(int64_t)al * a.ldtheta] : 0.0;
-                    }
-#pragma unroll
-                    for (int i = 0; i < MAXA; ++i)
-#pragma unroll
-                        for (int c = 0; c < W; ++c) acc[i][c] += tv[i] * x[c];
                 }
             }
             __syncthreads();
         }
     }
 
-    if constexpr (HAS_RED) {
+    if constexpr (RED == RED_PROJ) {
+        // v_mfma_f64_16x16x4 output layout (measured on gfx950): D[i][j] of a tile sits in
+        // lane j + 16 * (i % 4), element i / 4.  The waves' tiles are summed through LDS in
+        // wave order.
+        double* out = a.partials + (int64_t)blockIdx.x * a.part_stride;
+        const int j = lane & 15;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if (m >= ntiles) break;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pred[(wave * 4 + r) * 64 + lane] = dacc[m][r];
+            __syncthreads();
+            if (wave == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double v = 0.0;
+                    for (int w2 = 0; w2 < C::NWAVE; ++w2) v += pred[(w2 * 4 + r) * 64 + lane];
+                    const int col = 16 * m + (lane >> 4) + 4 * r;
+                    if (col < a.red_rows && j < W) out[(a.red_row0 + col) + (int64_t)j * a.part_rows_total] = v;
+                }
+            }
+            __syncthreads();
+        }
+    } else if constexpr (HAS_RED) {
         double* out = a.partials + (int64_t)blockIdx.x * a.part_stride;
 #pragma unroll
         for (int i = 0; i < MAXA; ++i) {
@@ -274,24 +353,51 @@ KernelPtr select_w(const PassKey& k) {
     return nullptr;
 }
 
+template <int W>
+int rows_w(int red) {
+    switch (red) {
+        case RED_PROJ: return Cfg<W, RED_PROJ>::ROWS;
+        case RED_GRAM: return Cfg<W, RED_GRAM>::ROWS;
+        case RED_SKETCH_SPARSE: return Cfg<W, RED_SKETCH_SPARSE>::ROWS;
+        case RED_SKETCH_DENSE: return Cfg<W, RED_SKETCH_DENSE>::ROWS;
+        default: return 0;
+    }
+}
+
+template <int W>
+int threads_w(int red) {
+    switch (red) {
+        case RED_SKETCH_SPARSE: return Cfg<W, RED_SKETCH_SPARSE>::NT;
+        case RED_SKETCH_DENSE: return Cfg<W, RED_SKETCH_DENSE>::NT;
+        case RED_PROJ: return Cfg<W, RED_PROJ>::NT;
+        case RED_GRAM: return Cfg<W, RED_GRAM>::NT;
+        default: return Cfg<W, RED_NONE>::NT;
+    }
+}
+
 }  // namespace passk
 
 // Per-width selectors, one translation unit each (pass_wNN.hip).
-passk::KernelPtr select_pass_w1(const PassKey& k);
-passk::KernelPtr select_pass_w2(const PassKey& k);
-passk::KernelPtr select_pass_w3(const PassKey& k);
-passk::KernelPtr select_pass_w4(const PassKey& k);
-passk::KernelPtr select_pass_w5(const PassKey& k);
-passk::KernelPtr select_pass_w6(const PassKey& k);
-passk::KernelPtr select_pass_w7(const PassKey& k);
-passk::KernelPtr select_pass_w8(const PassKey& k);
-passk::KernelPtr select_pass_w9(const PassKey& k);
-passk::KernelPtr select_pass_w10(const PassKey& k);
-passk::KernelPtr select_pass_w11(const PassKey& k);
-passk::KernelPtr select_pass_w12(const PassKey& k);
-passk::KernelPtr select_pass_w13(const PassKey& k);
-passk::KernelPtr select_pass_w14(const PassKey& k);
-passk::KernelPtr select_pass_w15(const PassKey& k);
-passk::KernelPtr select_pass_w16(const PassKey& k);
+struct PassSel {
+    passk::KernelPtr fn;
+    int threads;  // workgroup size (= strip rows)
+    int rows;     // reduction rows one launch can produce
+};
+PassSel select_pass_w1(const PassKey& k);
+PassSel select_pass_w2(const PassKey& k);
+PassSel select_pass_w3(const PassKey& k);
+PassSel select_pass_w4(const PassKey& k);
+PassSel select_pass_w5(const PassKey& k);
+PassSel select_pass_w6(const PassKey& k);
+PassSel select_pass_w7(const PassKey& k);
+PassSel select_pass_w8(const PassKey& k);
+PassSel select_pass_w9(const PassKey& k);
+PassSel select_pass_w10(const PassKey& k);
+PassSel select_pass_w11(const PassKey& k);
+PassSel select_pass_w12(const PassKey& k);
+PassSel select_pass_w13(const PassKey& k);
+PassSel select_pass_w14(const PassKey& k);
+PassSel select_pass_w15(const PassKey& k);
+PassSel select_pass_w16(const PassKey& k);
 
 }  // namespace sko

@@ -5,9 +5,7 @@
 namespace sko {
 namespace {
 
-using passk::KernelPtr;
-
-KernelPtr select_kernel(const PassKey& k) {
+PassSel select_kernel(const PassKey& k) {
     switch (k.W) {
         case 1: return select_pass_w1(k);
         case 2: return select_pass_w2(k);
@@ -25,34 +23,28 @@ KernelPtr select_kernel(const PassKey& k) {
         case 14: return select_pass_w14(k);
         case 15: return select_pass_w15(k);
         case 16: return select_pass_w16(k);
-        default: return nullptr;
+        default: return PassSel{nullptr, 0, 0};
     }
 }
-
-constexpr int NT = kPassThreads;
-constexpr int NWAVE = NT / 64;
 
 }  // namespace
 
-int pass_rows_per_launch(int W) {
-    switch (W) {
-#define SKO_W(w) case w: return NWAVE * passk::maxa<w>();
-        SKO_W(1) SKO_W(2) SKO_W(3) SKO_W(4) SKO_W(5) SKO_W(6) SKO_W(7) SKO_W(8)
-        SKO_W(9) SKO_W(10) SKO_W(11) SKO_W(12) SKO_W(13) SKO_W(14) SKO_W(15) SKO_W(16)
-#undef SKO_W
-        default: return 0;
-    }
+int pass_rows_per_launch(int W, int red) {
+    PassKey k{W, false, red, false, 0, false};
+    return select_kernel(k).rows;
 }
 
+int pass_strip_rows(const PassKey& key) { return select_kernel(key).threads; }
+
 int pass_grid_cap(const PassKey& key) {
-    KernelPtr f = select_kernel(key);
-    if (!f) return 0;
+    PassSel s = select_kernel(key);
+    if (!s.fn) return 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(f), NT, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(s.fn), s.threads, 0) !=
         hipSuccess)
         return 0;
     if (per_cu < 1) per_cu = 1;
@@ -60,13 +52,13 @@ int pass_grid_cap(const PassKey& key) {
 }
 
 hipError_t launch_pass(const PassKey& key, const PassArgs& args, int grid, hipStream_t stream) {
-    KernelPtr f = select_kernel(key);
-    if (!f) return hipErrorInvalidValue;
+    PassSel s = select_kernel(key);
+    if (!s.fn) return hipErrorInvalidValue;
     if (key.upd && args.pu * key.W > kMaxUpdCoef) return hipErrorInvalidValue;
-    if (key.red != RED_NONE && args.red_rows > pass_rows_per_launch(key.W)) return hipErrorInvalidValue;
+    if (key.red != RED_NONE && args.red_rows > s.rows) return hipErrorInvalidValue;
     if (grid < 1) return hipErrorInvalidValue;
     const size_t lds = key.upd ? sizeof(double) * (size_t)args.pu * key.W : 0;
-    hipLaunchKernelGGL(f, dim3(grid), dim3(NT), lds, stream, args);
+    hipLaunchKernelGGL(s.fn, dim3(grid), dim3(s.threads), lds, stream, args);
     return hipGetLastError();
 }
 

@@ -2,7 +2,11 @@
 #include "pass_impl.h"
 
 namespace sko {
-passk::KernelPtr select_pass_w10(const PassKey& k) {
-    return k.f32 ? passk::select_w<10, float>(k) : passk::select_w<10, double>(k);
+PassSel select_pass_w10(const PassKey& k) {
+    PassSel s;
+    s.fn = k.f32 ? passk::select_w<10, float>(k) : passk::select_w<10, double>(k);
+    s.threads = passk::threads_w<10>(k.red);
+    s.rows = passk::rows_w<10>(k.red);
+    return s;
 }
 }  // namespace sko

@@ -2,7 +2,11 @@
 #include "pass_impl.h"
 
 namespace sko {
-passk::KernelPtr select_pass_w15(const PassKey& k) {
-    return k.f32 ? passk::select_w<15, float>(k) : passk::select_w<15, double>(k);
+PassSel select_pass_w15(const PassKey& k) {
+    PassSel s;
+    s.fn = k.f32 ? passk::select_w<15, float>(k) : passk::select_w<15, double>(k);
+    s.threads = passk::threads_w<15>(k.red);
+    s.rows = passk::rows_w<15>(k.red);
+    return s;
 }
 }  // namespace sko

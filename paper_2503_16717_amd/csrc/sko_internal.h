@@ -71,8 +71,10 @@ struct PassKey {
 
 // Launch one pass over all n rows with `grid` workgroups (grid <= pass_grid_cap()).
 hipError_t launch_pass(const PassKey& key, const PassArgs& args, int grid, hipStream_t stream);
-// Reduction rows one launch can produce for panel width W (rows per wave * waves).
-int pass_rows_per_launch(int W);
+// Reduction rows one launch of reduction kind `red` can produce for panel width W.
+int pass_rows_per_launch(int W, int red);
+// Rows per strip (= threads per workgroup) of a pass variant.
+int pass_strip_rows(const PassKey& key);
 // Largest useful grid for a pass variant on the current device (resident workgroups).
 int pass_grid_cap(const PassKey& key);
 constexpr int kPassThreads = 256;
