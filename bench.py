@@ -67,6 +67,48 @@ def build_inputs(n: int, torch, wl):
     return Vd
 
 
+def copy_ceiling(torch, nbytes: int = 1 << 31, reps: int = 20) -> float:
+    """Device-to-device copy bandwidth (read + write bytes / time) of a plain copy kernel."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+PASS_SOURCE = os.path.join(ROOT, "paper_2503_16717_amd", "csrc", "pass_impl.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass_kernels.txt")
+
+
+def pass_source_digest() -> str:
+    import hashlib
+    return hashlib.sha256(open(PASS_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when it is missing or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest = pass_source_digest()
+    for line in open(TRAFFIC_FILE):
+        if not line.startswith("|") or "kernel" in line or "---" in line:
+            continue
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 5 and cells[0] == kernel and cells[4] == digest:
+            return float(cells[3])
+    return None
+
+
 def cpu_baseline(n_sample: int):
     """The FP64 oracle, untuned, on the first n_sample rows' worth of the same recipe."""
     from oracle import orth
@@ -96,7 +138,19 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 20)
     ap.add_argument("--n", type=int, default=N_ROWS, help="rows (default 2^24)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB five times (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read_per_launch": a.numel() * 8,
+                          "copy_calibration_bytes_written_per_launch": a.numel() * 8, "launches": 5}))
+        return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the path's multi-GPU sharding is "
                                    "design-only (see DESIGN.md)", "n_gpus": args.gpus}))
@@ -147,8 +201,9 @@ def main() -> int:
     avg_ms = dom["total_ms"] / dom["launches"]
     avg_bytes = dom["bytes"] / dom["launches"]
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom["name"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom["name"], "launches_per_step": dom["launches"] / args.steps,
                 "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": avg_bytes}
     kernels = [{"name": s["name"], "ms_per_step": round(s["total_ms"] / args.steps, 4),
@@ -165,8 +220,11 @@ def main() -> int:
         log("diag: " + " ".join(f"{v:.3e}" for v in np.diag(R)))
         return 3
 
+    ceiling = copy_ceiling(torch)
+    log(f"copy-kernel ceiling {ceiling:.0f} GB/s")
     extra = {"kernels_top": kernels, "event_ms_per_step": round(event_ms, 3),
-             "alg_bytes_per_step": abytes}
+             "alg_bytes_per_step": abytes, "copy_ceiling_GBps": round(ceiling, 1),
+             "pct_of_copy_ceiling": round(100 * value / ceiling, 2)}
     ctx.close()
 
     cpu = None

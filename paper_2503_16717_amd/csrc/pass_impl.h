@@ -256,12 +256,19 @@ __global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs 
                             }
                         }
                     } else if constexpr (RED == RED_SKETCH_SPARSE) {
+                        // decode the row's slot and sign once per hash block this wave covers
+                        // (sk_shift is wave-uniform and non-decreasing in i)
                         const uint64_t h = hs[rr];
+                        int slot = -2;
+                        double sgn = 0.0;
 #pragma unroll
                         for (int i = 0; i < MAXA; ++i) {
-                            const unsigned b = (unsigned)(h >> sk_shift[i]) & 0xffu;
-                            const int slot = (int)(((b >> 1) * (unsigned)sk_B) >> 7);
-                            const double coef = (slot == sk_slot[i]) ? ((b & 1u) ? -1.0 : 1.0) : 0.0;
+                            if (i == 0 || sk_shift[i] != sk_shift[i - 1]) {
+                                const unsigned b = (unsigned)(h >> sk_shift[i]) & 0xffu;
+                                slot = (int)(((b >> 1) * (unsigned)sk_B) >> 7);
+                                sgn = (b & 1u) ? -1.0 : 1.0;
+                            }
+                            const double coef = (slot == sk_slot[i]) ? sgn : 0.0;
 #pragma unroll
                             for (int c = 0; c < W; ++c) acc[i][c] = fma(coef, x[c], acc[i][c]);
                         }
@@ -337,6 +344,7 @@ KernelPtr select_w(const PassKey& k) {
         if (r == RED_SKETCH_DENSE) return &pass_kernel<W, T, RED_SKETCH_DENSE, false, 0, false>;
     }
     if (u && t == 0 && wr) {
+        if (r == RED_NONE) return &pass_kernel<W, T, RED_NONE, true, 0, true>;
         if (r == RED_GRAM) return &pass_kernel<W, T, RED_GRAM, true, 0, true>;
         if (r == RED_SKETCH_SPARSE) return &pass_kernel<W, T, RED_SKETCH_SPARSE, true, 0, true>;
         if (r == RED_SKETCH_DENSE) return &pass_kernel<W, T, RED_SKETCH_DENSE, true, 0, true>;
