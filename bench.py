@@ -13,10 +13,12 @@ count each tall operand once per pass of the pass schedule (block j with p = 6j
 previous columns: (4p + 10w) columns of 8 bytes per row; first block 6w).
 
 Also reported: roofline of the dominant kernel (event-timed launches over the timed
-region), the two-stage variant (s_hat = 30) when the library supports it, and the
-CPU oracle timed on a bounded sample of the same workload.
+region), the two-stage variant (s_hat = 30), the CPU oracle timed on a bounded sample of
+the same workload, and under "gmres" the time to a 1e-10 relative residual of the
+restarted s-step solver on the 100x100 Laplacian, the 192^3 convection-diffusion problem
+(FP64 and mixed) and 256 independent convection-diffusion systems (FP64 and mixed).
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu-baseline] [--skip-gmres]
 """
 from __future__ import annotations
 
@@ -42,6 +44,109 @@ def alg_bytes_one_stage(n: int, nb: int, w: int, eb: int = 8) -> float:
         p = j * w
         cols += (4 * p + 10 * w) if p > 0 else 6 * w
     return float(cols) * n * eb
+
+
+def alg_bytes_two_stage(n: int, nb: int, w: int, ppb: int, eb: int = 8) -> float:
+    """Pass schedule of the two-stage scheme (each tall operand once per pass)."""
+    Wb = ppb * w
+    cols = 0
+    for big in range(nb // ppb):
+        p = big * Wb
+        for i in range(ppb):
+            if p > 0:
+                cols += p + w          # C_i = Q_old^T V_i
+                cols += p + 2 * w      # V_hat_i = V_i - Q_old C_i (written) + sketch
+            else:
+                cols += w              # sketch of V_i
+            cols += (i * w + w) + w    # forward substitution, written
+        cols += Wb + 2 * Wb            # Gram of Q_bar, Q_hat = Q_bar R^{-1}
+        if p > 0:
+            cols += (p + Wb) + (p + 2 * Wb)  # C_2 = Q_old^T Q_hat, V_bar = Q_hat - Q_old C_2
+        cols += Wb + 2 * Wb            # Gram of V_bar, Q_P = V_bar R^{-1}
+    return float(cols) * n * eb
+
+
+def gmres_suite(B, torch, wl, args) -> dict:
+    """Time to relative residual 1e-10 (explicit, FP64) for the solver configurations."""
+    import numpy as np
+    out = {}
+    ctx = B.Context(0)
+
+    def solve(A, b, **kw):
+        Ad = B.csr_to_device(A)
+        bt = torch.from_numpy(np.asarray(b, dtype=np.float64)).cuda()
+        # the first solve sizes the workspace; the second is the one reported
+        x, info, st = ctx.gmres(Ad, bt, **kw)
+        torch.cuda.synchronize()
+        x, info, st = ctx.gmres(Ad, bt, **kw)
+        torch.cuda.synchronize()
+        return {"status": st, "converged": info["converged"], "iters": info["iters"],
+                "restarts": info["restarts"], "relres": info["relres"],
+                "time_s": round(info["t_total"], 5)}
+
+    # config 1: 2-D Laplacian 100x100, one-stage RandCholQR-BCGS2, Gaussian k = 24, s = 5, m = 30
+    A1 = wl.laplacian_2d(100)
+    th = B.colmajor_from_numpy(wl.gaussian_theta(A1.n, 24, 0), "cuda")
+    out["config1_fp64"] = solve(A1, wl.rhs_uniform(A1.n, 1), s=5, m=30, tol=1e-10,
+                                sketch=B.make_sketch("gaussian", theta=th))
+    log(f"config1: {out['config1_fp64']}")
+    # config 5: 3-D convection-diffusion 192^3, wind (10,20,30), Jacobi, two-stage s=10, s_hat=m=60, k=128
+    log("config5: assembling 192^3 convection-diffusion")
+    A5 = wl.convdiff_3d(192, (10.0, 20.0, 30.0))
+    b5 = np.ones(A5.n)
+    sk5 = B.make_sketch("sparse_sign", 128, 8, 0)
+    for prec in ("f64", "mixed"):
+        out[f"config5_{prec}"] = solve(A5, b5, s=10, m=60, shat=60, two_stage=True, precond=1, tol=1e-10,
+                                       precision=prec, sketch=sk5)
+        log(f"config5 {prec}: {out[f'config5_{prec}']}")
+    del A5
+    # config 4: 256 independent 2-D convection-diffusion systems, two-stage s=5, s_hat=20, m=40, k=48
+    specs = wl.batched_convdiff_specs(256)
+    As, bs, xs, keep = [], [], [], []
+    for sp in specs:
+        A = wl.convdiff_2d(sp["N"], sp["bx"], sp["by"])
+        Ad, k = B.csr_to_device(A)
+        As.append(Ad)
+        keep.append(k)
+        bt = torch.from_numpy(wl.batched_rhs(A.n, sp["rhs_seed"])).cuda()
+        bs.append(bt)
+        xs.append(torch.zeros_like(bt))
+    for prec in ("f64", "mixed"):
+        for x in xs:
+            x.zero_()
+        opts = B.gmres_opts(s=5, m=40, shat=20, two_stage=True, tol=1e-10, precision=prec,
+                            sketch=B.make_sketch("sparse_sign", 48, 8, 0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, infos = ctx.sko_gmres_batched(As, [b.data_ptr() for b in bs], [x.data_ptr() for x in xs], opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"config4_{prec}"] = {"status": st, "time_s": round(dt, 4),
+                                  "converged": int(sum(i.converged for i in infos)),
+                                  "iters_total": int(sum(i.iters for i in infos)), "systems": len(infos)}
+        log(f"config4 {prec}: {out[f'config4_{prec}']}")
+    # the same 256 systems solved one by one (FP64), the plain path the batched form replaces
+    for x in xs:
+        x.zero_()
+    opts = B.gmres_opts(s=5, m=40, shat=20, two_stage=True, tol=1e-10,
+                        sketch=B.make_sketch("sparse_sign", 48, 8, 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    conv = iters = 0
+    for i, (Ad, b, x) in enumerate(zip(As, bs, xs)):
+        oi = B.gmres_opts(s=5, m=40, shat=20, two_stage=True, tol=1e-10,
+                          sketch=B.make_sketch("sparse_sign", 48, 8, i))
+        st, inf = ctx.sko_gmres(Ad, b.data_ptr(), x.data_ptr(), oi)
+        conv += inf.converged
+        iters += inf.iters
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["config4_one_by_one_f64"] = {"time_s": round(dt, 4), "converged": int(conv), "iters_total": int(iters),
+                                     "systems": len(As)}
+    log(f"config4 one-by-one f64: {out['config4_one_by_one_f64']}")
+    del opts
+    ctx.close()
+    return out
 
 
 def log(msg: str) -> None:
@@ -138,6 +243,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 20)
     ap.add_argument("--n", type=int, default=N_ROWS, help="rows (default 2^24)")
+    ap.add_argument("--skip-gmres", action="store_true", help="skip the GMRES time-to-solution runs")
+    ap.add_argument("--skip-two-stage", action="store_true", help="skip the two-stage orthogonalisation run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (counter calibration)")
     args = ap.parse_args()
@@ -220,18 +327,36 @@ def main() -> int:
         log("diag: " + " ".join(f"{v:.3e}" for v in np.diag(R)))
         return 3
 
-    ceiling = copy_ceiling(torch)
-    log(f"copy-kernel ceiling {ceiling:.0f} GB/s")
     extra = {"kernels_top": kernels, "event_ms_per_step": round(event_ms, 3),
-             "alg_bytes_per_step": abytes, "copy_ceiling_GBps": round(ceiling, 1),
-             "pct_of_copy_ceiling": round(100 * value / ceiling, 2)}
+             "alg_bytes_per_step": abytes}
+
+    if not args.skip_two_stage:
+        # two-stage variant of the same workload (s_hat = 30: 6 blocks per big panel, W = 36)
+        opts2 = B.orth_opts(two_stage=True, panels_per_big=6, reorth=True,
+                            sketch=B.make_sketch("sparse_sign", SK_K, SK_ZETA, SK_SEED))
+        for _ in range(args.warmup):
+            step(opts2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(opts2)
+        torch.cuda.synchronize()
+        ms2 = (time.perf_counter() - t0) / args.steps * 1e3
+        ab2 = alg_bytes_two_stage(n, NB, W, 6)
+        extra["two_stage"] = {"ms_per_step": round(ms2, 4), "GBps": round(ab2 / (ms2 * 1e-3) / 1e9, 2),
+                              "alg_bytes_per_step": ab2, "s_hat": 30, "big_panel_width": 36}
+        log(f"two-stage: {ms2:.3f} ms/step")
+    extra["copy_ceiling_GBps"] = round(copy_ceiling(torch), 1)
     ctx.close()
+    del Qd
+    if not args.skip_gmres:
+        del Vd
+        torch.cuda.empty_cache()
+        extra["gmres"] = gmres_suite(B, torch, wl, args)
 
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline on {args.cpu_sample_rows} rows")
-        del Vd, Qd
-        torch.cuda.empty_cache()
         cpu = cpu_baseline(args.cpu_sample_rows)
 
     line = {

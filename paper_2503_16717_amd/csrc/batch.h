@@ -1,0 +1,84 @@
+// Batched launches: one kernel launch serves every active system of a batch of
+// independent solves (blockIdx.y selects the system).
+//
+// The host builds each launch's arguments once, for a template system (system 0's
+// addresses).  The kernel moves every pointer that lies in one of the template's regions
+// to the same place in its own system's region:
+//   * the Krylov basis (ld0 x columns, element size eb): same column and row of the
+//     system's basis, whose leading dimension and row count differ per system;
+//   * the small workspace, the partial sums and the reduction counters: equal-sized
+//     regions laid out one after another, so the offset is sys * region size.
+// Per-system scalars (row count, CSR operator, b, x, D^{-1}, sketch seed) come from the
+// system table.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sko {
+
+struct BatchSys {
+    int64_t n;               // rows
+    int64_t ld;              // basis leading dimension
+    int64_t nnz;
+    char* Q;                 // basis
+    const int32_t* rowptr;
+    const int32_t* colind;
+    const double* val;       // A (FP64)
+    const void* val_op;      // matrix-powers operator values (A D^{-1}, double or float)
+    const double* b;
+    double* x;
+    const double* dinv;      // Jacobi D^{-1} or null
+    uint64_t seed;           // sparse-sign sketch seed
+    int32_t kupd;            // basis vectors in the solution update at a cycle end
+    int32_t pad_;
+};
+
+struct BatchReloc {
+    const BatchSys* sys;     // system table (device)
+    const int* active;       // blockIdx.y -> system index (device)
+    int nact;                // active systems = gridDim.y
+    int eb;                  // basis element size (4 or 8)
+    const char* q0;          // template basis and its extent
+    int64_t q0_bytes;
+    int64_t ld0;
+    const char* ws0;         // template small workspace; system i's starts at ws0 + i * ws_bytes
+    int64_t ws_bytes;
+    const char* part0;       // template partial sums
+    int64_t part_bytes;
+    const char* cnt0;        // template reduction counters
+    int64_t cnt_bytes;
+};
+
+#ifdef __HIPCC__
+// System served by this workgroup.
+__device__ __forceinline__ int batch_system(const BatchReloc& br) { return br.active[blockIdx.y]; }
+
+template <typename P>
+__device__ __forceinline__ P* batch_ptr(const BatchReloc& br, int sys, const BatchSys& d, P* p) {
+    if (!p) return p;
+    const char* c = reinterpret_cast<const char*>(p);
+    int64_t o = c - br.q0;
+    if (o >= 0 && o < br.q0_bytes) {
+        const int64_t e = o / br.eb;
+        const int64_t col = e / br.ld0, row = e - col * br.ld0;
+        return reinterpret_cast<P*>(d.Q + (col * d.ld + row) * br.eb);
+    }
+    o = c - br.ws0;
+    if (o >= 0 && o < br.ws_bytes) return reinterpret_cast<P*>(const_cast<char*>(c) + (int64_t)sys * br.ws_bytes);
+    o = c - br.part0;
+    if (o >= 0 && o < br.part_bytes)
+        return reinterpret_cast<P*>(const_cast<char*>(c) + (int64_t)sys * br.part_bytes);
+    o = c - br.cnt0;
+    if (o >= 0 && o < br.cnt_bytes) return reinterpret_cast<P*>(const_cast<char*>(c) + (int64_t)sys * br.cnt_bytes);
+    return p;
+}
+
+// A tall leading dimension of the template becomes the system's.
+__device__ __forceinline__ int64_t batch_ld(const BatchReloc& br, const BatchSys& d, int64_t ld) {
+    return ld == br.ld0 ? d.ld : ld;
+}
+#endif
+
+}  // namespace sko

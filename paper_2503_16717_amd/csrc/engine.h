@@ -8,6 +8,7 @@
 #include <initializer_list>
 #include <string>
 
+#include "batch.h"
 #include "context.h"
 
 namespace sko {
@@ -33,10 +34,16 @@ struct Engine {
     int gmax = 0;
     int* status = nullptr;
     unsigned* counter = nullptr;
+    // Batched mode: every launch serves the active systems of `br` (template addresses are
+    // system 0's); n is the largest system's row count and rows_bytes the active systems'
+    // total, for the byte accounting.
+    const BatchReloc* br = nullptr;
+    double rows_bytes = 0.0;
 
     Engine(sko_ctx c_, int64_t n_, int W_, bool f32_, const sko_sketch& sk_)
         : c(c_), st(c_->stream), n(n_), W(W_), f32(f32_), sk(sk_) {
         nstrips = (n + kPassThreads - 1) / kPassThreads;
+        rows_bytes = (double)n;
     }
 
     int grid_for(std::initializer_list<PassKey> keys) const {
@@ -50,7 +57,8 @@ struct Engine {
     sko_status reduction(PassKey first, PassArgs a, int rows_total, const void* Xsrc, int64_t ldxs,
                          const void* Qp, int64_t ldqp, SmallArgs small, double scale) {
         const int rpl = pass_rows_per_launch(W, first.red);
-        PassKey rest{W, f32, first.red, false, 0, false};
+        if (first.red == RED_PROJ) first.tiles = (std::min(rpl, rows_total) + 15) / 16;
+        PassKey rest{W, f32, first.red, false, 0, false, first.tiles};
         const int G = (rows_total > rpl) ? grid_for({first, rest}) : grid_for({first});
         a.partials = partials;
         a.part_stride = part_stride;
@@ -77,7 +85,7 @@ struct Engine {
                 b.ldtheta = sk.ld_theta;
             }
             const int ev = c->prof.begin(pass_name(key), pass_bytes(key, b), st);
-            SKO_HIP(launch_pass(key, b, G, st));
+            SKO_HIP(launch_pass(key, b, G, st, br));
             c->prof.end(ev, st);
         }
         ReduceArgs ra{};
@@ -94,7 +102,7 @@ struct Engine {
         ra.small = small;
         ra.small.status = status;
         const int ev = c->prof.begin("reduce+small", 8.0 * G * ra.count, st);
-        SKO_HIP(launch_reduce(ra, st));
+        SKO_HIP(launch_reduce(ra, st, br));
         c->prof.end(ev, st);
         return SKO_OK;
     }
@@ -103,12 +111,11 @@ struct Engine {
     // handed to `small`.
     sko_status gemm_reduction(const void* A, int64_t lda, int ma, const void* B, int64_t ldb, int nbc,
                               SmallArgs small, int64_t ldo) {
-        const int64_t ns32 = (n + 31) / 32;
-        const int G = (int)std::max<int64_t>(1, std::min<int64_t>(ns32, skinny_gemm_grid_cap()));
+        const int G = gemm_grid();
         const int ev = c->prof.begin(std::string("wide_gemm_tn ") + (A == B ? "gram" : "proj") + " f" +
                                          (f32 ? "32" : "64"),
-                                     (double)n * (A == B ? ma : ma + nbc) * (f32 ? 4.0 : 8.0), st);
-        SKO_HIP(launch_skinny_gemm_tn(n, A, lda, ma, B, ldb, nbc, f32, partials, G, st));
+                                     rows_bytes * (A == B ? ma : ma + nbc) * (f32 ? 4.0 : 8.0), st);
+        SKO_HIP(launch_skinny_gemm_tn(n, A, lda, ma, B, ldb, nbc, f32, partials, G, st, br));
         c->prof.end(ev, st);
         ReduceArgs ra{};
         ra.partials = partials;
@@ -124,7 +131,7 @@ struct Engine {
         ra.small = small;
         ra.small.status = status;
         const int ev2 = c->prof.begin("reduce+small", 8.0 * G * ra.count, st);
-        SKO_HIP(launch_reduce(ra, st));
+        SKO_HIP(launch_reduce(ra, st, br));
         c->prof.end(ev2, st);
         return SKO_OK;
     }
@@ -133,8 +140,8 @@ struct Engine {
                      const double* R, void* X, int64_t ldx) {
         const int ev = c->prof.begin(std::string("wide_rowop f") + (f32 ? "32" : "64") + (pu > 0 ? " upd" : "") +
                                          (R ? " trsm" : ""),
-                                     (double)n * (2 * Wd + pu) * (f32 ? 4.0 : 8.0), st);
-        SKO_HIP(launch_wide_rowop(n, Wd, f32, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx, st));
+                                     rows_bytes * (2 * Wd + pu) * (f32 ? 4.0 : 8.0), st);
+        SKO_HIP(launch_wide_rowop(n, Wd, f32, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx, st, br));
         c->prof.end(ev, st);
         return SKO_OK;
     }
@@ -142,16 +149,27 @@ struct Engine {
     sko_status plain(PassKey key, PassArgs a) {
         a.n = n;
         const int ev = c->prof.begin(pass_name(key), pass_bytes(key, a), st);
-        SKO_HIP(launch_pass(key, a, grid_for({key}), st));
+        SKO_HIP(launch_pass(key, a, grid_for({key}), st, br));
         c->prof.end(ev, st);
         return SKO_OK;
+    }
+
+    // Workgroups of a wide Gram / projection launch (per system in batched mode, where a
+    // launch already holds many systems).
+    int gemm_grid() const {
+        const int64_t ns32 = (n + 31) / 32;
+        const int64_t want = br ? (ns32 + 63) / 64 : ns32;
+        return (int)std::max<int64_t>(1, std::min<int64_t>(want, skinny_gemm_grid_cap()));
     }
 
     static std::string pass_name(const PassKey& k) {
         static const char* reds[] = {"none", "proj", "gram", "sketch_sparse", "sketch_dense"};
         char buf[96];
-        snprintf(buf, sizeof buf, "pass W=%d %s red=%s upd=%d trsm=%d write=%d", k.W, k.f32 ? "f32" : "f64",
-                 reds[k.red], (int)k.upd, k.ntrsm, (int)k.write);
+        const int mt = k.red == RED_PROJ ? (k.tiles >= 1 && k.tiles <= 4 ? 4 : 8) : 0;
+        char tl[16] = "";
+        if (mt) snprintf(tl, sizeof tl, "/mt%d", mt);
+        snprintf(buf, sizeof buf, "pass W=%d %s red=%s%s upd=%d trsm=%d write=%d", k.W, k.f32 ? "f32" : "f64",
+                 reds[k.red], tl, (int)k.upd, k.ntrsm, (int)k.write);
         return buf;
     }
     // Algorithmic HBM bytes of one launch: every tall operand once (read or written).
@@ -159,7 +177,7 @@ struct Engine {
         const double eb = f32 ? 4.0 : 8.0;
         double cols = W + (k.write ? W : 0) + (k.upd ? a.pu : 0) + (k.red == RED_PROJ ? a.red_rows : 0);
         double per_row = cols * eb + (k.red == RED_SKETCH_DENSE ? 8.0 * a.red_rows : 0.0);
-        return per_row * (double)n;
+        return per_row * rows_bytes;
     }
 };
 

@@ -14,7 +14,13 @@
 //   10, 12); at the big-panel end CholQR (Line 15) and, when s_hat < m, BCGS + CholQR
 //   (Line 19); the implicit check runs once per big panel.
 // Cycle end: x += M^{-1} Q y with M = diag(A) for Jacobi (right preconditioning).
+//
+// Batched form (many independent systems, two-stage): the systems advance in lock step and
+// every launch serves all systems still active (batch.h); the host reads all systems'
+// residuals with one strided copy per check and drops converged systems from the launches.
+#include <algorithm>
 #include <chrono>
+#include <numeric>
 #include <vector>
 
 #include "engine.h"
@@ -42,7 +48,71 @@ struct GmCtx {
     int grid_cap;
     // host (pinned)
     double* host;  // [0] res, [1] beta, [2] bnorm; status at host+4 as int
+    // batched mode: template addresses are system 0's; launches go to every active system
+    const BatchReloc* br = nullptr;
+    double avg_nnz = 0.0;
+    int64_t max_n = 0;
+    double rows_bytes = 0.0, nnz_bytes = 0.0;  // active totals for the byte accounting
+    int spmv_cap = 0;
 };
+
+// Small per-solve device buffers, one contiguous block (offsets in bytes).
+struct SmallLayout {
+    size_t bb, gm, ts, st, bytes;
+};
+
+SmallLayout small_layout(int m, int W, int k, int Wb, bool two) {
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t mW = (size_t)m * W;
+    SmallLayout L{};
+    L.bb = 0;
+    L.gm = up(L.bb + sizeof(double) * (2 * mW + (size_t)std::max(k, W) * W + 5 * (size_t)W * W));
+    L.ts = up(L.gm + sizeof(double) * (3 * (size_t)(m + 1) * m + 3 * (size_t)(m + 1) + 8 + (size_t)(m + 1) * W));
+    L.st = up(L.ts + (two ? sizeof(double) * (mW + (size_t)k * Wb + (size_t)Wb * W + (size_t)W * W +
+                                              3 * (size_t)Wb * Wb + (size_t)m * Wb)
+                          : 0));
+    L.bytes = up(L.st + 256);
+    return L;
+}
+
+// Point g's small buffers into the block at `base`.
+void carve_small(GmCtx& g, char* base, const SmallLayout& L, int k) {
+    const int m = g.m, W = g.W;
+    const int64_t mW = (int64_t)m * W;
+    double* p = reinterpret_cast<double*>(base + L.bb);
+    g.bb.C1 = p;
+    g.bb.C2 = p + mW;
+    g.bb.Ysk = g.bb.C2 + mW;
+    g.bb.G2 = g.bb.Ysk + (int64_t)std::max(k, W) * W;
+    g.bb.G3 = g.bb.G2 + W * W;
+    g.bb.R1 = g.bb.G3 + W * W;
+    g.bb.R2 = g.bb.R1 + W * W;
+    g.bb.R3 = g.bb.R2 + W * W;
+    double* q = reinterpret_cast<double*>(base + L.gm);
+    const int64_t big = (int64_t)(m + 1) * m;
+    g.Tin = q;
+    g.Tout = q + big;
+    g.H = q + 2 * big;
+    g.g = q + 3 * big;
+    g.gw = g.g + (m + 1);
+    g.y = g.gw + (m + 1);
+    g.res = g.y + (m + 1);
+    g.beta = g.res + 2;
+    g.bnorm = g.beta + 2;
+    g.coef = g.res + 8;
+    if (g.two) {
+        double* t = reinterpret_cast<double*>(base + L.ts);
+        g.Cpan = t;
+        g.Yacc = g.Cpan + mW;
+        g.rt = g.Yacc + (int64_t)k * g.Wb;
+        g.rho = g.rt + (int64_t)g.Wb * W;
+        g.Gb = g.rho + W * W;
+        g.Rh = g.Gb + g.Wb * g.Wb;
+        g.Rt = g.Rh + g.Wb * g.Wb;
+        g.C2b = g.Rt + g.Wb * g.Wb;
+    }
+    g.status = reinterpret_cast<int*>(base + L.st);
+}
 
 void* col_ptr(const GmCtx& g, int col) {
     return static_cast<char*>(g.Q) + (int64_t)col * g.ld * (g.f32 ? 4 : 8);
@@ -71,11 +141,16 @@ sko_status norm2(GmCtx& g, Engine& e1, const double* v, double* out) {
 }
 
 sko_status mpk(GmCtx& g, int from, int s) {
+    const double nnz = g.br ? g.nnz_bytes : (double)g.A.nnz;
+    const double rows = g.br ? g.rows_bytes : (double)g.n;
     for (int i = 1; i <= s; ++i) {
         const int ev = g.c->prof.begin(std::string("spmv ") + (g.f32 ? "f32" : "f64"),
-                                       (double)g.A.nnz * (g.f32 ? 8.0 : 12.0) + (double)g.n * (g.f32 ? 12.0 : 20.0),
-                                       g.st);
-        SKO_HIP(launch_spmv(g.A, g.f32, col_ptr(g, from + i - 1), col_ptr(g, from + i), g.grid_cap, g.st));
+                                       nnz * (g.f32 ? 8.0 : 12.0) + rows * (g.f32 ? 12.0 : 20.0), g.st);
+        if (g.br)
+            SKO_HIP(launch_spmv_batched(g.f32, g.avg_nnz, g.max_n, col_ptr(g, from + i - 1), col_ptr(g, from + i),
+                                        g.spmv_cap, g.st, *g.br));
+        else
+            SKO_HIP(launch_spmv(g.A, g.f32, col_ptr(g, from + i - 1), col_ptr(g, from + i), g.grid_cap, g.st));
         g.c->prof.end(ev, g.st);
     }
     return SKO_OK;
@@ -94,7 +169,7 @@ sko_status gm_op(GmCtx& g, GmSmallArgs a) {
     a.beta = g.beta;
     a.coef = g.coef;
     const int ev = g.c->prof.begin("gmres small", 0.0, g.st);
-    SKO_HIP(launch_gm_small(a, g.st));
+    SKO_HIP(launch_gm_small(a, g.st, g.br));
     g.c->prof.end(ev, g.st);
     return SKO_OK;
 }
@@ -129,124 +204,140 @@ sko_status cycle_one_stage(GmCtx& g, Engine& e, double bnorm, double tol, sko_gm
     return SKO_OK;
 }
 
+// One s-step panel of a two-stage big panel (Fig. 5): MPK from the last pre-processed
+// vector, BCGS against the previous big panels, sketch with sketch-space BCGS2-HH, forward
+// substitution, and the block's Hessenberg columns.
+sko_status two_stage_panel(GmCtx& g, Engine& e, int k0, int i) {
+    sko_status s;
+    const int S = g.s, W = g.W, ld = (int)g.m + 1;
+    const int red_sk = g.sk.kind == SKO_SKETCH_SPARSE_SIGN ? RED_SKETCH_SPARSE : RED_SKETCH_DENSE;
+    const double sk_scale = g.sk.kind == SKO_SKETCH_SPARSE_SIGN ? 1.0 / std::sqrt((double)g.sk.zeta) : 1.0;
+    void* Qb = col_ptr(g, k0);
+    const int loc = i * S, kk = k0 + loc;
+    if ((s = mpk(g, kk, S))) return s;
+    void* V = col_ptr(g, kk);
+    PassKey key{W, g.f32, red_sk, false, 0, false};
+    PassArgs a{};
+    a.Y = V;
+    a.ldy = g.ld;
+    if (k0 > 0) {
+        PassArgs pa{};
+        pa.Y = V;
+        pa.ldy = g.ld;
+        SmallArgs sm{};
+        sm.op = OP_STORE;
+        sm.w = W;
+        sm.out = g.Cpan;
+        if ((s = e.reduction({W, g.f32, RED_PROJ, false, 0, false}, pa, k0, V, g.ld, g.Q, g.ld, sm, 1.0))) return s;
+        key.upd = true;
+        key.write = true;
+        a.Qu = g.Q;
+        a.ldqu = g.ld;
+        a.pu = k0;
+        a.Cu = g.Cpan;
+        a.X = V;
+        a.ldx = g.ld;
+    }
+    SmallArgs sm{};
+    sm.op = OP_SKETCH_BCGS2;
+    sm.w = W;
+    sm.k = g.sk.k;
+    sm.col0 = kk;
+    sm.out = g.bb.Ysk;
+    sm.R = g.rho;
+    sm.Yacc = g.Yacc;
+    sm.nacc = loc;
+    sm.r = g.rt;
+    sm.Rbar = g.coef + k0;
+    sm.ldrbar = ld;
+    sm.rbar_col0 = 0;
+    if ((s = e.reduction(key, a, g.sk.k, V, g.ld, nullptr, 0, sm, sk_scale))) return s;
+    PassArgs fa{};
+    fa.Y = V;
+    fa.ldy = g.ld;
+    fa.R1 = g.rho;
+    fa.X = V;
+    fa.ldx = g.ld;
+    PassKey fkey{W, g.f32, RED_NONE, false, 1, true};
+    if (loc > 0) {
+        fkey.upd = true;
+        fa.Qu = Qb;
+        fa.ldqu = g.ld;
+        fa.pu = loc;
+        fa.Cu = g.rt;
+    }
+    if ((s = e.plain(fkey, fa))) return s;
+    GmSmallArgs ga{};
+    ga.op = GM_BLOCK;
+    ga.kk = kk;
+    ga.k0 = k0;
+    ga.two_stage = 1;
+    ga.Cpan = k0 > 0 ? g.Cpan : nullptr;
+    return gm_op(g, ga);
+}
+
+// Big-panel close (Fig. 5 Line 15, Fig. 6 Line 19): CholQR of the pre-processed big panel,
+// then (s_hat < m) BCGS against the previous big panels and a second CholQR; the stored
+// Hessenberg columns are re-expressed in the final basis and the least squares solved.
+sko_status two_stage_bigclose(GmCtx& g, Engine& e, int k0) {
+    sko_status s;
+    const int Wb = g.Wb;
+    void* Qb = col_ptr(g, k0);
+    {
+        SmallArgs sm{};
+        sm.op = OP_CHOL;
+        sm.w = Wb;
+        sm.col0 = k0;
+        sm.out = g.Gb;
+        sm.R = g.Rh;
+        if ((s = e.gemm_reduction(Qb, g.ld, Wb, Qb, g.ld, Wb, sm, Wb))) return s;
+        if ((s = e.rowop(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rh, Qb, g.ld))) return s;
+    }
+    const bool proj2 = g.reorth && k0 > 0;
+    if (g.reorth) {
+        if (proj2) {
+            for (int a0 = 0; a0 < k0; a0 += 64) {
+                const int ma = std::min(64, k0 - a0);
+                SmallArgs sm{};
+                sm.op = OP_STORE;
+                sm.w = Wb;
+                sm.out = g.C2b + a0;
+                if ((s = e.gemm_reduction(col_ptr(g, a0), g.ld, ma, Qb, g.ld, Wb, sm, k0))) return s;
+            }
+            if ((s = e.rowop(Wb, Qb, g.ld, g.Q, g.ld, k0, g.C2b, nullptr, Qb, g.ld))) return s;
+        }
+        SmallArgs sm{};
+        sm.op = OP_CHOL;
+        sm.w = Wb;
+        sm.col0 = k0;
+        sm.out = g.Gb;
+        sm.R = g.Rt;
+        if ((s = e.gemm_reduction(Qb, g.ld, Wb, Qb, g.ld, Wb, sm, Wb))) return s;
+        if ((s = e.rowop(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rt, Qb, g.ld))) return s;
+    }
+    GmSmallArgs ga{};
+    ga.op = GM_BIGCLOSE;
+    ga.k0 = k0;
+    ga.Wb = Wb;
+    ga.kend = k0 + g.shat;
+    ga.two_stage = 1;
+    ga.Rh = g.Rh;
+    ga.Rt = g.reorth ? g.Rt : nullptr;
+    ga.C2 = proj2 ? g.C2b : nullptr;
+    return gm_op(g, ga);
+}
+
 sko_status cycle_two_stage(GmCtx& g, Engine& e, double bnorm, double tol, sko_gmres_info& inf, int64_t maxiter,
                            int* k_out) {
     sko_status s;
-    const int S = g.s, W = g.W, Wb = g.Wb, ld = (int)g.m + 1;
-    const int red_sk = g.sk.kind == SKO_SKETCH_SPARSE_SIGN ? RED_SKETCH_SPARSE : RED_SKETCH_DENSE;
-    const double sk_scale = g.sk.kind == SKO_SKETCH_SPARSE_SIGN ? 1.0 / std::sqrt((double)g.sk.zeta) : 1.0;
     int k0 = 0, k = 0;
     while (k0 < g.m) {
-        void* Qb = col_ptr(g, k0);
-        for (int i = 0; i < g.shat / S; ++i) {
-            const int loc = i * S, kk = k0 + loc;
-            if ((s = mpk(g, kk, S))) return s;
-            void* V = col_ptr(g, kk);
-            PassKey key{W, g.f32, red_sk, false, 0, false};
-            PassArgs a{};
-            a.Y = V;
-            a.ldy = g.ld;
-            if (k0 > 0) {
-                PassArgs pa{};
-                pa.Y = V;
-                pa.ldy = g.ld;
-                SmallArgs sm{};
-                sm.op = OP_STORE;
-                sm.w = W;
-                sm.out = g.Cpan;
-                if ((s = e.reduction({W, g.f32, RED_PROJ, false, 0, false}, pa, k0, V, g.ld, g.Q, g.ld, sm, 1.0)))
-                    return s;
-                key.upd = true;
-                key.write = true;
-                a.Qu = g.Q;
-                a.ldqu = g.ld;
-                a.pu = k0;
-                a.Cu = g.Cpan;
-                a.X = V;
-                a.ldx = g.ld;
-            }
-            SmallArgs sm{};
-            sm.op = OP_SKETCH_BCGS2;
-            sm.w = W;
-            sm.k = g.sk.k;
-            sm.col0 = kk;
-            sm.out = g.bb.Ysk;
-            sm.R = g.rho;
-            sm.Yacc = g.Yacc;
-            sm.nacc = loc;
-            sm.r = g.rt;
-            sm.Rbar = g.coef + k0;
-            sm.ldrbar = ld;
-            sm.rbar_col0 = 0;
-            if ((s = e.reduction(key, a, g.sk.k, V, g.ld, nullptr, 0, sm, sk_scale))) return s;
-            PassArgs fa{};
-            fa.Y = V;
-            fa.ldy = g.ld;
-            fa.R1 = g.rho;
-            fa.X = V;
-            fa.ldx = g.ld;
-            PassKey fkey{W, g.f32, RED_NONE, false, 1, true};
-            if (loc > 0) {
-                fkey.upd = true;
-                fa.Qu = Qb;
-                fa.ldqu = g.ld;
-                fa.pu = loc;
-                fa.Cu = g.rt;
-            }
-            if ((s = e.plain(fkey, fa))) return s;
-            GmSmallArgs ga{};
-            ga.op = GM_BLOCK;
-            ga.kk = kk;
-            ga.k0 = k0;
-            ga.two_stage = 1;
-            ga.Cpan = k0 > 0 ? g.Cpan : nullptr;
-            if ((s = gm_op(g, ga))) return s;
-            inf.iters += S;
+        for (int i = 0; i < g.shat / g.s; ++i) {
+            if ((s = two_stage_panel(g, e, k0, i))) return s;
+            inf.iters += g.s;
         }
-        // big-panel close
-        {
-            SmallArgs sm{};
-            sm.op = OP_CHOL;
-            sm.w = Wb;
-            sm.col0 = k0;
-            sm.out = g.Gb;
-            sm.R = g.Rh;
-            if ((s = e.gemm_reduction(Qb, g.ld, Wb, Qb, g.ld, Wb, sm, Wb))) return s;
-            if ((s = e.rowop(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rh, Qb, g.ld))) return s;
-        }
-        const bool proj2 = g.reorth && k0 > 0;
-        if (g.reorth) {
-            if (proj2) {
-                for (int a0 = 0; a0 < k0; a0 += 64) {
-                    const int ma = std::min(64, k0 - a0);
-                    SmallArgs sm{};
-                    sm.op = OP_STORE;
-                    sm.w = Wb;
-                    sm.out = g.C2b + a0;
-                    if ((s = e.gemm_reduction(col_ptr(g, a0), g.ld, ma, Qb, g.ld, Wb, sm, k0))) return s;
-                }
-                if ((s = e.rowop(Wb, Qb, g.ld, g.Q, g.ld, k0, g.C2b, nullptr, Qb, g.ld))) return s;
-            }
-            SmallArgs sm{};
-            sm.op = OP_CHOL;
-            sm.w = Wb;
-            sm.col0 = k0;
-            sm.out = g.Gb;
-            sm.R = g.Rt;
-            if ((s = e.gemm_reduction(Qb, g.ld, Wb, Qb, g.ld, Wb, sm, Wb))) return s;
-            if ((s = e.rowop(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rt, Qb, g.ld))) return s;
-        }
+        if ((s = two_stage_bigclose(g, e, k0))) return s;
         const int kend = k0 + g.shat;
-        GmSmallArgs ga{};
-        ga.op = GM_BIGCLOSE;
-        ga.k0 = k0;
-        ga.Wb = Wb;
-        ga.kend = kend;
-        ga.two_stage = 1;
-        ga.Rh = g.Rh;
-        ga.Rt = g.reorth ? g.Rt : nullptr;
-        ga.C2 = proj2 ? g.C2b : nullptr;
-        if ((s = gm_op(g, ga))) return s;
         int status = 0;
         if ((s = read_scalars(g, g.res, 1, &status))) return s;
         k = kend;
@@ -265,11 +356,11 @@ sko_status cycle_two_stage(GmCtx& g, Engine& e, double bnorm, double tol, sko_gm
 
 }  // namespace
 
-sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, const sko_gmres_opts* o,
-                      sko_gmres_info* info) {
-    sko_gmres_info inf{};
-    if (info) *info = inf;
-    if (!A || !b || !x || !o || !A->rowptr || !A->colind || !A->val || A->n < 1 || A->nnz < 1) return SKO_EINVAL;
+namespace {
+
+// Option checks shared by the single and batched solvers; fills the shape fields of g.
+sko_status check_opts(const sko_csr* A, const sko_gmres_opts* o, GmCtx& g) {
+    if (!A || !o || !A->rowptr || !A->colind || !A->val || A->n < 1 || A->nnz < 1) return SKO_EINVAL;
     const int S = o->s, m = o->m;
     if (S < 1 || m < S || m % S) return SKO_EINVAL;
     if (S + 1 > kMaxPassW || m + 1 > 255) return SKO_EUNSUPPORTED;
@@ -284,11 +375,6 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     if (need_sketch && !sketch_ok(o->sketch, A->n)) return SKO_EINVAL;
     if (need_sketch && o->sketch.k < (two ? shat + 1 : S + 1)) return SKO_EINVAL;
     if (!(o->tol > 0.0)) return SKO_EINVAL;
-    const int64_t maxiter = o->maxiter > 0 ? o->maxiter : 50000;
-
-    GmCtx g{};
-    g.c = c;
-    g.st = c->stream;
     g.n = A->n;
     g.ld = ((A->n + 63) / 64) * 64;
     g.s = S;
@@ -302,8 +388,29 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     g.reorth = two && shat < m;
     g.intra = o->intra;
     g.sk = o->sketch;
+    return SKO_OK;
+}
+
+int sketch_rows(const GmCtx& g) {
+    const bool need_sketch = g.two || g.intra == SKO_INTRA_RANDCHOLQR;
+    return need_sketch ? g.sk.k : g.W;
+}
+
+}  // namespace
+
+sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, const sko_gmres_opts* o,
+                      sko_gmres_info* info) {
+    sko_gmres_info inf{};
+    if (info) *info = inf;
+    GmCtx g{};
+    if (!b || !x) return SKO_EINVAL;
+    if (sko_status cs = check_opts(A, o, g)) return cs;
+    const int m = g.m;
+    const int64_t maxiter = o->maxiter > 0 ? o->maxiter : 50000;
+    g.c = c;
+    g.st = c->stream;
     const int eb = g.f32 ? 4 : 8;
-    const int k = need_sketch ? o->sketch.k : g.W;
+    const int k = sketch_rows(g);
 
     // ---- workspace
     Arena ar(c);
@@ -319,55 +426,15 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     const size_t part_doubles = std::max({(size_t)part_stride * gmax, (size_t)64 * 64 * std::max(1, skinny_gemm_grid_cap()),
                                           (size_t)g.grid_cap});
     const size_t o_part = ar.reserve(sizeof(double) * part_doubles);
-    const int mW = m * g.W;
-    const size_t o_bb = ar.reserve(sizeof(double) * (2 * (size_t)mW + (size_t)std::max(k, g.W) * g.W + 5 * g.W * g.W));
-    const size_t o_gm = ar.reserve(sizeof(double) * (3 * (size_t)(m + 1) * m + 3 * (size_t)(m + 1) + 8 +
-                                                     (size_t)(m + 1) * g.W));
-    const size_t o_ts = two ? ar.reserve(sizeof(double) * ((size_t)mW + (size_t)k * g.Wb + (size_t)g.Wb * g.W +
-                                                          g.W * g.W + 3 * (size_t)g.Wb * g.Wb + (size_t)m * g.Wb))
-                            : 0;
-    const size_t o_st = ar.reserve(256);
+    const SmallLayout L = small_layout(m, g.W, k, g.Wb, g.two);
+    const size_t o_small = ar.reserve(L.bytes);
     sko_status s = ensure_workspace(c, ar.used());
     if (s) return s;
     if ((s = ensure_pinned(c, 64))) return s;
     g.host = static_cast<double*>(c->pinned);
     g.Q = ar.at<void>(o_Q);
     g.dinv = g.jacobi ? ar.at<double>(o_dinv) : nullptr;
-    g.status = ar.at<int>(o_st);
-    {
-        double* p = ar.at<double>(o_bb);
-        g.bb.C1 = p;
-        g.bb.C2 = p + mW;
-        g.bb.Ysk = g.bb.C2 + mW;
-        g.bb.G2 = g.bb.Ysk + (int64_t)std::max(k, g.W) * g.W;
-        g.bb.G3 = g.bb.G2 + g.W * g.W;
-        g.bb.R1 = g.bb.G3 + g.W * g.W;
-        g.bb.R2 = g.bb.R1 + g.W * g.W;
-        g.bb.R3 = g.bb.R2 + g.W * g.W;
-        double* q = ar.at<double>(o_gm);
-        const int64_t big = (int64_t)(m + 1) * m;
-        g.Tin = q;
-        g.Tout = q + big;
-        g.H = q + 2 * big;
-        g.g = q + 3 * big;
-        g.gw = g.g + (m + 1);
-        g.y = g.gw + (m + 1);
-        g.res = g.y + (m + 1);
-        g.beta = g.res + 2;
-        g.bnorm = g.beta + 2;
-        g.coef = g.res + 8;
-        if (two) {
-            double* t = ar.at<double>(o_ts);
-            g.Cpan = t;
-            g.Yacc = g.Cpan + mW;
-            g.rt = g.Yacc + (int64_t)k * g.Wb;
-            g.rho = g.rt + (int64_t)g.Wb * g.W;
-            g.Gb = g.rho + g.W * g.W;
-            g.Rh = g.Gb + g.Wb * g.Wb;
-            g.Rt = g.Rh + g.Wb * g.Wb;
-            g.C2b = g.Rt + g.Wb * g.Wb;
-        }
-    }
+    carve_small(g, ar.at<char>(o_small), L, k);
 
     hipEvent_t t0 = nullptr, t1 = nullptr;
     SKO_HIP(hipEventCreate(&t0));
@@ -476,7 +543,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
             ia.op = GM_INIT;
             if ((s = gm_op(g, ia))) return s;
             int kreached = 0;
-            s = two ? cycle_two_stage(g, e, bnorm, o->tol, inf, maxiter, &kreached)
+            s = g.two ? cycle_two_stage(g, e, bnorm, o->tol, inf, maxiter, &kreached)
                     : cycle_one_stage(g, e, bnorm, o->tol, inf, maxiter, &kreached);
             if (s == SKO_EBREAKDOWN) {
                 result = s;
@@ -503,9 +570,10 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     return result;
 }
 
-sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const double* const* b, double* const* x,
-                              const sko_gmres_opts* o, sko_gmres_info* infos) {
-    if (nsys < 0 || (nsys > 0 && (!A || !b || !x || !o))) return SKO_EINVAL;
+namespace {
+
+sko_status gmres_sequential(sko_ctx c, int32_t nsys, const sko_csr* A, const double* const* b, double* const* x,
+                            const sko_gmres_opts* o, sko_gmres_info* infos) {
     sko_status first = SKO_OK;
     for (int32_t i = 0; i < nsys; ++i) {
         sko_gmres_opts oi = *o;
@@ -514,6 +582,371 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
         const sko_status s = gmres_impl(c, &A[i], b[i], x[i], &oi, &inf);
         if (infos) infos[i] = inf;
         if (s != SKO_OK && first == SKO_OK) first = s;
+    }
+    return first;
+}
+
+struct SysState {
+    double bnorm = 0.0;
+    bool finished = false;
+    bool in_cycle = false;
+    sko_status result = SKO_OK;
+    sko_gmres_info inf{};
+};
+
+}  // namespace
+
+// Many independent two-stage solves in lock step: one launch per step serves every system
+// still active.  Systems share (s, s_hat, m, precision, preconditioner, sketch size); system i
+// draws its sparse-sign sketch from seed + i, as a one-by-one solve of it would.
+sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const double* const* b, double* const* x,
+                              const sko_gmres_opts* o, sko_gmres_info* infos) {
+    if (nsys < 0 || (nsys > 0 && (!A || !b || !x || !o))) return SKO_EINVAL;
+    if (nsys == 0) return SKO_OK;
+    if (infos)
+        for (int32_t i = 0; i < nsys; ++i) infos[i] = sko_gmres_info{};
+    // lock step needs the two-stage scheme with the hashed sketch (no per-system Theta)
+    if (nsys == 1 || !o->two_stage || o->sketch.kind != SKO_SKETCH_SPARSE_SIGN)
+        return gmres_sequential(c, nsys, A, b, x, o, infos);
+
+    GmCtx g{};
+    std::vector<SysState> S(nsys);
+    for (int32_t i = 0; i < nsys; ++i) {
+        GmCtx gi{};
+        if (!b[i] || !x[i]) return SKO_EINVAL;
+        if (sko_status cs = check_opts(&A[i], o, gi)) return cs;
+        if (i == 0) g = gi;
+    }
+    const int m = g.m;
+    const int64_t maxiter = o->maxiter > 0 ? o->maxiter : 50000;
+    g.c = c;
+    g.st = c->stream;
+    const int eb = g.f32 ? 4 : 8;
+    const int k = sketch_rows(g);
+    const bool own_vals = g.jacobi || g.f32;
+    int64_t max_n = 0;
+    double nnz_sum = 0.0, n_sum = 0.0;
+    for (int32_t i = 0; i < nsys; ++i) {
+        max_n = std::max<int64_t>(max_n, A[i].n);
+        nnz_sum += (double)A[i].nnz;
+        n_sum += (double)A[i].n;
+    }
+
+    // ---- launch shapes: per system a fraction of the one-system grid, since one launch
+    // holds every system
+    const int cap = std::max(1, c->cus) * 8;
+    const int64_t strips_max = (max_n + kPassThreads - 1) / kPassThreads;
+    const int Gp = (int)std::max<int64_t>(1, std::min<int64_t>((strips_max + 7) / 8, cap));
+    const int64_t rows = std::max({(int64_t)m, (int64_t)k, (int64_t)g.W});
+    const int64_t part_stride = ((rows * g.W + 31) / 32) * 32;
+    const int64_t ns32 = (max_n + 31) / 32;
+    const int Gg = (int)std::max<int64_t>(1, std::min<int64_t>((ns32 + 63) / 64, skinny_gemm_grid_cap()));
+    const int64_t gemm_cells = std::max<int64_t>((int64_t)g.Wb * g.Wb, (int64_t)std::min(64, m) * g.Wb);
+    const int64_t groups8 = (max_n + 256 / 8 - 1) / (256 / 8);
+    const int Gr = (int)std::max<int64_t>(1, std::min<int64_t>((groups8 + 15) / 16, cap));
+    const size_t part_doubles = std::max({(size_t)part_stride * Gp, (size_t)gemm_cells * Gg, (size_t)Gr});
+    const size_t part_bytes = ((sizeof(double) * part_doubles + 255) / 256) * 256;
+    const SmallLayout L = small_layout(m, g.W, k, g.Wb, g.two);
+
+    // ---- workspace: per-system basis / operator values / D^{-1}, then the equal-sized small
+    // blocks, partial sums, the system table and the active list
+    Arena ar(c);
+    std::vector<size_t> o_Q(nsys), o_val(nsys, 0), o_dinv(nsys, 0);
+    for (int32_t i = 0; i < nsys; ++i) {
+        const int64_t ldi = ((A[i].n + 63) / 64) * 64;
+        o_Q[i] = ar.reserve((size_t)eb * ldi * (m + 1));
+        if (own_vals) o_val[i] = ar.reserve((size_t)eb * A[i].nnz);
+        if (g.jacobi) o_dinv[i] = ar.reserve(sizeof(double) * A[i].n);
+    }
+    const size_t o_small = ar.reserve(L.bytes * nsys);
+    const size_t o_part = ar.reserve(part_bytes * nsys);
+    const size_t o_tbl = ar.reserve(sizeof(BatchSys) * nsys);
+    const size_t o_act = ar.reserve(sizeof(int) * nsys);
+    sko_status s = ensure_workspace(c, ar.used());
+    if (s) return s;
+    const size_t pin_tbl = 0, pin_act = sizeof(BatchSys) * nsys, pin_dbl = pin_act + ((sizeof(int) * nsys + 63) / 64) * 64,
+                 pin_int = pin_dbl + sizeof(double) * nsys, pin_end = pin_int + sizeof(int) * nsys + 64;
+    if ((s = ensure_pinned(c, pin_end))) return s;
+    char* pin = static_cast<char*>(c->pinned);
+    BatchSys* tbl_h = reinterpret_cast<BatchSys*>(pin + pin_tbl);
+    int* act_h = reinterpret_cast<int*>(pin + pin_act);
+    double* dbl_h = reinterpret_cast<double*>(pin + pin_dbl);
+    int* int_h = reinterpret_cast<int*>(pin + pin_int);
+    g.host = dbl_h;
+
+    char* small0 = ar.at<char>(o_small);
+    double* part0 = ar.at<double>(o_part);
+    BatchSys* tbl_d = ar.at<BatchSys>(o_tbl);
+    int* act_d = ar.at<int>(o_act);
+    auto small_of = [&](int i) { return small0 + (size_t)i * L.bytes; };
+    auto part_of = [&](int i) { return reinterpret_cast<double*>(reinterpret_cast<char*>(part0) + (size_t)i * part_bytes); };
+
+    // template = system 0
+    g.ld = ((A[0].n + 63) / 64) * 64;
+    g.n = A[0].n;
+    g.Q = ar.at<void>(o_Q[0]);
+    carve_small(g, small_of(0), L, k);
+    g.grid_cap = cap;
+    g.avg_nnz = nnz_sum / std::max(1.0, n_sum);
+    g.max_n = max_n;
+    g.spmv_cap = (int)std::max<int64_t>(1, std::min<int64_t>((groups8 + 7) / 8, cap));
+    const size_t st_off = (size_t)(reinterpret_cast<char*>(g.status) - small_of(0));
+
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    SKO_HIP(hipEventCreate(&t0));
+    SKO_HIP(hipEventCreate(&t1));
+    SKO_HIP(hipEventRecord(t0, g.st));
+    SKO_HIP(hipMemset2DAsync(small0 + st_off, L.bytes, 0, 256, nsys, g.st));
+
+    // strided reads of one double / one int of every system's small block
+    auto read_dbl = [&](const double* tmpl) -> sko_status {
+        SKO_HIP(hipMemcpy2DAsync(dbl_h, sizeof(double), tmpl, L.bytes, sizeof(double), nsys, hipMemcpyDeviceToHost,
+                                 g.st));
+        SKO_HIP(hipMemcpy2DAsync(int_h, sizeof(int), g.status, L.bytes, sizeof(int), nsys, hipMemcpyDeviceToHost,
+                                 g.st));
+        SKO_HIP(hipStreamSynchronize(g.st));
+        c->prof.flush();
+        return SKO_OK;
+    };
+
+    // ---- per system: CSR check, operator set-up, ||b|| (single-system launches)
+    for (int32_t i = 0; i < nsys; ++i) {
+        int* st_i = reinterpret_cast<int*>(small_of(i) + st_off);
+        SKO_HIP(launch_csr_check(A[i].n, A[i].nnz, A[i].rowptr, A[i].colind, st_i + 32, g.st));
+    }
+    SKO_HIP(hipMemcpy2DAsync(int_h, sizeof(int), g.status + 32, L.bytes, sizeof(int), nsys, hipMemcpyDeviceToHost,
+                             g.st));
+    SKO_HIP(hipStreamSynchronize(g.st));
+    for (int32_t i = 0; i < nsys; ++i)
+        if (int_h[i]) {
+            S[i].finished = true;
+            S[i].result = SKO_EINVAL;
+        }
+    for (int32_t i = 0; i < nsys; ++i) {
+        const int64_t ldi = ((A[i].n + 63) / 64) * 64;
+        BatchSys& d = tbl_h[i];
+        d = BatchSys{};
+        d.n = A[i].n;
+        d.ld = ldi;
+        d.nnz = A[i].nnz;
+        d.Q = ar.at<char>(o_Q[i]);
+        d.rowptr = A[i].rowptr;
+        d.colind = A[i].colind;
+        d.val = A[i].val;
+        d.val_op = A[i].val;
+        d.b = b[i];
+        d.x = x[i];
+        d.dinv = g.jacobi ? ar.at<double>(o_dinv[i]) : nullptr;
+        d.seed = o->sketch.seed + (uint64_t)i;
+        d.kupd = 0;
+        if (S[i].finished) continue;
+        int* st_i = reinterpret_cast<int*>(small_of(i) + st_off);
+        if (g.jacobi)
+            SKO_HIP(launch_jacobi_setup(A[i].n, A[i].nnz, A[i].rowptr, A[i].colind, A[i].val,
+                                        const_cast<double*>(d.dinv), st_i, g.st));
+        if (own_vals) {
+            void* vo = ar.at<void>(o_val[i]);
+            SKO_HIP(launch_scale_values(A[i].nnz, A[i].colind, A[i].val, d.dinv, g.f32, vo, g.st));
+            d.val_op = vo;
+        }
+        GmCtx gi = g;
+        gi.n = A[i].n;
+        carve_small(gi, small_of(i), L, k);
+        Engine e1(c, A[i].n, 1, false, g.sk);
+        e1.partials = part_of(i);
+        e1.part_stride = part_stride;
+        e1.gmax = Gp;
+        e1.status = gi.status;
+        e1.counter = reinterpret_cast<unsigned*>(gi.status + 16);
+        c->tickets = 0;  // each system's counter is fresh
+        if ((s = norm2(gi, e1, b[i], gi.bnorm))) return s;
+    }
+    if ((s = read_dbl(g.bnorm))) return s;
+    for (int32_t i = 0; i < nsys; ++i) {
+        if (S[i].finished) continue;
+        if (int_h[i] == -1) {  // zero diagonal with Jacobi
+            S[i].finished = true;
+            S[i].result = SKO_EINVAL;
+            continue;
+        }
+        S[i].bnorm = dbl_h[i];
+        if (!(S[i].bnorm > 0.0) || !std::isfinite(S[i].bnorm)) {
+            S[i].finished = true;
+            S[i].result = S[i].bnorm == 0.0 ? SKO_OK : SKO_EINVAL;
+        }
+    }
+    SKO_HIP(hipMemcpyAsync(tbl_d, tbl_h, sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, g.st));
+    SKO_HIP(hipStreamSynchronize(g.st));
+
+    BatchReloc br{};
+    br.sys = tbl_d;
+    br.active = act_d;
+    br.nact = 0;
+    br.eb = eb;
+    br.q0 = static_cast<const char*>(g.Q);
+    br.q0_bytes = (int64_t)eb * g.ld * (m + 1);
+    br.ld0 = g.ld;
+    br.ws0 = small0;
+    br.ws_bytes = (int64_t)L.bytes;
+    br.part0 = reinterpret_cast<const char*>(part0);
+    br.part_bytes = (int64_t)part_bytes;
+    br.cnt0 = nullptr;
+    br.cnt_bytes = 0;
+    g.br = &br;
+
+    Engine e(c, max_n, g.W, g.f32, g.sk);
+    e.partials = part0;
+    e.part_stride = part_stride;
+    e.gmax = Gp;
+    e.status = g.status;
+    e.counter = reinterpret_cast<unsigned*>(g.status + 16);
+    e.br = &br;
+    Engine e1f(c, max_n, 1, g.f32, g.sk);
+    e1f.partials = part0;
+    e1f.part_stride = part_stride;
+    e1f.gmax = Gp;
+    e1f.status = g.status;
+    e1f.counter = e.counter;
+    e1f.br = &br;
+
+    // New active list (largest systems first, so their workgroups are dispatched first);
+    // the reduction counters restart from zero with it.
+    auto set_active = [&](std::vector<int> list) -> sko_status {
+        std::sort(list.begin(), list.end(), [&](int a, int q) { return A[a].n > A[q].n || (A[a].n == A[q].n && a < q); });
+        double nr = 0.0, nz = 0.0;
+        for (size_t j = 0; j < list.size(); ++j) {
+            act_h[j] = list[j];
+            nr += (double)A[list[j]].n;
+            nz += (double)A[list[j]].nnz;
+        }
+        br.nact = (int)list.size();
+        e.rows_bytes = e1f.rows_bytes = g.rows_bytes = nr;
+        g.nnz_bytes = nz;
+        if (list.empty()) return SKO_OK;
+        SKO_HIP(hipMemcpyAsync(act_d, act_h, sizeof(int) * list.size(), hipMemcpyHostToDevice, g.st));
+        SKO_HIP(hipMemset2DAsync(small0 + st_off + 16 * sizeof(int), L.bytes, 0, sizeof(unsigned), nsys, g.st));
+        SKO_HIP(hipStreamSynchronize(g.st));
+        c->tickets = 0;
+        return SKO_OK;
+    };
+
+    while (true) {
+        std::vector<int> live;
+        for (int32_t i = 0; i < nsys; ++i)
+            if (!S[i].finished) live.push_back(i);
+        if (live.empty()) break;
+        if ((s = set_active(live))) return s;
+        // explicit residuals r = b - A x into basis column 0, beta = ||r||
+        {
+            const int ev = c->prof.begin("residual f64", g.nnz_bytes * 12.0 + g.rows_bytes * 24.0,
+                                         g.st);
+            SKO_HIP(launch_residual_batched(g.f32, g.avg_nnz, g.Q, part0, Gr, g.st, br));
+            c->prof.end(ev, g.st);
+            ReduceArgs ra{};
+            ra.partials = part0;
+            ra.stride = 1;
+            ra.G = Gr;
+            ra.count = 1;
+            ra.scale = 1.0;
+            ra.counter = e.counter;
+            ra.ticket0 = c->tickets;
+            c->tickets += (unsigned)reduce_grid(1);
+            ra.rows = 1;
+            ra.ldo = 1;
+            ra.small.op = OP_CHOL;
+            ra.small.w = 1;
+            ra.small.out = g.gw;
+            ra.small.R = g.beta;
+            ra.small.status = nullptr;
+            SKO_HIP(launch_reduce(ra, g.st, &br));
+        }
+        if ((s = read_dbl(g.beta))) return s;
+        std::vector<int> cyc;
+        for (int i : live) {
+            SysState& q = S[i];
+            q.inf.relres = dbl_h[i] / q.bnorm;
+            if (q.inf.relres <= o->tol) {
+                q.inf.converged = 1;
+                q.finished = true;
+            } else if (q.inf.iters >= maxiter) {
+                q.result = SKO_ENOCONV;
+                q.finished = true;
+            } else {
+                cyc.push_back(i);
+            }
+        }
+        if (cyc.empty()) break;
+        if (cyc.size() != live.size() && (s = set_active(cyc))) return s;
+        for (int i : cyc) S[i].in_cycle = true;
+        {   // q_1 = r / beta
+            PassArgs a{};
+            a.Y = g.Q;
+            a.ldy = g.ld;
+            a.R1 = g.beta;
+            a.X = g.Q;
+            a.ldx = g.ld;
+            if ((s = e1f.plain({1, g.f32, RED_NONE, false, 1, true}, a))) return s;
+        }
+        GmSmallArgs ia{};
+        ia.op = GM_INIT;
+        if ((s = gm_op(g, ia))) return s;
+        std::vector<int> kreached(nsys, 0);
+        std::vector<int> running = cyc;
+        for (int k0 = 0; k0 < m && !running.empty(); k0 += g.shat) {
+            for (int i = 0; i < g.shat / g.s; ++i) {
+                if ((s = two_stage_panel(g, e, k0, i))) return s;
+                for (int j : running) S[j].inf.iters += g.s;
+            }
+            if ((s = two_stage_bigclose(g, e, k0))) return s;
+            if ((s = read_dbl(g.res))) return s;
+            const int kend = k0 + g.shat;
+            std::vector<int> next;
+            for (int j : running) {
+                SysState& q = S[j];
+                if (int_h[j]) {  // breakdown: no update from this cycle
+                    q.inf.breakdown_col = int_h[j];
+                    q.result = SKO_EBREAKDOWN;
+                    q.finished = true;
+                    q.in_cycle = false;
+                    kreached[j] = 0;
+                    continue;
+                }
+                kreached[j] = kend;
+                q.inf.relres_implicit = dbl_h[j] / q.bnorm;
+                if (q.inf.relres_implicit <= o->tol || q.inf.iters >= maxiter || kend >= m) continue;
+                next.push_back(j);
+            }
+            if (next.size() != running.size() && !next.empty() && (s = set_active(next))) return s;
+            running.swap(next);
+        }
+        // x += M^{-1} Q y for every system of this cycle
+        std::vector<int> upd;
+        for (int i : cyc) {
+            tbl_h[i].kupd = S[i].in_cycle ? kreached[i] : 0;
+            if (S[i].in_cycle && kreached[i] > 0) upd.push_back(i);
+            if (S[i].in_cycle) S[i].inf.restarts += 1;
+            S[i].in_cycle = false;
+        }
+        if (!upd.empty()) {
+            SKO_HIP(hipMemcpyAsync(tbl_d, tbl_h, sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, g.st));
+            if ((s = set_active(upd))) return s;
+            const int ev2 = c->prof.begin("update x", g.rows_bytes * (m * eb + 16.0), g.st);
+            SKO_HIP(launch_update_batched(g.f32, max_n, g.Q, m, g.y, g.st, br));
+            c->prof.end(ev2, g.st);
+        }
+    }
+    SKO_HIP(hipEventRecord(t1, g.st));
+    SKO_HIP(hipEventSynchronize(t1));
+    c->prof.flush();
+    float ms = 0.f;
+    SKO_HIP(hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    sko_status first = SKO_OK;
+    for (int32_t i = 0; i < nsys; ++i) {
+        S[i].inf.t_total = ms * 1e-3;
+        if (infos) infos[i] = S[i].inf;
+        if (S[i].result != SKO_OK && first == SKO_OK) first = S[i].result;
     }
     return first;
 }

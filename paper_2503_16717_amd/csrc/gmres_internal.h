@@ -63,6 +63,15 @@ struct GmSmallArgs {
     const double* C2;  // GM_BIGCLOSE: k0 x Wb or null
 };
 
-hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st);
+hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st, const BatchReloc* br = nullptr);
+
+// Batched forms (batch.h): one launch for every active system; x, y, r and Q are template
+// basis addresses, partials and y template workspace addresses.
+hipError_t launch_spmv_batched(bool f32, double avg_nnz, int64_t max_n, const void* x, void* y, int grid_cap,
+                               hipStream_t st, const BatchReloc& br);
+hipError_t launch_residual_batched(bool f32, double avg_nnz, void* r, double* partials, int grid, hipStream_t st,
+                                   const BatchReloc& br);
+hipError_t launch_update_batched(bool f32, int64_t max_n, const void* Q, int max_k, const double* y, hipStream_t st,
+                                 const BatchReloc& br);
 
 }  // namespace sko

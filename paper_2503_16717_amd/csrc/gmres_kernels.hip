@@ -8,6 +8,7 @@
 //   * the small Hessenberg bookkeeping (T_in / T_out, Givens least squares).
 #include <cmath>
 
+#include "batch.h"
 #include "gmres_internal.h"
 
 namespace sko {
@@ -47,13 +48,39 @@ __global__ void __launch_bounds__(NT) spmv_kernel(int64_t n, const int32_t* __re
     }
 }
 
+// Batched MPK step: x and y are template basis columns.
+template <int L, typename TV, typename TX, typename TY>
+__global__ void __launch_bounds__(NT) spmv_kernel_batched(const TX* x0, TY* y0, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    const TX* __restrict__ x = batch_ptr(br, sys, d, x0);
+    TY* __restrict__ y = batch_ptr(br, sys, d, y0);
+    const TV* __restrict__ val = static_cast<const TV*>(d.val_op);
+    const int32_t* __restrict__ rowptr = d.rowptr;
+    const int32_t* __restrict__ colind = d.colind;
+    const int64_t n = d.n;
+    const int tid = threadIdx.x;
+    const int sub = tid % L;
+    const int64_t rows_per_block = NT / L;
+    for (int64_t base = (int64_t)blockIdx.x * rows_per_block; base < n; base += (int64_t)gridDim.x * rows_per_block) {
+        const int64_t row = base + tid / L;
+        double sum = 0.0;
+        if (row < n) {
+            const int32_t e0 = rowptr[row], e1 = rowptr[row + 1];
+            for (int32_t e = e0 + sub; e < e1; e += L) sum += ld_(val + e) * ld_(x + colind[e]);
+        }
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (sub == 0 && row < n) y[row] = static_cast<TY>(sum);
+    }
+}
+
 // r = b - A x (double), stored into R (type T); partials[blockIdx.x] = sum of r^2.
 template <int L, typename T>
-__global__ void __launch_bounds__(NT) residual_kernel(int64_t n, const int32_t* __restrict__ rowptr,
-                                                      const int32_t* __restrict__ colind,
-                                                      const double* __restrict__ val, const double* __restrict__ x,
-                                                      const double* __restrict__ b, T* __restrict__ r,
-                                                      double* __restrict__ partials) {
+__device__ __forceinline__ void residual_body(int64_t n, const int32_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ colind, const double* __restrict__ val,
+                                              const double* __restrict__ x, const double* __restrict__ b,
+                                              T* __restrict__ r, double* __restrict__ partials) {
     __shared__ double red[NT / 64];
     const int tid = threadIdx.x;
     const int sub = tid % L;
@@ -84,19 +111,52 @@ __global__ void __launch_bounds__(NT) residual_kernel(int64_t n, const int32_t* 
     }
 }
 
+template <int L, typename T>
+__global__ void __launch_bounds__(NT) residual_kernel(int64_t n, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colind,
+                                                      const double* __restrict__ val, const double* __restrict__ x,
+                                                      const double* __restrict__ b, T* __restrict__ r,
+                                                      double* __restrict__ partials) {
+    residual_body<L, T>(n, rowptr, colind, val, x, b, r, partials);
+}
+
+template <int L, typename T>
+__global__ void __launch_bounds__(NT) residual_kernel_batched(T* r0, double* partials0, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    residual_body<L, T>(d.n, d.rowptr, d.colind, d.val, d.x, d.b, batch_ptr(br, sys, d, r0),
+                        batch_ptr(br, sys, d, partials0));
+}
+
 // x[row] += dinv[row] * sum_a Q[row, a] y[a]
+template <typename T>
+__device__ __forceinline__ void update_body(int64_t n, const T* __restrict__ Q, int64_t ldq, int k,
+                                            const double* __restrict__ y, const double* __restrict__ dinv,
+                                            double* __restrict__ x) {
+    extern __shared__ double sy[];
+    for (int i = threadIdx.x; i < k; i += NT) sy[i] = y[i];
+    __syncthreads();
+    for (int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x; row < n; row += (int64_t)gridDim.x * NT) {
+        double s = 0.0;
+        for (int a = 0; a < k; ++a) s += ld_(Q + row + (int64_t)a * ldq) * sy[a];
+        x[row] += dinv ? dinv[row] * s : s;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(NT) update_kernel(int64_t n, const T* __restrict__ Q, int64_t ldq, int k,
                                                     const double* __restrict__ y, const double* __restrict__ dinv,
                                                     double* __restrict__ x) {
-    extern __shared__ double sy[];
-    for (int i = threadIdx.x; i < k; i += NT) sy[i] = y[i];
-    __syncthreads();
-    const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (row >= n) return;
-    double s = 0.0;
-    for (int a = 0; a < k; ++a) s += ld_(Q + row + (int64_t)a * ldq) * sy[a];
-    x[row] += dinv ? dinv[row] * s : s;
+    update_body<T>(n, Q, ldq, k, y, dinv, x);
+}
+
+// Batched update: each system adds its own d.kupd basis vectors (none when 0).
+template <typename T>
+__global__ void __launch_bounds__(NT) update_kernel_batched(const T* Q0, const double* y0, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    if (d.kupd < 1) return;
+    update_body<T>(d.n, batch_ptr(br, sys, d, Q0), d.ld, d.kupd, batch_ptr(br, sys, d, y0), d.dinv, d.x);
 }
 
 // CSR structure check; touches rowptr[0..n] and colind[0..nnz) only by their own indices.
@@ -220,7 +280,7 @@ __device__ void lsq(const GmSmallArgs& a, int k) {
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(NT) gm_small_kernel(const GmSmallArgs a) {
+__device__ __forceinline__ void gm_small_body(const GmSmallArgs& a) {
     const int ld = a.m + 1;
     __shared__ double sub[256];
     if (a.op == GM_INIT) {
@@ -293,6 +353,28 @@ __global__ void __launch_bounds__(NT) gm_small_kernel(const GmSmallArgs a) {
         lsq(a, kend);
         return;
     }
+}
+
+__global__ void __launch_bounds__(NT) gm_small_kernel(const GmSmallArgs a) { gm_small_body(a); }
+
+__global__ void __launch_bounds__(NT) gm_small_kernel_batched(const GmSmallArgs t, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    GmSmallArgs a = t;
+    a.Tin = batch_ptr(br, sys, d, t.Tin);
+    a.Tout = batch_ptr(br, sys, d, t.Tout);
+    a.g = batch_ptr(br, sys, d, t.g);
+    a.gw = batch_ptr(br, sys, d, t.gw);
+    a.H = batch_ptr(br, sys, d, t.H);
+    a.y = batch_ptr(br, sys, d, t.y);
+    a.res = batch_ptr(br, sys, d, t.res);
+    a.beta = batch_ptr(br, sys, d, t.beta);
+    a.coef = batch_ptr(br, sys, d, t.coef);
+    a.Cpan = batch_ptr(br, sys, d, t.Cpan);
+    a.Rh = batch_ptr(br, sys, d, t.Rh);
+    a.Rt = batch_ptr(br, sys, d, t.Rt);
+    a.C2 = batch_ptr(br, sys, d, t.C2);
+    gm_small_body(a);
 }
 
 template <typename TV, typename TX, typename TY>
@@ -387,9 +469,75 @@ hipError_t launch_scale_values(int64_t nnz, const int32_t* colind, const double*
     return hipGetLastError();
 }
 
-hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st) {
+hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st, const BatchReloc* br) {
     if (a.m + 1 > 256 || a.Wb > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gm_small_kernel, dim3(1), dim3(NT), 0, st, a);
+    if (br) {
+        if (br->nact < 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(gm_small_kernel_batched, dim3(1, br->nact), dim3(NT), 0, st, a, *br);
+    } else {
+        hipLaunchKernelGGL(gm_small_kernel, dim3(1), dim3(NT), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_batched(bool f32, double avg_nnz, int64_t max_n, const void* x, void* y, int grid_cap,
+                               hipStream_t st, const BatchReloc& br) {
+    if (br.nact < 1) return hipErrorInvalidValue;
+    const int L = avg_nnz > 4.0 ? 8 : 4;
+    const int64_t groups = (max_n + NT / L - 1) / (NT / L);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, grid_cap));
+    const dim3 g(grid, br.nact);
+    if (f32) {
+        const float* xx = static_cast<const float*>(x);
+        float* yy = static_cast<float*>(y);
+        if (L == 8)
+            hipLaunchKernelGGL((spmv_kernel_batched<8, float, float, float>), g, dim3(NT), 0, st, xx, yy, br);
+        else
+            hipLaunchKernelGGL((spmv_kernel_batched<4, float, float, float>), g, dim3(NT), 0, st, xx, yy, br);
+    } else {
+        const double* xx = static_cast<const double*>(x);
+        double* yy = static_cast<double*>(y);
+        if (L == 8)
+            hipLaunchKernelGGL((spmv_kernel_batched<8, double, double, double>), g, dim3(NT), 0, st, xx, yy, br);
+        else
+            hipLaunchKernelGGL((spmv_kernel_batched<4, double, double, double>), g, dim3(NT), 0, st, xx, yy, br);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_batched(bool f32, double avg_nnz, void* r, double* partials, int grid, hipStream_t st,
+                                   const BatchReloc& br) {
+    if (br.nact < 1 || grid < 1) return hipErrorInvalidValue;
+    const bool l8 = avg_nnz > 4.0;
+    const dim3 g(grid, br.nact);
+    if (f32) {
+        if (l8)
+            hipLaunchKernelGGL((residual_kernel_batched<8, float>), g, dim3(NT), 0, st, static_cast<float*>(r),
+                               partials, br);
+        else
+            hipLaunchKernelGGL((residual_kernel_batched<4, float>), g, dim3(NT), 0, st, static_cast<float*>(r),
+                               partials, br);
+    } else {
+        if (l8)
+            hipLaunchKernelGGL((residual_kernel_batched<8, double>), g, dim3(NT), 0, st, static_cast<double*>(r),
+                               partials, br);
+        else
+            hipLaunchKernelGGL((residual_kernel_batched<4, double>), g, dim3(NT), 0, st, static_cast<double*>(r),
+                               partials, br);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update_batched(bool f32, int64_t max_n, const void* Q, int max_k, const double* y, hipStream_t st,
+                                 const BatchReloc& br) {
+    if (br.nact < 1 || max_k < 1) return hipErrorInvalidValue;
+    const dim3 g((unsigned)((max_n + 8 * NT - 1) / (8 * NT)), br.nact);
+    const size_t lds = sizeof(double) * (size_t)max_k;
+    if (f32)
+        hipLaunchKernelGGL((update_kernel_batched<float>), g, dim3(NT), lds, st, static_cast<const float*>(Q), y, br);
+    else
+        hipLaunchKernelGGL((update_kernel_batched<double>), g, dim3(NT), lds, st, static_cast<const double*>(Q), y,
+                           br);
     return hipGetLastError();
 }
 

@@ -1,23 +1,26 @@
 // Row-strip streaming pass kernel template for tall-skinny blocks on gfx950.
 //
-// A workgroup (4 or 8 waves of 64) walks strips of NT consecutive rows (grid-stride over
+// A workgroup (4 waves of 64) walks strips of NT consecutive rows (grid-stride over
 // strips).  Phase A gives each thread one row: the block row is loaded with one coalesced
 // access per column, updated, triangular-solved and written back; the result is staged in
 // LDS column-major (padded leading dimension, so column reads across lanes do not collide
 // in the LDS banks).  Phase B computes the pass's one reduction from the staged strip:
 //
-//  * projection Q^T x: FP64 MFMA (v_mfma_f64_16x16x4) tiles of 16 Q columns.  The waves
-//    split the strip's 16-row groups; per group every lane loads 4 consecutive rows of one
-//    Q column (one 32-byte piece; 16 lanes cover 16 columns, so each 128-byte line is used
-//    whole) and the matching 4 rows of x from LDS, and issues 4 MFMAs per tile.  A 16 x 16
-//    accumulator is 4 doubles per lane, so one launch covers up to 16 * MT columns of Q;
-//    the waves' tiles are summed through LDS once at the end.
-//  * Gram x^T x and the sketches Theta^T x: lanes own strip rows, waves own output rows,
-//    FP64 FMAs into register accumulators.
+//  * projection Q^T x and the sketches Theta^T x: FP64 MFMA (v_mfma_f64_16x16x4) tiles of
+//    16 output rows.  The waves split the strip's 16-row groups; per group every lane
+//    supplies 4 consecutive rows of one output row's operand (Q and a dense Theta are read
+//    as one 32-byte piece per lane, so 16 lanes use each 128-byte line whole; the
+//    sparse-sign Theta is decoded from the rows' hashes) and the matching 4 rows of x from
+//    LDS, and issues 4 MFMAs per tile.  A 16 x 16 accumulator is 4 doubles per lane, so one
+//    launch covers up to 16 * MT output rows; the waves' tiles are summed through LDS once
+//    at the end.
+//  * Gram x^T x: lanes own strip rows, waves own output rows, FP64 FMAs into register
+//    accumulators.
 //
 // Every tall operand is read from HBM once per pass; partial sums stay in registers for the
 // whole sweep and are written once per workgroup at the end.
 #pragma once
+#include "batch.h"
 #include "sko_internal.h"
 
 namespace sko {
@@ -28,18 +31,18 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // Per-(width, reduction) launch configuration.
 template <int W, int RED>
 struct Cfg {
-    // sketch passes use 8 waves (more output rows per launch) while the strip fits LDS
     static constexpr bool SK = RED == RED_SKETCH_SPARSE || RED == RED_SKETCH_DENSE;
-    static constexpr int NT = (SK && W <= 12) ? 512 : 256;
+    // reductions on MFMA tiles: the projection and both sketches
+    static constexpr bool MF = RED == RED_PROJ || SK;
+    static constexpr int NT = 256;
     static constexpr int NWAVE = NT / 64;
     static constexpr int LDX = NT + 1;  // padded LDS leading dimension of the strip
-    // vector reductions: output rows per wave (accumulators per lane = MAXA * W)
-    static constexpr int MAXA_GRAM = (40 / W) > (W + NWAVE - 1) / NWAVE ? (40 / W) : (W + NWAVE - 1) / NWAVE;
-    static constexpr int MAXA_SK = (64 / W) < 8 ? ((64 / W) < 1 ? 1 : (64 / W)) : 8;
-    static constexpr int MAXA = SK ? MAXA_SK : MAXA_GRAM;
-    // MFMA projection: 16-column tiles accumulated by every wave
-    static constexpr int MT = 8;
-    static constexpr int ROWS = RED == RED_PROJ ? 16 * MT : NWAVE * MAXA;
+    // Gram: output rows per wave (accumulators per lane = MAXA * W)
+    static constexpr int MAXA = (40 / W) > (W + NWAVE - 1) / NWAVE ? (40 / W) : (W + NWAVE - 1) / NWAVE;
+    // MFMA tiles of 16 output rows held by every wave (sketch sizes up to 64 rows in one
+    // launch; projections up to 128 previous columns)
+    static constexpr int MT = SK ? 4 : 8;
+    static constexpr int ROWS = MF ? 16 * MT : NWAVE * MAXA;
 };
 
 template <typename T>
@@ -65,20 +68,40 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <int W, typename T, int RED, bool UPD, int NTRSM, bool WRITE>
-__global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs a) {
+// Loads rows row0..row0+3 of one operand column (Q or a dense Theta) into av; rows at or
+// beyond n read as zero.  `vec`: the column pointer is 32-byte aligned for every group.
+template <typename TA>
+__device__ __forceinline__ void load_col4(const TA* q, bool vec, bool full, int64_t row0, int64_t n,
+                                          double av[4]) {
+    if (vec && full) {
+        const double2 v0 = *reinterpret_cast<const double2*>(q);
+        const double2 v1 = *reinterpret_cast<const double2*>(q + 2);
+        av[0] = v0.x;
+        av[1] = v0.y;
+        av[2] = v1.x;
+        av[3] = v1.y;
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) av[u] = (row0 + u < n) ? ldv(q + u) : 0.0;
+    }
+}
+
+// One pass over the rows of `a` by workgroup wg of nwg.
+template <int W, typename T, int RED, bool UPD, int NTRSM, bool WRITE, int MTX>
+__device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const int nwg) {
     using C = Cfg<W, RED>;
     constexpr int NT = C::NT;
     constexpr int LDX = C::LDX;
     constexpr int RPL = NT / 64;
     constexpr int MAXA = C::MAXA;
-    constexpr int MT = C::MT;
+    constexpr int MT = MTX > 0 ? MTX : C::MT;  // MFMA tiles held (fewer: more waves per SIMD)
+    constexpr bool MF = C::MF;
     constexpr bool HAS_RED = RED != RED_NONE;
-    constexpr bool VEC_RED = HAS_RED && RED != RED_PROJ;
+    constexpr bool GRAM = RED == RED_GRAM;
     __shared__ double xs[HAS_RED ? W * LDX : 1];
     __shared__ uint64_t hs[RED == RED_SKETCH_SPARSE ? NT : 1];
     __shared__ double sR[NTRSM > 0 ? NTRSM * W * W : 1];
-    __shared__ double pred[RED == RED_PROJ ? 4 * 64 * C::NWAVE : 1];  // cross-wave tile sums
+    __shared__ double pred[MF ? 4 * 64 * C::NWAVE : 1];  // cross-wave tile sums
     extern __shared__ double sC[];  // UPD coefficients, pu * W doubles (dynamic LDS)
 
     const int tid = threadIdx.x;
@@ -105,37 +128,39 @@ __global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs 
             for (int c = 0; c < W; ++c) rinv[t * W + c] = 1.0 / sR[t * W * W + c * W + c];
     }
 
-    // vector reductions: this wave accumulates output rows [a_lo, a_lo + MAXA)
+    // Gram: this wave accumulates output rows [a_lo, a_lo + MAXA)
     const int a_lo = wave * MAXA;
-    double acc[VEC_RED ? MAXA : 1][W];
+    double acc[GRAM ? MAXA : 1][W];
 #pragma unroll
-    for (int i = 0; i < (VEC_RED ? MAXA : 1); ++i)
+    for (int i = 0; i < (GRAM ? MAXA : 1); ++i)
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[i][c] = 0.0;
-    // MFMA projection accumulators: tile m covers Q columns 16m..16m+15 of this launch
-    double4_t dacc[RED == RED_PROJ ? MT : 1];
+    // MFMA accumulators: tile m covers output rows 16m..16m+15 of this launch
+    double4_t dacc[MF ? MT : 1];
     const int ntiles = (a.red_rows + 15) / 16;
 #pragma unroll
-    for (int m = 0; m < (RED == RED_PROJ ? MT : 1); ++m) dacc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int m = 0; m < (MF ? MT : 1); ++m) dacc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
 
-    // Sparse sketch: slot block t and slot j of each owned output row (wave-uniform).
-    int sk_shift[RED == RED_SKETCH_SPARSE ? MAXA : 1];
-    int sk_slot[RED == RED_SKETCH_SPARSE ? MAXA : 1];
-    int sk_B = 1;
+    // Sparse sketch: the MFMA A operand of lane l is Theta[row][16m + l % 16]; that sketch
+    // row is slot j of hash byte t, so the lane keeps (8t, j) per tile.
+    int sk_shift[RED == RED_SKETCH_SPARSE ? MT : 1];
+    int sk_slot[RED == RED_SKETCH_SPARSE ? MT : 1];
+    unsigned sk_B = 1;
     if constexpr (RED == RED_SKETCH_SPARSE) {
-        sk_B = a.sk_k / a.sk_zeta;
+        sk_B = (unsigned)(a.sk_k / a.sk_zeta);
 #pragma unroll
-        for (int i = 0; i < MAXA; ++i) {
-            const int g = a.red_row0 + a_lo + i;
-            const int t = g / sk_B;
-            const bool live = (a_lo + i) < a.red_rows && t < a.sk_zeta;
-            sk_shift[i] = live ? 8 * t : 0;
-            sk_slot[i] = live ? g - t * sk_B : -1;  // -1 never matches a slot
+        for (int m = 0; m < MT; ++m) {
+            const int loc = 16 * m + (lane & 15);
+            const int g = a.red_row0 + loc;
+            const int t = g / (int)sk_B;
+            const bool live = loc < a.red_rows && t < a.sk_zeta;
+            sk_shift[m] = live ? 8 * t : 0;
+            sk_slot[m] = live ? g - t * (int)sk_B : -1;  // -1 never matches a slot
         }
     }
 
     const int64_t nstrips = (n + NT - 1) / NT;
-    for (int64_t s = blockIdx.x; s < nstrips; s += gridDim.x) {
+    for (int64_t s = wg; s < nstrips; s += nwg) {
         const int64_t base = s * NT;
         // ---------------- phase A: one row per thread ----------------
         {
@@ -199,36 +224,44 @@ __global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs 
         }
         if constexpr (HAS_RED) {
             __syncthreads();
-            if constexpr (RED == RED_PROJ) {
-                // ---------------- phase B, MFMA projection ----------------
+            if constexpr (MF) {
+                // ---------------- phase B, MFMA tiles ----------------
                 const int g = lane >> 4, ci = lane & 15;
                 const T* Qp = static_cast<const T*>(a.Qp);
+                const double* Th = a.theta;
                 // 32-byte row pieces can be read as two 16-byte vectors when aligned
-                const bool vec = sizeof(T) == 8 && (a.ldqp % 4) == 0 && ((uintptr_t)Qp % 32) == 0;
+                bool vec = false;
+                if constexpr (RED == RED_PROJ)
+                    vec = sizeof(T) == 8 && (a.ldqp % 4) == 0 && ((uintptr_t)Qp % 32) == 0;
+                if constexpr (RED == RED_SKETCH_DENSE) vec = (a.ldtheta % 4) == 0 && ((uintptr_t)Th % 32) == 0;
                 for (int gam = wave; gam < NT / 16; gam += C::NWAVE) {
                     const int r0 = gam * 16 + 4 * g;  // strip-local rows r0..r0+3 for this lane
                     const bool full = base + r0 + 3 < n;
                     double bv[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) bv[u] = (ci < W) ? xs[ci * LDX + r0 + u] : 0.0;
+                    uint64_t h[RED == RED_SKETCH_SPARSE ? 4 : 1];
+                    if constexpr (RED == RED_SKETCH_SPARSE) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) h[u] = hs[r0 + u];
+                    }
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
                         if (m < ntiles) {
                             const int col = 16 * m + ci;
                             double av[4] = {0.0, 0.0, 0.0, 0.0};
-                            if (col < a.red_rows) {
-                                const T* q = Qp + (int64_t)col * a.ldqp + base + r0;
-                                if (vec && full) {
-                                    const double2 v0 = *reinterpret_cast<const double2*>(q);
-                                    const double2 v1 = *reinterpret_cast<const double2*>(q + 2);
-                                    av[0] = v0.x;
-                                    av[1] = v0.y;
-                                    av[2] = v1.x;
-                                    av[3] = v1.y;
-                                } else {
+                            if constexpr (RED == RED_SKETCH_SPARSE) {
 #pragma unroll
-                                    for (int u = 0; u < 4; ++u) av[u] = (base + r0 + u < n) ? ldv(q + u) : 0.0;
+                                for (int u = 0; u < 4; ++u) {
+                                    const unsigned b = (unsigned)(h[u] >> sk_shift[m]) & 0xffu;
+                                    const int slot = (int)(((b >> 1) * sk_B) >> 7);
+                                    av[u] = (slot == sk_slot[m]) ? ((b & 1u) ? -1.0 : 1.0) : 0.0;
                                 }
+                            } else if (col < a.red_rows) {
+                                if constexpr (RED == RED_PROJ)
+                                    load_col4(Qp + (int64_t)col * a.ldqp + base + r0, vec, full, base + r0, n, av);
+                                else
+                                    load_col4(Th + (int64_t)col * a.ldtheta + base + r0, vec, full, base + r0, n, av);
                             }
 #pragma unroll
                             for (int u = 0; u < 4; ++u)
@@ -236,54 +269,22 @@ __global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs 
                         }
                     }
                 }
-            } else {
+            } else if constexpr (GRAM) {
                 // ---------------- phase B, lanes over rows, waves over output rows ----------------
 #pragma unroll 2
                 for (int r = 0; r < RPL; ++r) {
                     const int rr = r * 64 + lane;
-                    const int64_t row = base + rr;
                     double x[W];
 #pragma unroll
                     for (int c = 0; c < W; ++c) x[c] = xs[c * LDX + rr];
-                    if constexpr (RED == RED_GRAM) {
 #pragma unroll
-                        for (int i = 0; i < MAXA; ++i) {
-                            const int al = a_lo + i;
-                            if (al < a.red_rows) {
-                                const double xa = xs[(a.red_row0 + al) * LDX + rr];
+                    for (int i = 0; i < MAXA; ++i) {
+                        const int al = a_lo + i;
+                        if (al < a.red_rows) {
+                            const double xa = xs[(a.red_row0 + al) * LDX + rr];
 #pragma unroll
-                                for (int c = 0; c < W; ++c) acc[i][c] += xa * x[c];
-                            }
+                            for (int c = 0; c < W; ++c) acc[i][c] += xa * x[c];
                         }
-                    } else if constexpr (RED == RED_SKETCH_SPARSE) {
-                        // decode the row's slot and sign once per hash block this wave covers
-                        // (sk_shift is wave-uniform and non-decreasing in i)
-                        const uint64_t h = hs[rr];
-                        int slot = -2;
-                        double sgn = 0.0;
-#pragma unroll
-                        for (int i = 0; i < MAXA; ++i) {
-                            if (i == 0 || sk_shift[i] != sk_shift[i - 1]) {
-                                const unsigned b = (unsigned)(h >> sk_shift[i]) & 0xffu;
-                                slot = (int)(((b >> 1) * (unsigned)sk_B) >> 7);
-                                sgn = (b & 1u) ? -1.0 : 1.0;
-                            }
-                            const double coef = (slot == sk_slot[i]) ? sgn : 0.0;
-#pragma unroll
-                            for (int c = 0; c < W; ++c) acc[i][c] = fma(coef, x[c], acc[i][c]);
-                        }
-                    } else if constexpr (RED == RED_SKETCH_DENSE) {
-                        const double* th = a.theta + row;
-                        double tv[MAXA];
-#pragma unroll
-                        for (int i = 0; i < MAXA; ++i) {
-                            const int al = a_lo + i;
-                            tv[i] = (al < a.red_rows && row < n) ? th[(int64_t)al * a.ldtheta] : 0.0;
-                        }
-#pragma unroll
-                        for (int i = 0; i < MAXA; ++i)
-#pragma unroll
-                            for (int c = 0; c < W; ++c) acc[i][c] += tv[i] * x[c];
                     }
                 }
             }
@@ -291,11 +292,11 @@ __global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs 
         }
     }
 
-    if constexpr (RED == RED_PROJ) {
+    if constexpr (MF) {
         // v_mfma_f64_16x16x4 output layout (measured on gfx950): D[i][j] of a tile sits in
         // lane j + 16 * (i % 4), element i / 4.  The waves' tiles are summed through LDS in
         // wave order.
-        double* out = a.partials + (int64_t)blockIdx.x * a.part_stride;
+        double* out = a.partials + (int64_t)wg * a.part_stride;
         const int j = lane & 15;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
@@ -314,8 +315,8 @@ __global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs 
             }
             __syncthreads();
         }
-    } else if constexpr (HAS_RED) {
-        double* out = a.partials + (int64_t)blockIdx.x * a.part_stride;
+    } else if constexpr (GRAM) {
+        double* out = a.partials + (int64_t)wg * a.part_stride;
 #pragma unroll
         for (int i = 0; i < MAXA; ++i) {
             const int al = a_lo + i;
@@ -329,7 +330,36 @@ __global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs 
     }
 }
 
+template <int W, typename T, int RED, bool UPD, int NTRSM, bool WRITE, int MTX = 0>
+__global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs a) {
+    pass_body<W, T, RED, UPD, NTRSM, WRITE, MTX>(a, blockIdx.x, gridDim.x);
+}
+
+// Batched form: the template arguments are moved to the system of blockIdx.y.
+template <int W, typename T, int RED, bool UPD, int NTRSM, bool WRITE, int MTX = 0>
+__global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel_batched(const PassArgs t, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    PassArgs a = t;
+    a.n = d.n;
+    a.Y = batch_ptr(br, sys, d, t.Y);
+    a.ldy = batch_ld(br, d, t.ldy);
+    a.Qu = batch_ptr(br, sys, d, t.Qu);
+    a.ldqu = batch_ld(br, d, t.ldqu);
+    a.Cu = batch_ptr(br, sys, d, t.Cu);
+    a.R1 = batch_ptr(br, sys, d, t.R1);
+    a.R2 = batch_ptr(br, sys, d, t.R2);
+    a.X = batch_ptr(br, sys, d, t.X);
+    a.ldx = batch_ld(br, d, t.ldx);
+    a.Qp = batch_ptr(br, sys, d, t.Qp);
+    a.ldqp = batch_ld(br, d, t.ldqp);
+    a.partials = batch_ptr(br, sys, d, t.partials);
+    a.sk_seed = d.seed;
+    pass_body<W, T, RED, UPD, NTRSM, WRITE, MTX>(a, blockIdx.x, gridDim.x);
+}
+
 using KernelPtr = void (*)(const PassArgs);
+using BatchedKernelPtr = void (*)(const PassArgs, const BatchReloc);
 
 // The pass variants the orchestration launches: (reduction, update, solves, write).
 template <int W, typename T>
@@ -337,8 +367,10 @@ KernelPtr select_w(const PassKey& k) {
     const int r = k.red;
     const bool u = k.upd, wr = k.write;
     const int t = k.ntrsm;
+    const bool few = k.tiles >= 1 && k.tiles <= 4;  // projection fits 4 tiles
     if (!u && t == 0 && !wr) {
-        if (r == RED_PROJ) return &pass_kernel<W, T, RED_PROJ, false, 0, false>;
+        if (r == RED_PROJ)
+            return few ? &pass_kernel<W, T, RED_PROJ, false, 0, false, 4> : &pass_kernel<W, T, RED_PROJ, false, 0, false>;
         if (r == RED_GRAM) return &pass_kernel<W, T, RED_GRAM, false, 0, false>;
         if (r == RED_SKETCH_SPARSE) return &pass_kernel<W, T, RED_SKETCH_SPARSE, false, 0, false>;
         if (r == RED_SKETCH_DENSE) return &pass_kernel<W, T, RED_SKETCH_DENSE, false, 0, false>;
@@ -351,12 +383,34 @@ KernelPtr select_w(const PassKey& k) {
     }
     if (!u && t == 1 && !wr && r == RED_GRAM) return &pass_kernel<W, T, RED_GRAM, false, 1, false>;
     if (!u && t == 2 && wr) {
-        if (r == RED_PROJ) return &pass_kernel<W, T, RED_PROJ, false, 2, true>;
+        if (r == RED_PROJ)
+            return few ? &pass_kernel<W, T, RED_PROJ, false, 2, true, 4> : &pass_kernel<W, T, RED_PROJ, false, 2, true>;
         if (r == RED_GRAM) return &pass_kernel<W, T, RED_GRAM, false, 2, true>;
     }
     if (r == RED_NONE && t == 1 && wr) {
         if (!u) return &pass_kernel<W, T, RED_NONE, false, 1, true>;
         return &pass_kernel<W, T, RED_NONE, true, 1, true>;
+    }
+    return nullptr;
+}
+
+// The batched variants the lock-step two-stage solver launches.
+template <int W, typename T>
+BatchedKernelPtr select_w_batched(const PassKey& k) {
+    const int r = k.red;
+    const bool u = k.upd, wr = k.write;
+    const int t = k.ntrsm;
+    const bool few = k.tiles >= 1 && k.tiles <= 4;
+    if (!u && t == 0 && !wr) {
+        if (r == RED_PROJ)
+            return few ? &pass_kernel_batched<W, T, RED_PROJ, false, 0, false, 4>
+                       : &pass_kernel_batched<W, T, RED_PROJ, false, 0, false>;
+        if (r == RED_SKETCH_SPARSE) return &pass_kernel_batched<W, T, RED_SKETCH_SPARSE, false, 0, false>;
+    }
+    if (u && t == 0 && wr && r == RED_SKETCH_SPARSE) return &pass_kernel_batched<W, T, RED_SKETCH_SPARSE, true, 0, true>;
+    if (r == RED_NONE && t == 1 && wr) {
+        if (!u) return &pass_kernel_batched<W, T, RED_NONE, false, 1, true>;
+        return &pass_kernel_batched<W, T, RED_NONE, true, 1, true>;
     }
     return nullptr;
 }
@@ -388,6 +442,7 @@ int threads_w(int red) {
 // Per-width selectors, one translation unit each (pass_wNN.hip).
 struct PassSel {
     passk::KernelPtr fn;
+    passk::BatchedKernelPtr fnb;  // batched form (null where not instantiated)
     int threads;  // workgroup size (= strip rows)
     int rows;     // reduction rows one launch can produce
 };

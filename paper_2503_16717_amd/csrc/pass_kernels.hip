@@ -23,7 +23,7 @@ PassSel select_kernel(const PassKey& k) {
         case 14: return select_pass_w14(k);
         case 15: return select_pass_w15(k);
         case 16: return select_pass_w16(k);
-        default: return PassSel{nullptr, 0, 0};
+        default: return PassSel{nullptr, nullptr, 0, 0};
     }
 }
 
@@ -51,14 +51,19 @@ int pass_grid_cap(const PassKey& key) {
     return per_cu * cus;
 }
 
-hipError_t launch_pass(const PassKey& key, const PassArgs& args, int grid, hipStream_t stream) {
+hipError_t launch_pass(const PassKey& key, const PassArgs& args, int grid, hipStream_t stream, const BatchReloc* br) {
     PassSel s = select_kernel(key);
-    if (!s.fn) return hipErrorInvalidValue;
+    if (!s.fn || (br && !s.fnb)) return hipErrorInvalidValue;
     if (key.upd && args.pu * key.W > kMaxUpdCoef) return hipErrorInvalidValue;
     if (key.red != RED_NONE && args.red_rows > s.rows) return hipErrorInvalidValue;
     if (grid < 1) return hipErrorInvalidValue;
     const size_t lds = key.upd ? sizeof(double) * (size_t)args.pu * key.W : 0;
-    hipLaunchKernelGGL(s.fn, dim3(grid), dim3(s.threads), lds, stream, args);
+    if (br) {
+        if (br->nact < 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(s.fnb, dim3(grid, br->nact), dim3(s.threads), lds, stream, args, *br);
+    } else {
+        hipLaunchKernelGGL(s.fn, dim3(grid), dim3(s.threads), lds, stream, args);
+    }
     return hipGetLastError();
 }
 

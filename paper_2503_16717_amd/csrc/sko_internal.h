@@ -10,6 +10,8 @@
 
 namespace sko {
 
+struct BatchReloc;  // batched launches (batch.h)
+
 // ---------------------------------------------------------------------------
 // Row-strip pass: one streaming sweep over n rows of a tall-skinny block.
 //
@@ -67,10 +69,13 @@ struct PassKey {
     bool upd;
     int ntrsm;
     bool write;
+    int tiles = 0;     // projection: 16-row MFMA tiles one launch needs (0: the maximum)
 };
 
-// Launch one pass over all n rows with `grid` workgroups (grid <= pass_grid_cap()).
-hipError_t launch_pass(const PassKey& key, const PassArgs& args, int grid, hipStream_t stream);
+// Launch one pass over all n rows with `grid` workgroups (grid <= pass_grid_cap()).  With
+// `br`, one launch serves every active system of a batch (grid workgroups each).
+hipError_t launch_pass(const PassKey& key, const PassArgs& args, int grid, hipStream_t stream,
+                       const BatchReloc* br = nullptr);
 // Reduction rows one launch of reduction kind `red` can produce for panel width W.
 int pass_rows_per_launch(int W, int red);
 // Rows per strip (= threads per workgroup) of a pass variant.
@@ -142,20 +147,22 @@ struct ReduceArgs {
 // Number of workgroups launch_reduce uses for `count` reduced values.
 int reduce_grid(int count);
 
-hipError_t launch_reduce(const ReduceArgs& args, hipStream_t stream);
+hipError_t launch_reduce(const ReduceArgs& args, hipStream_t stream, const BatchReloc* br = nullptr);
 
 // Small dense kernels used outside a reduction.
 // Big-panel helpers (two-stage): C = A^T B for tall A (n x ma), B (n x nb), ma, nb <= 64.
 hipError_t launch_skinny_gemm_tn(int64_t n, const void* A, int64_t lda, int ma,
                                  const void* B, int64_t ldb, int nb, bool f32,
-                                 double* partials, int grid, hipStream_t stream);
+                                 double* partials, int grid, hipStream_t stream,
+                                 const BatchReloc* br = nullptr);
 int skinny_gemm_grid_cap();
 
 // Row-wise X = (Y - Qu Cu) * R^{-1} for wide blocks (w <= 64); used by the big-panel
 // close of the two-stage scheme.
 hipError_t launch_wide_rowop(int64_t n, int W, bool f32, const void* Y, int64_t ldy,
                              const void* Qu, int64_t ldqu, int pu, const double* Cu,
-                             const double* R, void* X, int64_t ldx, hipStream_t stream);
+                             const double* R, void* X, int64_t ldx, hipStream_t stream,
+                             const BatchReloc* br = nullptr);
 
 // Small matrix helpers on the device (single workgroup).
 hipError_t launch_small_matmul_upper(int w, const double* A, const double* B, double* C,

@@ -5,6 +5,7 @@
 // Partials are summed in a fixed order (workgroup g in strides of 32, then the 32
 // part sums in order), so results are bitwise reproducible for a given grid.  All
 // small factorisations are in double precision regardless of the storage type.
+#include "batch.h"
 #include "sko_internal.h"
 
 #include <cmath>
@@ -250,7 +251,7 @@ __device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* r
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(RT) reduce_kernel(const ReduceArgs a) {
+__device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
     extern __shared__ double lds[];
     __shared__ double part[RT];
     __shared__ double red[4 * 16];
@@ -306,6 +307,30 @@ __global__ void __launch_bounds__(RT) reduce_kernel(const ReduceArgs a) {
     }
 }
 
+__global__ void __launch_bounds__(RT) reduce_kernel(const ReduceArgs a) { reduce_body(a); }
+
+// Batched form: the template arguments are moved to the system of blockIdx.y.
+__global__ void __launch_bounds__(RT) reduce_kernel_batched(const ReduceArgs t, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    ReduceArgs a = t;
+    a.partials = batch_ptr(br, sys, d, t.partials);
+    a.counter = batch_ptr(br, sys, d, t.counter);
+    SmallArgs& m = a.small;
+    m.out = batch_ptr(br, sys, d, t.small.out);
+    m.R = batch_ptr(br, sys, d, t.small.R);
+    m.status = batch_ptr(br, sys, d, t.small.status);
+    m.Yacc = batch_ptr(br, sys, d, t.small.Yacc);
+    m.r = batch_ptr(br, sys, d, t.small.r);
+    m.Rbar = batch_ptr(br, sys, d, t.small.Rbar);
+    m.Ra = batch_ptr(br, sys, d, t.small.Ra);
+    m.Rb = batch_ptr(br, sys, d, t.small.Rb);
+    m.C1 = batch_ptr(br, sys, d, t.small.C1);
+    m.C2 = batch_ptr(br, sys, d, t.small.C2);
+    m.Rout = batch_ptr(br, sys, d, t.small.Rout);
+    reduce_body(a);
+}
+
 __global__ void matmul_upper_kernel(int w, const double* A, const double* B, double* C) {
     for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
         const int a = idx % w, c = idx / w;
@@ -319,7 +344,7 @@ __global__ void matmul_upper_kernel(int w, const double* A, const double* B, dou
 
 int reduce_grid(int count) { return (count + EPW - 1) / EPW; }
 
-hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream) {
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream, const BatchReloc* br) {
     if (a.count <= 0 || a.G <= 0) return hipErrorInvalidValue;
     const SmallArgs& s = a.small;
     size_t lds = 0;
@@ -336,7 +361,12 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream) {
     }
     if (lds > 60 * 1024) return hipErrorInvalidValue;
     const int grid = reduce_grid(a.count);
-    hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(RT), lds, stream, a);
+    if (br) {
+        if (br->nact < 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(reduce_kernel_batched, dim3(grid, br->nact), dim3(RT), lds, stream, a, *br);
+    } else {
+        hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(RT), lds, stream, a);
+    }
     return hipGetLastError();
 }
 

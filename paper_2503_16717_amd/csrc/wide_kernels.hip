@@ -7,6 +7,7 @@
 //               ma, nb <= 64: 32-row strips of A and B staged in LDS, each of 256 threads
 //               accumulating a 4 x 4 tile of C in registers.  For the Gram matrix (A == B)
 //               only tiles on or above the diagonal are computed.
+#include "batch.h"
 #include "sko_internal.h"
 
 namespace sko {
@@ -19,11 +20,30 @@ __device__ __forceinline__ double ldv(const T* p) {
 
 constexpr int ROW_NT = 256;
 
+struct RowopArgs {
+    int64_t n;
+    int w;
+    const void* Y;
+    int64_t ldy;
+    const void* Qu;
+    int64_t ldqu;
+    int pu;
+    const double* Cu;
+    const double* R;
+    void* X;
+    int64_t ldx;
+};
+
 template <int WB, typename T, bool UPD, bool TRSM>
-__global__ void __launch_bounds__(ROW_NT) wide_rowop_kernel(int64_t n, int w, const T* __restrict__ Y, int64_t ldy,
-                                                            const T* __restrict__ Qu, int64_t ldqu, int pu,
-                                                            const double* __restrict__ Cu,
-                                                            const double* __restrict__ R, T* X, int64_t ldx) {
+__device__ __forceinline__ void rowop_body(const RowopArgs& ra) {
+    const int64_t n = ra.n;
+    const int w = ra.w, pu = ra.pu;
+    const T* __restrict__ Y = static_cast<const T*>(ra.Y);
+    const T* __restrict__ Qu = static_cast<const T*>(ra.Qu);
+    const double* __restrict__ Cu = ra.Cu;
+    const double* __restrict__ R = ra.R;
+    T* X = static_cast<T*>(ra.X);
+    const int64_t ldy = ra.ldy, ldqu = ra.ldqu, ldx = ra.ldx;
     extern __shared__ double lds[];
     double* sR = lds;                          // w * w
     double* sC = lds + (TRSM ? w * w : 0);     // pu * w
@@ -33,8 +53,7 @@ __global__ void __launch_bounds__(ROW_NT) wide_rowop_kernel(int64_t n, int w, co
     if (UPD)
         for (int i = tid; i < pu * w; i += ROW_NT) sC[i] = Cu[i];
     __syncthreads();
-    const int64_t row = (int64_t)blockIdx.x * ROW_NT + tid;
-    if (row >= n) return;
+    for (int64_t row = (int64_t)blockIdx.x * ROW_NT + tid; row < n; row += (int64_t)gridDim.x * ROW_NT) {
     double x[WB];
 #pragma unroll
     for (int c = 0; c < WB; ++c) x[c] = (c < w) ? ldv(Y + row + (int64_t)c * ldy) : 0.0;
@@ -60,16 +79,54 @@ __global__ void __launch_bounds__(ROW_NT) wide_rowop_kernel(int64_t n, int w, co
 #pragma unroll
     for (int c = 0; c < WB; ++c)
         if (c < w) X[row + (int64_t)c * ldx] = static_cast<T>(x[c]);
+    }
+}
+
+template <int WB, typename T, bool UPD, bool TRSM>
+__global__ void __launch_bounds__(ROW_NT) wide_rowop_kernel(const RowopArgs ra) {
+    rowop_body<WB, T, UPD, TRSM>(ra);
+}
+
+template <int WB, typename T, bool UPD, bool TRSM>
+__global__ void __launch_bounds__(ROW_NT) wide_rowop_kernel_batched(const RowopArgs t, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    RowopArgs ra = t;
+    ra.n = d.n;
+    ra.Y = batch_ptr(br, sys, d, t.Y);
+    ra.ldy = batch_ld(br, d, t.ldy);
+    ra.Qu = batch_ptr(br, sys, d, t.Qu);
+    ra.ldqu = batch_ld(br, d, t.ldqu);
+    ra.Cu = batch_ptr(br, sys, d, t.Cu);
+    ra.R = batch_ptr(br, sys, d, t.R);
+    ra.X = batch_ptr(br, sys, d, t.X);
+    ra.ldx = batch_ld(br, d, t.ldx);
+    rowop_body<WB, T, UPD, TRSM>(ra);
 }
 
 constexpr int GT = 256;   // threads
 constexpr int GS = 32;    // rows per strip
 constexpr int GLD = 65;   // padded LDS row length
 
+struct GemmArgs {
+    int64_t n;
+    const void* A;
+    int64_t lda;
+    int ma;
+    const void* B;
+    int64_t ldb;
+    int nb;
+    double* partials;
+    int64_t stride;
+};
+
 template <typename T, bool SYM>
-__global__ void __launch_bounds__(GT) wide_gemm_tn_kernel(int64_t n, const T* __restrict__ A, int64_t lda, int ma,
-                                                          const T* __restrict__ B, int64_t ldb, int nb,
-                                                          double* partials, int64_t stride) {
+__device__ __forceinline__ void gemm_body(const GemmArgs& ga) {
+    const int64_t n = ga.n;
+    const T* __restrict__ A = static_cast<const T*>(ga.A);
+    const T* __restrict__ B = static_cast<const T*>(ga.B);
+    const int64_t lda = ga.lda, ldb = ga.ldb;
+    const int ma = ga.ma, nb = ga.nb;
     __shared__ double As[GS * GLD];
     __shared__ double Bs[SYM ? 1 : GS * GLD];
     const int tid = threadIdx.x;
@@ -114,7 +171,7 @@ __global__ void __launch_bounds__(GT) wide_gemm_tn_kernel(int64_t n, const T* __
         }
         __syncthreads();
     }
-    double* out = partials + (int64_t)blockIdx.x * stride;
+    double* out = ga.partials + (int64_t)blockIdx.x * ga.stride;
     if (active) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -126,43 +183,73 @@ __global__ void __launch_bounds__(GT) wide_gemm_tn_kernel(int64_t n, const T* __
     }
 }
 
+template <typename T, bool SYM>
+__global__ void __launch_bounds__(GT) wide_gemm_tn_kernel(const GemmArgs ga) {
+    gemm_body<T, SYM>(ga);
+}
+
+template <typename T, bool SYM>
+__global__ void __launch_bounds__(GT) wide_gemm_tn_kernel_batched(const GemmArgs t, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    GemmArgs ga = t;
+    ga.n = d.n;
+    ga.A = batch_ptr(br, sys, d, t.A);
+    ga.lda = batch_ld(br, d, t.lda);
+    ga.B = batch_ptr(br, sys, d, t.B);
+    ga.ldb = batch_ld(br, d, t.ldb);
+    ga.partials = batch_ptr(br, sys, d, t.partials);
+    gemm_body<T, SYM>(ga);
+}
+
+template <int WB, typename T, bool UPD, bool TRSM>
+void rowop_launch(const RowopArgs& ra, int grid, size_t lds, hipStream_t st, const BatchReloc* br) {
+    if (br)
+        hipLaunchKernelGGL((wide_rowop_kernel_batched<WB, T, UPD, TRSM>), dim3(grid, br->nact), dim3(ROW_NT), lds, st,
+                           ra, *br);
+    else
+        hipLaunchKernelGGL((wide_rowop_kernel<WB, T, UPD, TRSM>), dim3(grid), dim3(ROW_NT), lds, st, ra);
+}
+
 template <int WB, typename T>
-hipError_t rowop_dispatch(int64_t n, int w, const void* Y, int64_t ldy, const void* Qu, int64_t ldqu, int pu,
-                          const double* Cu, const double* R, void* X, int64_t ldx, hipStream_t st) {
-    const int grid = (int)((n + ROW_NT - 1) / ROW_NT);
-    const size_t lds = sizeof(double) * ((R ? (size_t)w * w : 0) + (pu > 0 ? (size_t)pu * w : 0));
-    const T* y = static_cast<const T*>(Y);
-    const T* q = static_cast<const T*>(Qu);
-    T* x = static_cast<T*>(X);
-    if (pu > 0 && R)
-        hipLaunchKernelGGL((wide_rowop_kernel<WB, T, true, true>), dim3(grid), dim3(ROW_NT), lds, st, n, w, y, ldy, q,
-                           ldqu, pu, Cu, R, x, ldx);
-    else if (pu > 0)
-        hipLaunchKernelGGL((wide_rowop_kernel<WB, T, true, false>), dim3(grid), dim3(ROW_NT), lds, st, n, w, y, ldy, q,
-                           ldqu, pu, Cu, R, x, ldx);
-    else if (R)
-        hipLaunchKernelGGL((wide_rowop_kernel<WB, T, false, true>), dim3(grid), dim3(ROW_NT), lds, st, n, w, y, ldy, q,
-                           ldqu, pu, Cu, R, x, ldx);
+hipError_t rowop_dispatch(const RowopArgs& ra, hipStream_t st, const BatchReloc* br) {
+    // one row per thread; in a batched launch (many systems at once) each workgroup takes
+    // up to 8 strips of its system
+    const int64_t strips = (ra.n + ROW_NT - 1) / ROW_NT;
+    const int grid = (int)(br ? (strips + 7) / 8 : strips);
+    const size_t lds = sizeof(double) * ((ra.R ? (size_t)ra.w * ra.w : 0) + (ra.pu > 0 ? (size_t)ra.pu * ra.w : 0));
+    if (ra.pu > 0 && ra.R)
+        rowop_launch<WB, T, true, true>(ra, grid, lds, st, br);
+    else if (ra.pu > 0)
+        rowop_launch<WB, T, true, false>(ra, grid, lds, st, br);
+    else if (ra.R)
+        rowop_launch<WB, T, false, true>(ra, grid, lds, st, br);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
+template <typename T, bool SYM>
+void gemm_launch(const GemmArgs& ga, int grid, hipStream_t st, const BatchReloc* br) {
+    if (br)
+        hipLaunchKernelGGL((wide_gemm_tn_kernel_batched<T, SYM>), dim3(grid, br->nact), dim3(GT), 0, st, ga, *br);
+    else
+        hipLaunchKernelGGL((wide_gemm_tn_kernel<T, SYM>), dim3(grid), dim3(GT), 0, st, ga);
+}
+
 }  // namespace
 
 hipError_t launch_wide_rowop(int64_t n, int W, bool f32, const void* Y, int64_t ldy, const void* Qu, int64_t ldqu,
-                             int pu, const double* Cu, const double* R, void* X, int64_t ldx, hipStream_t st) {
+                             int pu, const double* Cu, const double* R, void* X, int64_t ldx, hipStream_t st,
+                             const BatchReloc* br) {
     if (W < 1 || W > 64 || n < 1) return hipErrorInvalidValue;
+    if (br && br->nact < 1) return hipErrorInvalidValue;
     if (sizeof(double) * ((R ? (size_t)W * W : 0) + (size_t)(pu > 0 ? pu : 0) * W) > 60 * 1024)
         return hipErrorInvalidValue;
-    if (W <= 16)
-        return f32 ? rowop_dispatch<16, float>(n, W, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx, st)
-                   : rowop_dispatch<16, double>(n, W, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx, st);
-    if (W <= 32)
-        return f32 ? rowop_dispatch<32, float>(n, W, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx, st)
-                   : rowop_dispatch<32, double>(n, W, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx, st);
-    return f32 ? rowop_dispatch<64, float>(n, W, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx, st)
-               : rowop_dispatch<64, double>(n, W, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx, st);
+    const RowopArgs ra{n, W, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx};
+    if (W <= 16) return f32 ? rowop_dispatch<16, float>(ra, st, br) : rowop_dispatch<16, double>(ra, st, br);
+    if (W <= 32) return f32 ? rowop_dispatch<32, float>(ra, st, br) : rowop_dispatch<32, double>(ra, st, br);
+    return f32 ? rowop_dispatch<64, float>(ra, st, br) : rowop_dispatch<64, double>(ra, st, br);
 }
 
 int skinny_gemm_grid_cap() {
@@ -173,28 +260,21 @@ int skinny_gemm_grid_cap() {
 }
 
 hipError_t launch_skinny_gemm_tn(int64_t n, const void* A, int64_t lda, int ma, const void* B, int64_t ldb, int nb,
-                                 bool f32, double* partials, int grid, hipStream_t st) {
+                                 bool f32, double* partials, int grid, hipStream_t st, const BatchReloc* br) {
     if (ma < 1 || nb < 1 || ma > 64 || nb > 64 || grid < 1) return hipErrorInvalidValue;
+    if (br && br->nact < 1) return hipErrorInvalidValue;
     const bool sym = (A == B) && (lda == ldb) && (ma == nb);
-    const int64_t stride = (int64_t)ma * nb;
+    const GemmArgs ga{n, A, lda, ma, B, ldb, nb, partials, (int64_t)ma * nb};
     if (f32) {
-        const float* a = static_cast<const float*>(A);
-        const float* b = static_cast<const float*>(B);
         if (sym)
-            hipLaunchKernelGGL((wide_gemm_tn_kernel<float, true>), dim3(grid), dim3(GT), 0, st, n, a, lda, ma, b, ldb,
-                               nb, partials, stride);
+            gemm_launch<float, true>(ga, grid, st, br);
         else
-            hipLaunchKernelGGL((wide_gemm_tn_kernel<float, false>), dim3(grid), dim3(GT), 0, st, n, a, lda, ma, b,
-                               ldb, nb, partials, stride);
+            gemm_launch<float, false>(ga, grid, st, br);
     } else {
-        const double* a = static_cast<const double*>(A);
-        const double* b = static_cast<const double*>(B);
         if (sym)
-            hipLaunchKernelGGL((wide_gemm_tn_kernel<double, true>), dim3(grid), dim3(GT), 0, st, n, a, lda, ma, b,
-                               ldb, nb, partials, stride);
+            gemm_launch<double, true>(ga, grid, st, br);
         else
-            hipLaunchKernelGGL((wide_gemm_tn_kernel<double, false>), dim3(grid), dim3(GT), 0, st, n, a, lda, ma, b,
-                               ldb, nb, partials, stride);
+            gemm_launch<double, false>(ga, grid, st, br);
     }
     return hipGetLastError();
 }
