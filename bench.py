@@ -241,7 +241,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 20)
+    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 21)
     ap.add_argument("--n", type=int, default=N_ROWS, help="rows (default 2^24)")
     ap.add_argument("--skip-gmres", action="store_true", help="skip the GMRES time-to-solution runs")
     ap.add_argument("--skip-two-stage", action="store_true", help="skip the two-stage orthogonalisation run")
@@ -288,7 +288,7 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    R_first = R.copy()
+    R_first = R.copy() if args.warmup > 0 else None
     log("warmup done; timing")
     ctx.sko_profile_enable(True)
     torch.cuda.synchronize()
@@ -322,8 +322,9 @@ def main() -> int:
     # correctness guard on the benchmarked output: finite Q samples, a positive diagonal,
     # and the same R bit for bit as the first warm-up step
     Qs = Qd[:: max(1, n // 65536)]
-    if not (torch.isfinite(Qs).all().item() and np.all(np.diag(R) > 0) and np.array_equal(R, R_first)):
-        log(f"R check failed: diag min {np.diag(R).min():.3e}, equal to first step: {np.array_equal(R, R_first)}")
+    same = R_first is None or np.array_equal(R, R_first)
+    if not (torch.isfinite(Qs).all().item() and np.all(np.diag(R) > 0) and same):
+        log(f"R check failed: diag min {np.diag(R).min():.3e}, equal to first step: {same}")
         log("diag: " + " ".join(f"{v:.3e}" for v in np.diag(R)))
         return 3
 
