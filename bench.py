@@ -338,14 +338,22 @@ def main() -> int:
         for _ in range(args.warmup):
             step(opts2)
         torch.cuda.synchronize()
+        ctx.sko_profile_enable(True)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step(opts2)
         torch.cuda.synchronize()
         ms2 = (time.perf_counter() - t0) / args.steps * 1e3
+        ctx.sko_profile_enable(False)
+        stats2 = ctx.sko_profile_read()
         ab2 = alg_bytes_two_stage(n, NB, W, 6)
         extra["two_stage"] = {"ms_per_step": round(ms2, 4), "GBps": round(ab2 / (ms2 * 1e-3) / 1e9, 2),
-                              "alg_bytes_per_step": ab2, "s_hat": 30, "big_panel_width": 36}
+                              "alg_bytes_per_step": ab2, "s_hat": 30, "big_panel_width": 36,
+                              "kernels_top": [{"name": q["name"], "ms_per_step": round(q["total_ms"] / args.steps, 4),
+                                               "launches_per_step": q["launches"] / args.steps,
+                                               "GBps": round(q["bytes"] / (q["total_ms"] * 1e-3) / 1e9, 1)
+                                               if q["total_ms"] > 0 else None} for q in stats2[:10]]}
         log(f"two-stage: {ms2:.3f} ms/step")
     extra["copy_ceiling_GBps"] = round(copy_ceiling(torch), 1)
     ctx.close()
