@@ -191,7 +191,7 @@ def copy_ceiling(torch, nbytes: int = 1 << 31, reps: int = 20) -> float:
 
 
 PASS_SOURCE = os.path.join(ROOT, "paper_2503_16717_amd", "csrc", "pass_impl.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass_kernels.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass_kernels_blockorth_n2p24_w6.md")
 
 
 def pass_source_digest() -> str:

@@ -1,0 +1,119 @@
+"""Summaries of rocprofv3 output for the pass kernels (markdown tables on stdout).
+
+    python -m paper_2503_16717_amd.rocprof_summary stats KERNEL_STATS_CSV [--top N]
+    python -m paper_2503_16717_amd.rocprof_summary traffic --fetch CSV --write CSV \\
+        --copy-fetch CSV --copy-write CSV --copy-bytes BYTES
+
+`stats` lists the kernels of a `--kernel-trace --stats` run by total time.  `traffic`
+turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs (KiB per dispatch) into HBM bytes
+per launch of each pass kernel.  Each counter is scaled by the factor that makes it read
+the known size of a plain device copy (`bench.py --copy-calibration`: read and written
+bytes per launch given by --copy-bytes).  Pass kernels are named as the library's
+profiler names them (sko_profile_read), and each row carries the digest of the pass-kernel
+source, so a reader can tell whether the counts still describe the current kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+import re
+import sys
+from collections import defaultdict
+
+_REDS = ["none", "proj", "gram", "sketch_sparse", "sketch_dense"]
+_PASS_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "pass_impl.h")
+
+
+def source_digest(path: str = _PASS_SOURCE) -> str:
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def profiler_name(kernel: str) -> str | None:
+    """'void sko::passk::pass_kernel<6, double, 1, false, 0, false, 4>(...)' -> the name the
+    library's profiler gives the same launch ('pass W=6 f64 red=proj/mt4 upd=0 trsm=0 write=0')."""
+    m = re.search(r"pass_kernel(?:_batched)?<(\d+), (double|float), (\d), (true|false), (\d), (true|false)"
+                  r"(?:, (\d+))?>", kernel)
+    if not m:
+        return None
+    w, t, red, upd, ntrsm, write, mtx = m.groups()
+    red = int(red)
+    mt = ""
+    if red == 1:
+        mt = "/mt4" if mtx is not None and int(mtx) == 4 else "/mt8"
+    return (f"pass W={w} {'f32' if t == 'float' else 'f64'} red={_REDS[red]}{mt} upd={int(upd == 'true')} "
+            f"trsm={ntrsm} write={int(write == 'true')}")
+
+
+def short_name(kernel: str) -> str:
+    p = profiler_name(kernel)
+    if p:
+        return p
+    k = re.sub(r"\([^()]*\)$", "", kernel)
+    return k[:80]
+
+
+def counter_means(path: str, counter: str) -> dict[str, tuple[int, float]]:
+    """Kernel name -> (dispatches, mean counter value)."""
+    acc = defaultdict(list)
+    for row in csv.DictReader(open(path)):
+        if row.get("Counter_Name") == counter:
+            acc[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+    return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
+
+
+def cmd_stats(a) -> int:
+    rows = list(csv.DictReader(open(a.csv)))
+    print("| kernel | calls | average µs | total ms | % of kernel time |")
+    print("|---|---:|---:|---:|---:|")
+    for r in rows[: a.top]:
+        print(f"| {short_name(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+              f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    return 0
+
+
+def cmd_traffic(a) -> int:
+    cf = counter_means(a.copy_fetch, "FETCH_SIZE")
+    cw = counter_means(a.copy_write, "WRITE_SIZE")
+    copy = [k for k in cf if "copyBuffer" in k]
+    if not copy or copy[0] not in cw:
+        print("no copy kernel in the calibration runs", file=sys.stderr)
+        return 1
+    fr = a.copy_bytes / (cf[copy[0]][1] * 1024.0)
+    fw = a.copy_bytes / (cw[copy[0]][1] * 1024.0)
+    pf = counter_means(a.fetch, "FETCH_SIZE")
+    pw = counter_means(a.write, "WRITE_SIZE")
+    dig = source_digest()
+    print(f"Calibration (plain copy of {a.copy_bytes} bytes): FETCH_SIZE x {fr:.4f}, WRITE_SIZE x {fw:.4f}")
+    print()
+    print("| kernel | HBM read bytes / launch | HBM write bytes / launch | HBM bytes / launch | source digest |")
+    print("|---|---:|---:|---:|---|")
+    for k in sorted(pf, key=lambda k: -pf[k][1] * pf[k][0]):
+        name = profiler_name(k)
+        if not name or k not in pw:
+            continue
+        rb = pf[k][1] * 1024.0 * fr
+        wb = pw[k][1] * 1024.0 * fw
+        print(f"| {name} | {rb:.4g} | {wb:.4g} | {rb + wb:.6g} | {dig} |")
+    return 0
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--top", type=int, default=15)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--copy-fetch", required=True)
+    t.add_argument("--copy-write", required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    a = ap.parse_args(argv)
+    return cmd_stats(a) if a.cmd == "stats" else cmd_traffic(a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
