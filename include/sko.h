@@ -188,6 +188,23 @@ sko_status sko_gmres_batched(sko_ctx ctx, int32_t nsys, const sko_csr* A,
                              const sko_gmres_opts* opts, sko_gmres_info* infos);
 
 /*
+ * Launch-shape autotuning (the row-strip passes of the block orthogonalisation).
+ * How many workgroups per compute unit stream a pass fastest depends on the pass variant
+ * (its registers, LDS and the number of column streams it reads).  This call times every
+ * pass variant that sko_orth_blocks(ctx, n, nb, w, ..., opts) launches, each at its median
+ * operand width, on scratch blocks the library allocates (n x (2w + p_max) elements plus
+ * small buffers, freed before returning), for 2..8 workgroups per compute unit, and keeps
+ * the fastest count in ctx for that variant and row-count class (floor(log2(n / 256))).
+ * Later launches of those variants on this context, by any entry point, use the choice;
+ * all other launches keep the default (as many workgroups as are resident at once).
+ * The arithmetic per row is unchanged; only the grouping of the per-workgroup partial
+ * sums follows the grid, so results may change in the last bits once, when a choice
+ * changes.  n below 1024 * (compute units) rows: nothing to tune, returns SKO_OK.
+ * Errors: SKO_EINVAL (arguments as for sko_orth_blocks), SKO_ENOMEM (scratch), SKO_EDEVICE.
+ */
+sko_status sko_autotune_orth(sko_ctx ctx, int64_t n, int32_t nb, int32_t w, const sko_orth_opts* opts);
+
+/*
  * Kernel profiling (tracing subsystem).  When enabled, every tall-pass and reduction
  * launch issued by the context is bracketed by HIP events on the context's stream,
  * and per kernel kind the library accumulates the launch count, the summed event time

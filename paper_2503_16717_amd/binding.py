@@ -20,7 +20,8 @@ SKO_SKETCH_GAUSSIAN, SKO_SKETCH_SPARSE_SIGN = 0, 1
 SKO_INTRA_CHOLQR2, SKO_INTRA_RANDCHOLQR = 0, 1
 
 EXPORTED = ["sko_create", "sko_destroy", "sko_set_stream", "sko_strerror", "sko_orth_block",
-            "sko_orth_blocks", "sko_gmres", "sko_gmres_batched", "sko_profile_enable", "sko_profile_read"]
+            "sko_orth_blocks", "sko_gmres", "sko_gmres_batched", "sko_autotune_orth", "sko_profile_enable",
+            "sko_profile_read"]
 
 
 class sko_sketch(C.Structure):
@@ -75,6 +76,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
                               C.POINTER(sko_gmres_info)]
     lib.sko_gmres_batched.argtypes = [vp, i32, C.POINTER(sko_csr), C.POINTER(vp), C.POINTER(vp),
                                       C.POINTER(sko_gmres_opts), C.POINTER(sko_gmres_info)]
+    lib.sko_autotune_orth.argtypes = [vp, i64, i32, i32, C.POINTER(sko_orth_opts)]
     lib.sko_profile_enable.argtypes = [vp, C.c_int]
     lib.sko_profile_read.argtypes = [vp, C.POINTER(sko_kernel_stat), i32]
     for name in EXPORTED:
@@ -199,6 +201,15 @@ class Context:
         infos = (sko_gmres_info * ns)()
         st = _lib.sko_gmres_batched(self.h, ns, Aarr, barr, xarr, C.byref(opts), infos)
         return st, list(infos)
+
+    def sko_autotune_orth(self, n, nb, w, opts: sko_orth_opts):
+        return _lib.sko_autotune_orth(self.h, n, nb, w, C.byref(opts))
+
+    def autotune_orth(self, n: int, nb: int, w: int, **opt_kw):
+        """Tune the launch shapes of sko_orth_blocks(n, nb, w, opts(**opt_kw)) on this context."""
+        st = self.sko_autotune_orth(n, nb, w, orth_opts(**opt_kw))
+        if st != SKO_OK:
+            raise SkoError(st, "sko_autotune_orth")
 
     def sko_profile_enable(self, enable: bool):
         st = _lib.sko_profile_enable(self.h, int(bool(enable)))

@@ -95,6 +95,12 @@ sko_status sko_gmres_batched(sko_ctx c, int32_t nsys, const sko_csr* A, const do
     return sko::gmres_batched_impl(c, nsys, A, b, x, opts, infos);
 }
 
+sko_status sko_autotune_orth(sko_ctx c, int64_t n, int32_t nb, int32_t w, const sko_orth_opts* opts) {
+    if (!c) return SKO_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;
+    return sko::autotune_orth_impl(c, n, nb, w, opts);
+}
+
 sko_status sko_profile_enable(sko_ctx c, int enable) {
     if (!c) return SKO_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;

@@ -92,6 +92,8 @@ struct sko_ctx_s {
     size_t pinned_bytes = 0;
     sko::Profiler prof;
     unsigned tickets = 0;        // reduce-kernel arrivals on the workspace counter since it was zeroed
+    // sko_autotune_orth: workgroups per CU per (pass kernel, log2 of its strip count)
+    std::map<std::pair<const void*, int>, int> grid_wpc;
 };
 
 namespace sko {
@@ -162,6 +164,7 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
 sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq,
                            const void* V, int64_t ldv, void* Qo, int64_t ldqo, double* Rp, double* Rd,
                            const sko_orth_opts* o, int32_t* breakdown_col);
+sko_status autotune_orth_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const sko_orth_opts* o);
 sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, const sko_gmres_opts* o,
                       sko_gmres_info* info);
 sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const double* const* b,

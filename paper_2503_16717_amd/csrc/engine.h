@@ -46,9 +46,19 @@ struct Engine {
         rows_bytes = (double)n;
     }
 
+    // Workgroups of a pass launch: the autotuned count for the variant and this row-count
+    // class if sko_autotune_orth chose one, else as many as are resident at once.
     int grid_for(std::initializer_list<PassKey> keys) const {
         int cap = gmax;
-        for (const PassKey& k : keys) cap = std::min(cap, std::max(1, pass_grid_cap(k)));
+        const int bucket = nstrips > 0 ? (int)std::floor(std::log2((double)nstrips)) : 0;
+        for (const PassKey& k : keys) {
+            int kc = pass_grid_cap(k);
+            if (!c->grid_wpc.empty()) {
+                const auto it = c->grid_wpc.find({pass_kernel_id(k), bucket});
+                if (it != c->grid_wpc.end()) kc = it->second * std::max(1, c->cus);
+            }
+            cap = std::min(cap, std::max(1, kc));
+        }
         return (int)std::max<int64_t>(1, std::min<int64_t>(nstrips, cap));
     }
 
@@ -165,7 +175,7 @@ struct Engine {
     static std::string pass_name(const PassKey& k) {
         static const char* reds[] = {"none", "proj", "gram", "sketch_sparse", "sketch_dense"};
         char buf[96];
-        const int mt = k.red == RED_PROJ ? (k.tiles >= 1 && k.tiles <= 4 ? 4 : 8) : 0;
+        const int mt = k.red == RED_PROJ ? (k.tiles >= 1 && k.tiles <= 4 ? 4 : k.tiles >= 5 && k.tiles <= 6 ? 6 : 8) : 0;
         char tl[16] = "";
         if (mt) snprintf(tl, sizeof tl, "/mt%d", mt);
         snprintf(buf, sizeof buf, "pass W=%d %s red=%s%s upd=%d trsm=%d write=%d", k.W, k.f32 ? "f32" : "f64",

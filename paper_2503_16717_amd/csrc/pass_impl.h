@@ -37,8 +37,8 @@ struct Cfg {
     static constexpr int NT = 256;
     static constexpr int NWAVE = NT / 64;
     static constexpr int LDX = NT + 1;  // padded LDS leading dimension of the strip
-    // Gram: output rows per wave (accumulators per lane = MAXA * W)
-    static constexpr int MAXA = (40 / W) > (W + NWAVE - 1) / NWAVE ? (40 / W) : (W + NWAVE - 1) / NWAVE;
+    // Gram: output rows per wave (accumulators per lane = MAXA * W), spread over all waves
+    static constexpr int MAXA = (W + NWAVE - 1) / NWAVE;
     // MFMA tiles of 16 output rows held by every wave (sketch sizes up to 64 rows in one
     // launch; projections up to 128 previous columns)
     static constexpr int MT = SK ? 4 : 8;
@@ -367,10 +367,13 @@ KernelPtr select_w(const PassKey& k) {
     const int r = k.red;
     const bool u = k.upd, wr = k.write;
     const int t = k.ntrsm;
-    const bool few = k.tiles >= 1 && k.tiles <= 4;  // projection fits 4 tiles
+    // projections: the fewest accumulator tiles that hold the launch's rows
+    const int mt = (k.tiles >= 1 && k.tiles <= 4) ? 4 : (k.tiles >= 5 && k.tiles <= 6) ? 6 : 8;
     if (!u && t == 0 && !wr) {
         if (r == RED_PROJ)
-            return few ? &pass_kernel<W, T, RED_PROJ, false, 0, false, 4> : &pass_kernel<W, T, RED_PROJ, false, 0, false>;
+            return mt == 4   ? &pass_kernel<W, T, RED_PROJ, false, 0, false, 4>
+                   : mt == 6 ? &pass_kernel<W, T, RED_PROJ, false, 0, false, 6>
+                             : &pass_kernel<W, T, RED_PROJ, false, 0, false>;
         if (r == RED_GRAM) return &pass_kernel<W, T, RED_GRAM, false, 0, false>;
         if (r == RED_SKETCH_SPARSE) return &pass_kernel<W, T, RED_SKETCH_SPARSE, false, 0, false>;
         if (r == RED_SKETCH_DENSE) return &pass_kernel<W, T, RED_SKETCH_DENSE, false, 0, false>;
@@ -384,7 +387,9 @@ KernelPtr select_w(const PassKey& k) {
     if (!u && t == 1 && !wr && r == RED_GRAM) return &pass_kernel<W, T, RED_GRAM, false, 1, false>;
     if (!u && t == 2 && wr) {
         if (r == RED_PROJ)
-            return few ? &pass_kernel<W, T, RED_PROJ, false, 2, true, 4> : &pass_kernel<W, T, RED_PROJ, false, 2, true>;
+            return mt == 4   ? &pass_kernel<W, T, RED_PROJ, false, 2, true, 4>
+                   : mt == 6 ? &pass_kernel<W, T, RED_PROJ, false, 2, true, 6>
+                             : &pass_kernel<W, T, RED_PROJ, false, 2, true>;
         if (r == RED_GRAM) return &pass_kernel<W, T, RED_GRAM, false, 2, true>;
     }
     if (r == RED_NONE && t == 1 && wr) {

@@ -36,6 +36,8 @@ int pass_rows_per_launch(int W, int red) {
 
 int pass_strip_rows(const PassKey& key) { return select_kernel(key).threads; }
 
+const void* pass_kernel_id(const PassKey& key) { return reinterpret_cast<const void*>(select_kernel(key).fn); }
+
 int pass_grid_cap(const PassKey& key) {
     PassSel s = select_kernel(key);
     if (!s.fn) return 0;

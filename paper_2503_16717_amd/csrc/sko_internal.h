@@ -78,6 +78,8 @@ hipError_t launch_pass(const PassKey& key, const PassArgs& args, int grid, hipSt
                        const BatchReloc* br = nullptr);
 // Reduction rows one launch of reduction kind `red` can produce for panel width W.
 int pass_rows_per_launch(int W, int red);
+// Identity of the kernel a pass variant launches (null if the variant does not exist).
+const void* pass_kernel_id(const PassKey& key);
 // Rows per strip (= threads per workgroup) of a pass variant.
 int pass_strip_rows(const PassKey& key);
 // Largest useful grid for a pass variant on the current device (resident workgroups).

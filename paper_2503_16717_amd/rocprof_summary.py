@@ -41,7 +41,7 @@ def profiler_name(kernel: str) -> str | None:
     red = int(red)
     mt = ""
     if red == 1:
-        mt = "/mt4" if mtx is not None and int(mtx) == 4 else "/mt8"
+        mt = f"/mt{int(mtx)}" if mtx is not None and int(mtx) in (4, 6) else "/mt8"
     return (f"pass W={w} {'f32' if t == 'float' else 'f64'} red={_REDS[red]}{mt} upd={int(upd == 'true')} "
             f"trsm={ntrsm} write={int(write == 'true')}")
 
