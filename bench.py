@@ -124,13 +124,19 @@ def gmres_suite(B, torch, wl, args) -> dict:
         opts = B.gmres_opts(s=5, m=40, shat=20, two_stage=True, tol=1e-10, precision=prec,
                             sketch=B.make_sketch("sparse_sign", 48, 8, 0))
         torch.cuda.synchronize()
+        ctx.sko_profile_enable(True)
         t0 = time.perf_counter()
         st, infos = ctx.sko_gmres_batched(As, [b.data_ptr() for b in bs], [x.data_ptr() for x in xs], opts)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        ctx.sko_profile_enable(False)
+        prof4 = [{"name": q["name"], "ms": round(q["total_ms"], 2), "launches": q["launches"]}
+                 for q in ctx.sko_profile_read()[:8]]
         out[f"config4_{prec}"] = {"status": st, "time_s": round(dt, 4),
                                   "converged": int(sum(i.converged for i in infos)),
-                                  "iters_total": int(sum(i.iters for i in infos)), "systems": len(infos)}
+                                  "iters_total": int(sum(i.iters for i in infos)),
+                                  "iters_max": int(max(i.iters for i in infos)), "systems": len(infos),
+                                  "kernels_top": prof4}
         log(f"config4 {prec}: {out[f'config4_{prec}']}")
     # the same 256 systems solved one by one (FP64), the plain path the batched form replaces
     for x in xs:
@@ -312,12 +318,16 @@ def main() -> int:
     R_first = R.copy() if args.warmup > 0 else None
     log("warmup done; timing")
     ctx.sko_profile_enable(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         step()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
     ctx.sko_profile_enable(False)
     stats = ctx.sko_profile_read()
     ms = (t1 - t0) / args.steps * 1e3
@@ -350,6 +360,7 @@ def main() -> int:
         return 3
 
     extra = {"kernels_top": kernels, "event_ms_per_step": round(event_ms, 3),
+             "step_ms_median": round(step_ms[len(step_ms) // 2], 4), "step_ms_min": round(step_ms[0], 4),
              "alg_bytes_per_step": abytes, "autotune_s": None if args.no_autotune else round(t_tune, 3)}
 
     if not args.skip_two_stage:
@@ -374,7 +385,9 @@ def main() -> int:
                                                "GBps": round(q["bytes"] / (q["total_ms"] * 1e-3) / 1e9, 1)
                                                if q["total_ms"] > 0 else None} for q in stats2[:10]]}
         log(f"two-stage: {ms2:.3f} ms/step")
-    extra["copy_ceiling_GBps"] = round(copy_ceiling(torch), 1)
+    ceiling = copy_ceiling(torch)
+    extra["copy_ceiling_GBps"] = round(ceiling, 1)
+    extra["pct_of_copy_ceiling"] = round(100.0 * value / ceiling, 2)
     ctx.close()
     del Qd
     if not args.skip_gmres:

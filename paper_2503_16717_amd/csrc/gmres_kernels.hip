@@ -48,6 +48,58 @@ __global__ void __launch_bounds__(NT) spmv_kernel(int64_t n, const int32_t* __re
     }
 }
 
+// One row per thread; each workgroup first copies the contiguous nonzero range of its NT
+// rows into LDS with coalesced loads (when it holds at most 8 entries per row on average,
+// else the rows read the arrays directly), so the per-row loops touch only LDS and x.
+constexpr int STAGE = 8 * NT;
+
+template <typename TV, typename TX, typename TY>
+__device__ __forceinline__ void spmv_staged_body(int64_t n, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ colind, const TV* __restrict__ val,
+                                                 const TX* __restrict__ x, TY* __restrict__ y) {
+    __shared__ TV sv[STAGE];
+    __shared__ int32_t sc[STAGE];
+    const int tid = threadIdx.x;
+    for (int64_t base = (int64_t)blockIdx.x * NT; base < n; base += (int64_t)gridDim.x * NT) {
+        const int64_t rend = base + NT < n ? base + NT : n;
+        const int32_t e0 = rowptr[base], cnt = rowptr[rend] - e0;
+        const bool staged = cnt <= STAGE;
+        if (staged)
+            for (int i = tid; i < cnt; i += NT) {
+                sv[i] = val[e0 + i];
+                sc[i] = colind[e0 + i];
+            }
+        __syncthreads();
+        const int64_t row = base + tid;
+        if (row < n) {
+            const int32_t a = rowptr[row] - e0, b = rowptr[row + 1] - e0;
+            double sum = 0.0;
+            if (staged)
+                for (int32_t e = a; e < b; ++e) sum += ld_(sv + e) * ld_(x + sc[e]);
+            else
+                for (int32_t e = a; e < b; ++e) sum += ld_(val + e0 + e) * ld_(x + colind[e0 + e]);
+            y[row] = static_cast<TY>(sum);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename TV, typename TX, typename TY>
+__global__ void __launch_bounds__(NT) spmv_staged_kernel(int64_t n, const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ colind,
+                                                         const TV* __restrict__ val, const TX* __restrict__ x,
+                                                         TY* __restrict__ y) {
+    spmv_staged_body<TV, TX, TY>(n, rowptr, colind, val, x, y);
+}
+
+template <typename TV, typename TX, typename TY>
+__global__ void __launch_bounds__(NT) spmv_staged_kernel_batched(const TX* x0, TY* y0, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    spmv_staged_body<TV, TX, TY>(d.n, d.rowptr, d.colind, static_cast<const TV*>(d.val_op),
+                                 batch_ptr(br, sys, d, x0), batch_ptr(br, sys, d, y0));
+}
+
 // Batched MPK step: x and y are template basis columns.
 template <int L, typename TV, typename TX, typename TY>
 __global__ void __launch_bounds__(NT) spmv_kernel_batched(const TX* x0, TY* y0, const BatchReloc br) {
@@ -377,16 +429,41 @@ __global__ void __launch_bounds__(NT) gm_small_kernel_batched(const GmSmallArgs 
     gm_small_body(a);
 }
 
+// Kernel choice (measured on the 7-point 192^3 matrix, ~7 entries per row): FP64 values
+// run fastest with 4 lanes per row, FP32 values with one row per thread over an LDS-staged
+// nonzero range; rows much longer than 8 entries go to 8 lanes per row.
+enum SpmvKind { SPMV_L2, SPMV_L4, SPMV_L8, SPMV_STAGED };
+
+template <typename TV>
+SpmvKind spmv_kind(double avg) {
+    if (avg > 12.0) return SPMV_L8;
+    if (sizeof(TV) == 4 && avg <= 8.0) return SPMV_STAGED;
+    return avg > 3.0 ? SPMV_L4 : SPMV_L2;
+}
+
+int spmv_rows_per_block(SpmvKind k) { return k == SPMV_L8 ? NT / 8 : k == SPMV_L4 ? NT / 4 : k == SPMV_L2 ? NT / 2 : NT; }
+
 template <typename TV, typename TX, typename TY>
 hipError_t spmv_dispatch(int64_t n, double avg, const int32_t* rp, const int32_t* ci, const TV* v, const TX* x, TY* y,
                          int grid_cap, hipStream_t st) {
-    const int L = avg > 4.0 ? 8 : 4;
-    const int64_t groups = (n + NT / L - 1) / (NT / L);
+    const SpmvKind k = spmv_kind<TV>(avg);
+    const int rpb = spmv_rows_per_block(k);
+    const int64_t groups = (n + rpb - 1) / rpb;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, grid_cap));
-    if (L == 8)
-        hipLaunchKernelGGL((spmv_kernel<8, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
-    else
-        hipLaunchKernelGGL((spmv_kernel<4, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+    switch (k) {
+        case SPMV_L8:
+            hipLaunchKernelGGL((spmv_kernel<8, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+            break;
+        case SPMV_L4:
+            hipLaunchKernelGGL((spmv_kernel<4, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+            break;
+        case SPMV_L2:
+            hipLaunchKernelGGL((spmv_kernel<2, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+            break;
+        case SPMV_STAGED:
+            hipLaunchKernelGGL((spmv_staged_kernel<TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+            break;
+    }
     return hipGetLastError();
 }
 
@@ -402,14 +479,14 @@ hipError_t launch_spmv(const CsrView& A, bool f32, const void* x, void* y, int g
 }
 
 int residual_grid(int64_t n, int grid_cap) {
-    const int64_t groups = (n + NT / 8 - 1) / (NT / 8);
+    const int64_t groups = (n + NT / 4 - 1) / (NT / 4);
     return (int)std::max<int64_t>(1, std::min<int64_t>(groups, grid_cap));
 }
 
 hipError_t launch_residual(const CsrView& A, const double* x, const double* b, bool f32, void* r, double* partials,
                            int grid, hipStream_t st) {
     const double avg = (double)A.nnz / (double)std::max<int64_t>(1, A.n);
-    const bool l8 = avg > 4.0;
+    const bool l8 = avg > 12.0;
     if (f32) {
         if (l8)
             hipLaunchKernelGGL((residual_kernel<8, float>), dim3(grid), dim3(NT), 0, st, A.n, A.rowptr, A.colind, A.val,
@@ -483,24 +560,46 @@ hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st, const BatchRelo
 hipError_t launch_spmv_batched(bool f32, double avg_nnz, int64_t max_n, const void* x, void* y, int grid_cap,
                                hipStream_t st, const BatchReloc& br) {
     if (br.nact < 1) return hipErrorInvalidValue;
-    const int L = avg_nnz > 4.0 ? 8 : 4;
-    const int64_t groups = (max_n + NT / L - 1) / (NT / L);
+    const SpmvKind k = f32 ? spmv_kind<float>(avg_nnz) : spmv_kind<double>(avg_nnz);
+    const int rpb = spmv_rows_per_block(k);
+    const int64_t groups = (max_n + rpb - 1) / rpb;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, grid_cap));
     const dim3 g(grid, br.nact);
     if (f32) {
         const float* xx = static_cast<const float*>(x);
         float* yy = static_cast<float*>(y);
-        if (L == 8)
-            hipLaunchKernelGGL((spmv_kernel_batched<8, float, float, float>), g, dim3(NT), 0, st, xx, yy, br);
-        else
-            hipLaunchKernelGGL((spmv_kernel_batched<4, float, float, float>), g, dim3(NT), 0, st, xx, yy, br);
+        switch (k) {
+            case SPMV_L8:
+                hipLaunchKernelGGL((spmv_kernel_batched<8, float, float, float>), g, dim3(NT), 0, st, xx, yy, br);
+                break;
+            case SPMV_L4:
+                hipLaunchKernelGGL((spmv_kernel_batched<4, float, float, float>), g, dim3(NT), 0, st, xx, yy, br);
+                break;
+            case SPMV_L2:
+                hipLaunchKernelGGL((spmv_kernel_batched<2, float, float, float>), g, dim3(NT), 0, st, xx, yy, br);
+                break;
+            case SPMV_STAGED:
+                hipLaunchKernelGGL((spmv_staged_kernel_batched<float, float, float>), g, dim3(NT), 0, st, xx, yy, br);
+                break;
+        }
     } else {
         const double* xx = static_cast<const double*>(x);
         double* yy = static_cast<double*>(y);
-        if (L == 8)
-            hipLaunchKernelGGL((spmv_kernel_batched<8, double, double, double>), g, dim3(NT), 0, st, xx, yy, br);
-        else
-            hipLaunchKernelGGL((spmv_kernel_batched<4, double, double, double>), g, dim3(NT), 0, st, xx, yy, br);
+        switch (k) {
+            case SPMV_L8:
+                hipLaunchKernelGGL((spmv_kernel_batched<8, double, double, double>), g, dim3(NT), 0, st, xx, yy, br);
+                break;
+            case SPMV_L4:
+                hipLaunchKernelGGL((spmv_kernel_batched<4, double, double, double>), g, dim3(NT), 0, st, xx, yy, br);
+                break;
+            case SPMV_L2:
+                hipLaunchKernelGGL((spmv_kernel_batched<2, double, double, double>), g, dim3(NT), 0, st, xx, yy, br);
+                break;
+            case SPMV_STAGED:
+                hipLaunchKernelGGL((spmv_staged_kernel_batched<double, double, double>), g, dim3(NT), 0, st, xx, yy,
+                                   br);
+                break;
+        }
     }
     return hipGetLastError();
 }
@@ -508,7 +607,7 @@ hipError_t launch_spmv_batched(bool f32, double avg_nnz, int64_t max_n, const vo
 hipError_t launch_residual_batched(bool f32, double avg_nnz, void* r, double* partials, int grid, hipStream_t st,
                                    const BatchReloc& br) {
     if (br.nact < 1 || grid < 1) return hipErrorInvalidValue;
-    const bool l8 = avg_nnz > 4.0;
+    const bool l8 = avg_nnz > 12.0;
     const dim3 g(grid, br.nact);
     if (f32) {
         if (l8)

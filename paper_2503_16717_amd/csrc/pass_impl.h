@@ -1,10 +1,11 @@
 // Row-strip streaming pass kernel template for tall-skinny blocks on gfx950.
 //
-// A workgroup (4 waves of 64) walks strips of NT consecutive rows (grid-stride over
-// strips).  Phase A gives each thread one row: the block row is loaded with one coalesced
-// access per column, updated, triangular-solved and written back; the result is staged in
-// LDS column-major (padded leading dimension, so column reads across lanes do not collide
-// in the LDS banks).  Phase B computes the pass's one reduction from the staged strip:
+// A workgroup (4 waves of 64) walks strips of consecutive rows (grid-stride over strips).
+// Phase A gives each thread RPT consecutive rows (two for float storage of blocks up to 8
+// columns, read and written as one 8-byte access per column, so a wave moves 512 bytes per
+// load as it does for double storage; wider float blocks would not fit the registers): the rows are loaded with coalesced accesses, updated, triangular-solved
+// and written back; the result is staged in LDS column-major (padded leading dimension,
+// so column reads across lanes do not collide in the LDS banks).  Phase B computes the pass's one reduction from the staged strip:
 //
 //  * projection Q^T x and the sketches Theta^T x: FP64 MFMA (v_mfma_f64_16x16x4) tiles of
 //    16 output rows.  The waves split the strip's 16-row groups; per group every lane
@@ -36,7 +37,6 @@ struct Cfg {
     static constexpr bool MF = RED == RED_PROJ || SK;
     static constexpr int NT = 256;
     static constexpr int NWAVE = NT / 64;
-    static constexpr int LDX = NT + 1;  // padded LDS leading dimension of the strip
     // Gram: output rows per wave (accumulators per lane = MAXA * W), spread over all waves
     static constexpr int MAXA = (W + NWAVE - 1) / NWAVE;
     // MFMA tiles of 16 output rows held by every wave (sketch sizes up to 64 rows in one
@@ -74,16 +74,68 @@ template <typename TA>
 __device__ __forceinline__ void load_col4(const TA* q, bool vec, bool full, int64_t row0, int64_t n,
                                           double av[4]) {
     if (vec && full) {
-        const double2 v0 = *reinterpret_cast<const double2*>(q);
-        const double2 v1 = *reinterpret_cast<const double2*>(q + 2);
-        av[0] = v0.x;
-        av[1] = v0.y;
-        av[2] = v1.x;
-        av[3] = v1.y;
+        if constexpr (sizeof(TA) == 8) {
+            const double2 v0 = *reinterpret_cast<const double2*>(q);
+            const double2 v1 = *reinterpret_cast<const double2*>(q + 2);
+            av[0] = v0.x;
+            av[1] = v0.y;
+            av[2] = v1.x;
+            av[3] = v1.y;
+        } else {
+            const float4 v = *reinterpret_cast<const float4*>(q);
+            av[0] = v.x;
+            av[1] = v.y;
+            av[2] = v.z;
+            av[3] = v.w;
+        }
     } else {
 #pragma unroll
         for (int u = 0; u < 4; ++u) av[u] = (row0 + u < n) ? ldv(q + u) : 0.0;
     }
+}
+
+// Rows row0..row0+R-1 of one column (zero at or beyond n); `vec`: R == 2 and the column
+// start and leading dimension allow 2-element vector accesses.
+template <int R, typename T>
+__device__ __forceinline__ void load_rows(const T* col, bool vec, int64_t row0, int64_t n, double v[R]) {
+    if constexpr (R == 2) {
+        if (vec && row0 + 1 < n) {
+            if constexpr (sizeof(T) == 8) {
+                const double2 p = *reinterpret_cast<const double2*>(col + row0);
+                v[0] = p.x;
+                v[1] = p.y;
+            } else {
+                const float2 p = *reinterpret_cast<const float2*>(col + row0);
+                v[0] = p.x;
+                v[1] = p.y;
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = (row0 + r < n) ? ldv(col + row0 + r) : 0.0;
+}
+
+template <int R, typename T>
+__device__ __forceinline__ void store_rows(T* col, bool vec, int64_t row0, int64_t n, const double v[R]) {
+    if constexpr (R == 2) {
+        if (vec && row0 + 1 < n) {
+            if constexpr (sizeof(T) == 8) {
+                *reinterpret_cast<double2*>(col + row0) = double2{v[0], v[1]};
+            } else {
+                *reinterpret_cast<float2*>(col + row0) = float2{static_cast<float>(v[0]), static_cast<float>(v[1])};
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (row0 + r < n) stv(col + row0 + r, v[r]);
+}
+
+template <typename T>
+__device__ __forceinline__ bool pair_aligned(const void* p, int64_t ld) {
+    return p == nullptr || (((uintptr_t)p % (2 * sizeof(T))) == 0 && (ld % 2) == 0);
 }
 
 // One pass over the rows of `a` by workgroup wg of nwg.
@@ -91,15 +143,18 @@ template <int W, typename T, int RED, bool UPD, int NTRSM, bool WRITE, int MTX>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const int nwg) {
     using C = Cfg<W, RED>;
     constexpr int NT = C::NT;
-    constexpr int LDX = C::LDX;
-    constexpr int RPL = NT / 64;
+    constexpr int RPT = (sizeof(T) == 4 && W <= 8) ? 2 : 1;  // rows per thread in phase A
+    constexpr int STRIP = NT * RPT;
+    constexpr int LDX = STRIP + 1;  // padded LDS leading dimension of the strip
+    constexpr int RPL = STRIP / 64;
     constexpr int MAXA = C::MAXA;
     constexpr int MT = MTX > 0 ? MTX : C::MT;  // MFMA tiles held (fewer: more waves per SIMD)
     constexpr bool MF = C::MF;
+    constexpr bool WAVE_LOCAL = C::SK;  // sketch tiles reduce each wave's own rows
     constexpr bool HAS_RED = RED != RED_NONE;
     constexpr bool GRAM = RED == RED_GRAM;
     __shared__ double xs[HAS_RED ? W * LDX : 1];
-    __shared__ uint64_t hs[RED == RED_SKETCH_SPARSE ? NT : 1];
+    __shared__ uint64_t hs[RED == RED_SKETCH_SPARSE ? STRIP : 1];
     __shared__ double sR[NTRSM > 0 ? NTRSM * W * W : 1];
     __shared__ double pred[MF ? 4 * 64 * C::NWAVE : 1];  // cross-wave tile sums
     extern __shared__ double sC[];  // UPD coefficients, pu * W doubles (dynamic LDS)
@@ -159,10 +214,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
         }
     }
 
-    const int64_t nstrips = (n + NT - 1) / NT;
+    // 2-row vector accesses need every tall operand's column starts 2-element aligned
+    const bool vec = RPT == 2 && pair_aligned<T>(a.Y, a.ldy) && (!UPD || pair_aligned<T>(a.Qu, a.ldqu)) &&
+                     (!WRITE || pair_aligned<T>(a.X, a.ldx));
+    const int64_t nstrips = (n + STRIP - 1) / STRIP;
     for (int64_t s = wg; s < nstrips; s += nwg) {
-        const int64_t base = s * NT;
-        // ---------------- phase A: one row per thread ----------------
+        const int64_t base = s * STRIP;
+        // keep the triangular factors and update coefficients in LDS for wide blocks: the
+        // compiler would hoist every entry into registers for the whole sweep (w(w-1)/2 per
+        // factor), which for w >= 10 halves the resident waves; narrow blocks keep them
+        if constexpr ((NTRSM > 0 || UPD) && W >= 10) asm volatile("" ::: "memory");
+        // ---------------- phase A: RPT consecutive rows per thread ----------------
+        if constexpr (RPT == 1)
         {
             const int64_t row = base + tid;
             double x[W];
@@ -222,8 +285,118 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                 for (int c = 0; c < W; ++c) xs[c * LDX + tid] = x[c];
             }
         }
+        else
+        {
+            const int64_t row0 = base + (int64_t)RPT * tid;
+            double x[RPT][W];
+            if (row0 < n) {
+                const T* Y = static_cast<const T*>(a.Y);
+#pragma unroll
+                for (int c = 0; c < W; ++c) {
+                    double v[RPT];
+                    load_rows<RPT>(Y + (int64_t)c * a.ldy, vec, row0, n, v);
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) x[r][c] = v[r];
+                }
+                if constexpr (UPD) {
+                    const T* Q = static_cast<const T*>(a.Qu);
+                    const int pu = a.pu;
+                    int j = 0;
+                    for (; j + 4 <= pu; j += 4) {
+                        double q[4][RPT];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) load_rows<RPT>(Q + (int64_t)(j + u) * a.ldqu, vec, row0, n, q[u]);
+#pragma unroll
+                        for (int c = 0; c < W; ++c) {
+                            const double c0 = sC[j + 0 + c * pu], c1 = sC[j + 1 + c * pu];
+                            const double c2 = sC[j + 2 + c * pu], c3 = sC[j + 3 + c * pu];
+#pragma unroll
+                            for (int r = 0; r < RPT; ++r) {
+                                double v = x[r][c];
+                                v -= q[0][r] * c0;
+                                v -= q[1][r] * c1;
+                                v -= q[2][r] * c2;
+                                v -= q[3][r] * c3;
+                                x[r][c] = v;
+                            }
+                        }
+                    }
+                    for (; j < pu; ++j) {
+                        double q[RPT];
+                        load_rows<RPT>(Q + (int64_t)j * a.ldqu, vec, row0, n, q);
+#pragma unroll
+                        for (int c = 0; c < W; ++c) {
+                            const double cj = sC[j + c * pu];
+#pragma unroll
+                            for (int r = 0; r < RPT; ++r) x[r][c] -= q[r] * cj;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < NTRSM; ++t) {
+                    const double* R = sR + t * W * W;
+#pragma unroll
+                    for (int c = 0; c < W; ++c) {
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            double v = x[r][c];
+#pragma unroll
+                            for (int q = 0; q < c; ++q) v -= x[r][q] * R[q + c * W];
+                            x[r][c] = v * rinv[t * W + c];
+                        }
+                    }
+                }
+                if constexpr (WRITE) {
+                    T* X = static_cast<T*>(a.X);
+#pragma unroll
+                    for (int c = 0; c < W; ++c) {
+                        double v[RPT];
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) v[r] = x[r][c];
+                        store_rows<RPT>(X + (int64_t)c * a.ldx, vec, row0, n, v);
+                    }
+                }
+                // rows past n (a partial last pair) contribute zero to the reduction
+#pragma unroll
+                for (int r = 1; r < RPT; ++r)
+                    if (row0 + r >= n)
+#pragma unroll
+                        for (int c = 0; c < W; ++c) x[r][c] = 0.0;
+                if constexpr (RED == RED_SKETCH_SPARSE) {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r)
+                        hs[RPT * tid + r] = (row0 + r < n) ? splitmix64(a.sk_seed, (uint64_t)(row0 + r)) : 0;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r)
+#pragma unroll
+                    for (int c = 0; c < W; ++c) x[r][c] = 0.0;
+                if constexpr (RED == RED_SKETCH_SPARSE) {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) hs[RPT * tid + r] = 0;
+                }
+            }
+            if constexpr (HAS_RED) {
+#pragma unroll
+                for (int c = 0; c < W; ++c)
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) xs[c * LDX + RPT * tid + r] = x[r][c];
+            }
+        }
         if constexpr (HAS_RED) {
-            __syncthreads();
+            // Sketches: each wave reduces the rows it staged itself, so only the wave's own LDS
+            // writes must be visible (no workgroup barrier: the waves drift apart and one
+            // wave's MFMA tiles overlap another's loads).  Projections and the Gram share the
+            // whole strip across the waves (the projection's Q reads then cover each column's
+            // strip segment at once, which the HBM pages favour).
+            if constexpr (WAVE_LOCAL) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else {
+                __syncthreads();
+            }
             if constexpr (MF) {
                 // ---------------- phase B, MFMA tiles ----------------
                 const int g = lane >> 4, ci = lane & 15;
@@ -232,9 +405,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                 // 32-byte row pieces can be read as two 16-byte vectors when aligned
                 bool vec = false;
                 if constexpr (RED == RED_PROJ)
-                    vec = sizeof(T) == 8 && (a.ldqp % 4) == 0 && ((uintptr_t)Qp % 32) == 0;
+                    vec = (a.ldqp % 4) == 0 && ((uintptr_t)Qp % (4 * sizeof(T))) == 0;
                 if constexpr (RED == RED_SKETCH_DENSE) vec = (a.ldtheta % 4) == 0 && ((uintptr_t)Th % 32) == 0;
-                for (int gam = wave; gam < NT / 16; gam += C::NWAVE) {
+                constexpr int GPW = STRIP / 16 / C::NWAVE;  // 16-row groups per wave
+                const int g0 = WAVE_LOCAL ? wave * GPW : wave, gstep = WAVE_LOCAL ? 1 : C::NWAVE;
+                // not unrolled: the unrolled groups hold more loads and tiles at once and cost a
+                // resident wave
+#pragma unroll 1
+                for (int gam = g0, it = 0; it < GPW; gam += gstep, ++it) {
                     const int r0 = gam * 16 + 4 * g;  // strip-local rows r0..r0+3 for this lane
                     const bool full = base + r0 + 3 < n;
                     double bv[4];
@@ -288,7 +466,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                     }
                 }
             }
-            __syncthreads();
+            // the next strip's phase A overwrites the staged rows
+            if constexpr (WAVE_LOCAL) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            } else {
+                __syncthreads();
+            }
         }
     }
 
