@@ -332,7 +332,71 @@ __device__ void lsq(const GmSmallArgs& a, int k) {
     __syncthreads();
 }
 
+// lsq with T_in, H and g staged in LDS (rows 0..k, leading dimension k + 1): the row-wise
+// substitutions, the rotations and the back substitution then read no global memory.
+// Lds holds 2 k (k + 1) + (k + 1) doubles.
+__device__ void lsq_lds(const GmSmallArgs& a, int k, double* lds) {
+    const int ld = a.m + 1, lh = k + 1;
+    double* Hs = lds;
+    double* Ts = lds + (int64_t)lh * k;
+    double* gs = Ts + (int64_t)lh * k;
+    __shared__ double cs[2];
+    for (int idx = threadIdx.x; idx < lh * k; idx += NT) {
+        const int r = idx % lh, c = idx / lh;
+        Ts[idx] = a.Tin[r + (int64_t)c * ld];
+    }
+    for (int i = threadIdx.x; i <= k; i += NT) gs[i] = a.g[i];
+    __syncthreads();
+    // H[r, c] = (T_out[r, c] - sum_{q<c} H[r, q] T_in[q, c]) / T_in[c, c]
+    for (int r = threadIdx.x; r <= k; r += NT) {
+        for (int c = 0; c < k; ++c) {
+            double v = a.Tout[r + (int64_t)c * ld];
+            for (int q = 0; q < c; ++q) v -= Hs[r + q * lh] * Ts[q + c * lh];
+            Hs[r + c * lh] = v / Ts[c + c * lh];
+        }
+    }
+    __syncthreads();
+    for (int i = 0; i < k; ++i) {
+        if (threadIdx.x == 0) {
+            const double x = Hs[i + i * lh], z = Hs[i + 1 + i * lh];
+            const double rad = hypot(x, z);
+            cs[0] = rad == 0.0 ? 1.0 : x / rad;
+            cs[1] = rad == 0.0 ? 0.0 : z / rad;
+        }
+        __syncthreads();
+        const double c = cs[0], sn = cs[1];
+        for (int j = i + threadIdx.x; j < k; j += NT) {
+            const double top = Hs[i + j * lh], bot = Hs[i + 1 + j * lh];
+            Hs[i + j * lh] = c * top + sn * bot;
+            Hs[i + 1 + j * lh] = -sn * top + c * bot;
+        }
+        if (threadIdx.x == 0) {
+            const double gi = gs[i], gj = gs[i + 1];
+            gs[i] = c * gi + sn * gj;
+            gs[i + 1] = -sn * gi + c * gj;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // y overwrites gs[0..k) from the bottom up
+        for (int i = k - 1; i >= 0; --i) {
+            double v = gs[i];
+            for (int j = i + 1; j < k; ++j) v -= Hs[i + j * lh] * gs[j];
+            gs[i] = v / Hs[i + i * lh];
+        }
+        a.res[0] = fabs(gs[k]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += NT) a.y[i] = gs[i];
+    __syncthreads();
+}
+
+// Doubles of dynamic LDS the staged least squares needs for basis size up to m.
+constexpr int lsq_lds_doubles(int m) { return 2 * m * (m + 1) + (m + 1); }
+constexpr int kLsqLdsMax = 8000;  // 62.5 KiB
+
 __device__ __forceinline__ void gm_small_body(const GmSmallArgs& a) {
+    extern __shared__ double gm_dyn[];
     const int ld = a.m + 1;
     __shared__ double sub[256];
     if (a.op == GM_INIT) {
@@ -362,7 +426,12 @@ __device__ __forceinline__ void gm_small_body(const GmSmallArgs& a) {
         __syncthreads();
         replace_row(a, kk, sub);
         store_block(a, kk, a.coef);
-        if (a.do_lsq) lsq(a, kk + a.s);
+        if (a.do_lsq) {
+            if (lsq_lds_doubles(a.m) <= kLsqLdsMax)
+                lsq_lds(a, kk + a.s, gm_dyn);
+            else
+                lsq(a, kk + a.s);
+        }
         return;
     }
     if (a.op == GM_BIGCLOSE) {
@@ -402,7 +471,10 @@ __device__ __forceinline__ void gm_small_body(const GmSmallArgs& a) {
             }
         }
         __syncthreads();
-        lsq(a, kend);
+        if (lsq_lds_doubles(a.m) <= kLsqLdsMax)
+            lsq_lds(a, kend, gm_dyn);
+        else
+            lsq(a, kend);
         return;
     }
 }
@@ -548,11 +620,12 @@ hipError_t launch_scale_values(int64_t nnz, const int32_t* colind, const double*
 
 hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st, const BatchReloc* br) {
     if (a.m + 1 > 256 || a.Wb > 64) return hipErrorInvalidValue;
+    const size_t lds = lsq_lds_doubles(a.m) <= kLsqLdsMax ? sizeof(double) * lsq_lds_doubles(a.m) : 0;
     if (br) {
         if (br->nact < 1) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(gm_small_kernel_batched, dim3(1, br->nact), dim3(NT), 0, st, a, *br);
+        hipLaunchKernelGGL(gm_small_kernel_batched, dim3(1, br->nact), dim3(NT), lds, st, a, *br);
     } else {
-        hipLaunchKernelGGL(gm_small_kernel, dim3(1), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL(gm_small_kernel, dim3(1), dim3(NT), lds, st, a);
     }
     return hipGetLastError();
 }

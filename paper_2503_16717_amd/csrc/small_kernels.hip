@@ -141,32 +141,100 @@ __device__ void householder_lds(double* A, int k, int w, double* E, double* R, i
     __syncthreads();
 }
 
-// Right-looking upper Cholesky of the w x w matrix G (LDS, column-major), w <= 64.
-__device__ void cholesky_lds(double* G, int w, double* R, int* status, int col0, double* scal) {
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < w * w; idx += RT) R[idx] = 0.0;
+// Orders this wave's LDS writes before its later LDS reads (no other wave involved).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// householder_lds for k <= 64, run by one wave (one row per lane): the column norms and
+// reflector products are shuffle reductions, and no step waits for the other waves.  The
+// caller synchronises the workgroup afterwards.
+__device__ void householder_wave(double* A, int k, int w, double* E, double* R, int ldr, int* status, int col0,
+                                 double* scal) {
+    const int lane = threadIdx.x & 63;
+    double* vhead = scal;      // w
+    double* beta = scal + 16;  // w
+    double* sgn = scal + 48;   // w
     for (int j = 0; j < w; ++j) {
-        if (tid == 0) {
-            const double d = G[j + j * w];
-            if (!(d > 0.0) || !isfinite(d)) {
-                if (status) atomicCAS(status, 0, col0 + j + 1);
-            }
-            scal[0] = sqrt(d);
+        const double aj = (lane > j && lane < k) ? A[lane + j * k] : 0.0;
+        const double ss = wave_sum(aj * aj);
+        const double x0 = A[j + j * k];
+        const double normx = sqrt(x0 * x0 + ss);
+        double alpha = 0.0, b = 0.0, v0 = 0.0;
+        if (normx != 0.0) {
+            alpha = -copysign(normx, x0);
+            v0 = x0 - alpha;
+            b = 2.0 / (v0 * v0 + ss);
         }
-        __syncthreads();
-        const double r = scal[0];
-        for (int c = j + tid; c < w; c += RT) {
+        const double vi = (lane == j) ? v0 : aj;
+        for (int c = j + 1; c < w; ++c) {
+            const double ac = lane < k ? A[lane + c * k] : 0.0;
+            const double d = wave_sum(vi * ac);
+            if (lane >= j && lane < k) A[lane + c * k] = ac - b * d * vi;
+        }
+        wave_sync();
+        if (lane == 0) {
+            A[j + j * k] = alpha;
+            vhead[j] = v0;
+            beta[j] = b;
+        }
+        wave_sync();
+    }
+    if (lane < w) {
+        const double d = A[lane + lane * k];
+        sgn[lane] = d < 0.0 ? -1.0 : 1.0;
+        if (d == 0.0 && status) atomicCAS(status, 0, col0 + lane + 1);
+    }
+    wave_sync();
+    for (int idx = lane; idx < w * w; idx += 64) {
+        const int r = idx % w, c = idx / w;
+        R[r + c * ldr] = (r <= c) ? sgn[r] * A[r + c * k] : 0.0;
+    }
+    if (!E) return;
+    // explicit thin Q: H_0 ... H_{w-1} applied in reverse to [I; 0]
+    for (int idx = lane; idx < k * w; idx += 64) {
+        const int r = idx % k, c = idx / k;
+        E[idx] = (r == c) ? 1.0 : 0.0;
+    }
+    wave_sync();
+    for (int j = w - 1; j >= 0; --j) {
+        const double v0 = vhead[j], b = beta[j];
+        const double vi = (lane == j) ? v0 : ((lane > j && lane < k) ? A[lane + j * k] : 0.0);
+        for (int c = 0; c < w; ++c) {
+            const double ec = lane < k ? E[lane + c * k] : 0.0;
+            const double d = wave_sum(vi * ec);
+            if (lane >= j && lane < k) E[lane + c * k] = ec - b * d * vi;
+        }
+        wave_sync();
+    }
+    for (int idx = lane; idx < k * w; idx += 64) E[idx] *= sgn[idx / k];
+    wave_sync();
+}
+
+// Right-looking upper Cholesky of the w x w matrix G (LDS, column-major), w <= 64, run by
+// one wave: each column's pivot, row scaling and trailing update are wave-parallel and
+// ordered by wave-level fences only.  The caller synchronises the workgroup afterwards.
+__device__ void cholesky_wave(double* G, int w, double* R, int* status, int col0, double* scal) {
+    const int lane = threadIdx.x & 63;
+    for (int idx = lane; idx < w * w; idx += 64) R[idx] = 0.0;
+    for (int j = 0; j < w; ++j) {
+        const double d = G[j + j * w];
+        if (lane == 0 && (!(d > 0.0) || !isfinite(d)) && status) atomicCAS(status, 0, col0 + j + 1);
+        const double r = sqrt(d);
+        for (int c = j + lane; c < w; c += 64) {
             const double v = (c == j) ? r : G[j + c * w] / r;
             R[j + c * w] = v;
             scal[8 + c] = v;  // row j of R for the trailing update
         }
-        __syncthreads();
+        wave_sync();
         const int m = w - j - 1;
-        for (int idx = tid; idx < m * m; idx += RT) {
+        for (int idx = lane; idx < m * m; idx += 64) {
             const int a = j + 1 + idx % m, c = j + 1 + idx / m;
             if (a <= c) G[a + c * w] -= scal[8 + a] * scal[8 + c];
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -207,11 +275,15 @@ __device__ void assemble(const SmallArgs& s, double* rh) {
 }
 
 // Sketch-space BCGS2 with Householder (Fig. 8a): y (k x w) against Yacc[:, 0:nacc].
-__device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* red, double* scal) {
+// Ys: LDS copy of Yacc[:, 0:nacc] with leading dimension k + 1 (so lanes reading different
+// columns at one row index fall in different banks); the dot products then never wait on
+// global memory.
+__device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* Ys, double* red, double* scal) {
     const int tid = threadIdx.x;
     const int k = s.k, w = s.w, na = s.nacc;
-    const double* Y = s.Yacc;
+    const int ldy = k + 1;
     for (int idx = tid; idx < k * w; idx += RT) Z[idx] = load_coherent(s.out + idx);
+    for (int idx = tid; idx < k * na; idx += RT) Ys[idx % k + (idx / k) * ldy] = s.Yacc[idx];
     __syncthreads();
     if (na > 0) {
         for (int pass = 0; pass < 2; ++pass) {
@@ -219,21 +291,26 @@ __device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* r
             for (int idx = tid; idx < na * w; idx += RT) {
                 const int a = idx % na, c = idx / na;
                 double d = 0.0;
-                for (int i = 0; i < k; ++i) d += Y[i + (int64_t)a * k] * Z[i + c * k];
+                for (int i = 0; i < k; ++i) d += Ys[i + a * ldy] * Z[i + c * k];
                 E[idx] = d;
             }
             __syncthreads();
             for (int idx = tid; idx < k * w; idx += RT) {
                 const int i = idx % k, c = idx / k;
                 double v = Z[idx];
-                for (int a = 0; a < na; ++a) v -= Y[i + (int64_t)a * k] * E[a + c * na];
+                for (int a = 0; a < na; ++a) v -= Ys[i + a * ldy] * E[a + c * na];
                 Z[idx] = v;
             }
             for (int idx = tid; idx < na * w; idx += RT) s.r[idx] = (pass == 0) ? E[idx] : s.r[idx] + E[idx];
             __syncthreads();
         }
     }
-    householder_lds(Z, k, w, E, s.R, w, s.status, s.col0, red, scal);
+    if (k <= 64) {
+        if (tid < 64) householder_wave(Z, k, w, E, s.R, w, s.status, s.col0, scal);
+        __syncthreads();
+    } else {
+        householder_lds(Z, k, w, E, s.R, w, s.status, s.col0, red, scal);
+    }
     // append q to the accumulated sketches (replacing the boundary column at nacc)
     for (int idx = tid; idx < k * w; idx += RT) s.Yacc[(int64_t)na * k + idx] = E[idx];
     if (s.Rbar) {
@@ -289,12 +366,17 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
         double* A = lds;
         for (int idx = tid; idx < s.k * s.w; idx += RT) A[idx] = load_coherent(s.out + idx);
         __syncthreads();
-        householder_lds(A, s.k, s.w, nullptr, s.R, s.w, s.status, s.col0, red, scal);
+        if (s.k <= 64) {
+            if (tid < 64) householder_wave(A, s.k, s.w, nullptr, s.R, s.w, s.status, s.col0, scal);
+            __syncthreads();
+        } else {
+            householder_lds(A, s.k, s.w, nullptr, s.R, s.w, s.status, s.col0, red, scal);
+        }
     } else if (s.op == OP_CHOL) {
         double* G = lds;
         for (int idx = tid; idx < s.w * s.w; idx += RT) G[idx] = load_coherent(s.out + idx);
         __syncthreads();
-        cholesky_lds(G, s.w, s.R, s.status, s.col0, scal);
+        if (tid < 64) cholesky_wave(G, s.w, s.R, s.status, s.col0, scal);
         __syncthreads();
         if (s.assemble) {
             __threadfence();
@@ -303,7 +385,8 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
     } else if (s.op == OP_SKETCH_BCGS2) {
         double* Z = lds;
         double* E = lds + s.k * s.w;
-        sketch_bcgs2(s, Z, E, red, scal);
+        double* Ys = E + (s.k * s.w > s.nacc * s.w ? s.k * s.w : s.nacc * s.w);
+        sketch_bcgs2(s, Z, E, Ys, red, scal);
     }
 }
 
@@ -357,9 +440,20 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream, const BatchRel
     } else if (s.op == OP_SKETCH_BCGS2) {
         if (s.k > RT || s.w > 16 || s.k < s.w) return hipErrorInvalidValue;
         const size_t e = (size_t)s.k * s.w > (size_t)s.nacc * s.w ? (size_t)s.k * s.w : (size_t)s.nacc * s.w;
-        lds = sizeof(double) * ((size_t)s.k * s.w + e);
+        lds = sizeof(double) * ((size_t)s.k * s.w + e + (size_t)(s.k + 1) * s.nacc);
     }
-    if (lds > 60 * 1024) return hipErrorInvalidValue;
+    // dynamic LDS beyond 64 KiB needs the kernels' limit raised once (gfx950: 160 KiB per CU)
+    constexpr size_t kMaxLds = 150 * 1024;
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    static bool raised = false;
+    if (lds > 60 * 1024 && !raised) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(reduce_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void*>(reduce_kernel_batched),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess)
+            return hipErrorInvalidValue;
+        raised = true;
+    }
     const int grid = reduce_grid(a.count);
     if (br) {
         if (br->nact < 1) return hipErrorInvalidValue;
