@@ -66,6 +66,67 @@ def alg_bytes_two_stage(n: int, nb: int, w: int, ppb: int, eb: int = 8) -> float
     return float(cols) * n * eb
 
 
+def c3_suite(B, torch, wl, n: int) -> dict:
+    """Mixed precision at the config-2 shape with w = 11 (s = 10): the same blocks stored in
+    FP32 and in FP64, one-stage RandCholQR-BCGS2, sparse-sign k = 64; errors of the FP32 run
+    measured in FP64 on the device (||I - Q^T Q||_2 and ||V - QR||_F / ||V||_F, V the FP32
+    input itself)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    w, nb = 11, 12
+    N = w * nb
+    out = {}
+    ctx = B.Context(0)
+    sk = B.make_sketch("sparse_sign", SK_K, SK_ZETA, SK_SEED)
+    for e in (6.0, 10.0):
+        V64 = torch.empty((N, n), dtype=torch.float64, device="cuda")
+
+        def one(j):
+            blk = wl.glued_block(n, w, e, j)
+            V64[j * w:(j + 1) * w].copy_(torch.from_numpy(np.ascontiguousarray(blk.T)))
+
+        with ThreadPoolExecutor(max_workers=12) as ex:
+            list(ex.map(one, range(nb)))
+        V32 = V64.float()
+        res = {}
+        for prec, V in (("f64", V64), ("mixed", V32)):
+            Q = torch.empty_like(V)
+            R = np.zeros((N, N), order="F")
+            o = B.orth_opts(intra="randcholqr", precision=prec, sketch=sk)
+
+            def step():
+                st, col = ctx.sko_orth_blocks(n, nb, w, V.data_ptr(), n, Q.data_ptr(), n, R, N, o)
+                if st != B.SKO_OK:
+                    raise B.SkoError(st, "sko_orth_blocks", col)
+
+            step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                step()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / 3 * 1e3
+            ab = alg_bytes_one_stage(n, nb, w, 4 if prec == "mixed" else 8)
+            Qd = Q.t().double()            # n x N
+            G = (Qd.t() @ Qd).cpu().numpy()
+            orth = float(np.linalg.norm(np.eye(N) - G, 2))
+            Rt = torch.from_numpy(R).cuda()
+            num = den = 0.0
+            for r0 in range(0, n, 1 << 22):
+                Vc = V.t()[r0:r0 + (1 << 22)].double()
+                num += float(((Vc - Qd[r0:r0 + (1 << 22)] @ Rt) ** 2).sum())
+                den += float((Vc ** 2).sum())
+            res[prec] = {"ms_per_step": round(ms, 3), "GBps": round(ab / (ms * 1e-3) / 1e9, 1),
+                         "orth_error": orth, "backward_error": (num / den) ** 0.5}
+            del Q, Qd, Rt
+            log(f"config3 kappa 1e{e:g} {prec}: {res[prec]}")
+        out[f"kappa_1e{int(e)}"] = res
+        del V64, V32
+        torch.cuda.empty_cache()
+    ctx.close()
+    return out
+
+
 def gmres_suite(B, torch, wl, args) -> dict:
     """Time to relative residual 1e-10 (explicit, FP64) for the solver configurations."""
     import numpy as np
@@ -267,6 +328,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=N_ROWS, help="rows (default 2^24)")
     ap.add_argument("--skip-gmres", action="store_true", help="skip the GMRES time-to-solution runs")
     ap.add_argument("--skip-two-stage", action="store_true", help="skip the two-stage orthogonalisation run")
+    ap.add_argument("--skip-c3", action="store_true", help="skip the mixed-precision block orthogonalisation run")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (counter calibration)")
@@ -399,9 +461,12 @@ def main() -> int:
     extra["pct_of_copy_ceiling"] = round(100.0 * value / ceiling, 2)
     ctx.close()
     del Qd
-    if not args.skip_gmres:
+    if not (args.skip_gmres and args.skip_c3):
         del Vd
         torch.cuda.empty_cache()
+    if not args.skip_c3:
+        extra["config3_mixed_blockorth"] = c3_suite(B, torch, wl, n)
+    if not args.skip_gmres:
         extra["gmres"] = gmres_suite(B, torch, wl, args)
 
     cpu = None

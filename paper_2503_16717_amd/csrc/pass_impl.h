@@ -1,9 +1,10 @@
 // Row-strip streaming pass kernel template for tall-skinny blocks on gfx950.
 //
 // A workgroup (4 waves of 64) walks strips of consecutive rows (grid-stride over strips).
-// Phase A gives each thread RPT consecutive rows (two for float storage of blocks up to 8
-// columns, read and written as one 8-byte access per column, so a wave moves 512 bytes per
-// load as it does for double storage; wider float blocks would not fit the registers): the rows are loaded with coalesced accesses, updated, triangular-solved
+// Phase A gives each thread RPT consecutive rows (two for float storage, read and written
+// as one 8-byte access per column, so a wave moves 512 bytes per load as it does for
+// double storage; not for wide float blocks with triangular solves, which would not fit the
+// registers): the rows are loaded with coalesced accesses, updated, triangular-solved
 // and written back; the result is staged in LDS column-major (padded leading dimension,
 // so column reads across lanes do not collide in the LDS banks).  Phase B computes the pass's one reduction from the staged strip:
 //
@@ -21,6 +22,7 @@
 // Every tall operand is read from HBM once per pass; partial sums stay in registers for the
 // whole sweep and are written once per workgroup at the end.
 #pragma once
+#include <type_traits>
 #include "batch.h"
 #include "sko_internal.h"
 
@@ -143,7 +145,9 @@ template <int W, typename T, int RED, bool UPD, int NTRSM, bool WRITE, int MTX>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const int nwg) {
     using C = Cfg<W, RED>;
     constexpr int NT = C::NT;
-    constexpr int RPT = (sizeof(T) == 4 && W <= 8) ? 2 : 1;  // rows per thread in phase A
+    // rows per thread in phase A: two for float storage (8-byte accesses), except for wide
+    // blocks with triangular solves, whose two rows would not fit the registers
+    constexpr int RPT = (sizeof(T) == 4 && (W <= 8 || NTRSM == 0)) ? 2 : 1;
     constexpr int STRIP = NT * RPT;
     constexpr int LDX = STRIP + 1;  // padded LDS leading dimension of the strip
     constexpr int RPL = STRIP / 64;
@@ -153,7 +157,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
     constexpr bool WAVE_LOCAL = C::SK;  // sketch tiles reduce each wave's own rows
     constexpr bool HAS_RED = RED != RED_NONE;
     constexpr bool GRAM = RED == RED_GRAM;
-    __shared__ double xs[HAS_RED ? W * LDX : 1];
+    // the strip in LDS, in the storage type: float storage reduces the rounded values it
+    // stores (and halves the LDS)
+    using XS = typename std::conditional<sizeof(T) == 4, float, double>::type;
+    __shared__ XS xs[HAS_RED ? W * LDX : 1];
     __shared__ uint64_t hs[RED == RED_SKETCH_SPARSE ? STRIP : 1];
     __shared__ double sR[NTRSM > 0 ? NTRSM * W * W : 1];
     __shared__ double pred[MF ? 4 * 64 * C::NWAVE : 1];  // cross-wave tile sums
@@ -282,7 +289,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
             }
             if constexpr (HAS_RED) {
 #pragma unroll
-                for (int c = 0; c < W; ++c) xs[c * LDX + tid] = x[c];
+                for (int c = 0; c < W; ++c) xs[c * LDX + tid] = static_cast<XS>(x[c]);
             }
         }
         else
@@ -381,7 +388,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
 #pragma unroll
                 for (int c = 0; c < W; ++c)
 #pragma unroll
-                    for (int r = 0; r < RPT; ++r) xs[c * LDX + RPT * tid + r] = x[r][c];
+                    for (int r = 0; r < RPT; ++r) xs[c * LDX + RPT * tid + r] = static_cast<XS>(x[r][c]);
             }
         }
         if constexpr (HAS_RED) {
