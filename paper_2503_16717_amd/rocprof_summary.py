@@ -3,6 +3,7 @@
     python -m paper_2503_16717_amd.rocprof_summary stats KERNEL_STATS_CSV [--top N]
     python -m paper_2503_16717_amd.rocprof_summary traffic --fetch CSV --write CSV \\
         --copy-fetch CSV --copy-write CSV --copy-bytes BYTES
+    python -m paper_2503_16717_amd.rocprof_summary last KERNEL_TRACE_CSV --kernel NAME --last N
 
 `stats` lists the kernels of a `--kernel-trace --stats` run by total time.  `traffic`
 turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs (KiB per dispatch) into HBM bytes
@@ -73,6 +74,20 @@ def cmd_stats(a) -> int:
     return 0
 
 
+def cmd_last(a) -> int:
+    """Average duration of the last N dispatches of one kernel (by profiler name or a
+    substring of the demangled name): the launches of the timed steps, after any tuning."""
+    rows = [r for r in csv.DictReader(open(a.csv))
+            if a.kernel == short_name(r["Kernel_Name"]) or a.kernel in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows][-a.last:]
+    if not d:
+        print("no dispatches of", a.kernel, file=sys.stderr)
+        return 1
+    print(f"{a.kernel}: {len(d)} dispatches, average {sum(d) / len(d):.1f} µs")
+    return 0
+
+
 def cmd_traffic(a) -> int:
     cf = counter_means(a.copy_fetch, "FETCH_SIZE")
     cw = counter_means(a.copy_write, "WRITE_SIZE")
@@ -111,8 +126,12 @@ def main(argv=None) -> int:
     t.add_argument("--copy-fetch", required=True)
     t.add_argument("--copy-write", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
+    la = sub.add_parser("last")
+    la.add_argument("csv")
+    la.add_argument("--kernel", required=True)
+    la.add_argument("--last", type=int, required=True)
     a = ap.parse_args(argv)
-    return cmd_stats(a) if a.cmd == "stats" else cmd_traffic(a)
+    return {"stats": cmd_stats, "traffic": cmd_traffic, "last": cmd_last}[a.cmd](a)
 
 
 if __name__ == "__main__":
