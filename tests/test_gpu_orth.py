@@ -175,3 +175,26 @@ def test_mixed_precision_storage(B, ctx):
     assert metrics.orth_error(Q)[0] <= 1e-5
     assert metrics.backward_error(V, Q, R) <= 1e-6
     assert metrics.rel_diff(R, ref.R) <= 1e-5
+
+
+@pytest.mark.parametrize("w", [6, 11])
+@pytest.mark.parametrize("n,pad", [(20000, 0), (20001, 0), (20000, 1)])
+def test_mixed_precision_layouts(B, ctx, w, n, pad):
+    """Float storage in both strip layouts: pairs of rows read as one 8-byte access (even n,
+    even leading dimension), a partial last pair (odd n) and the element-wise fallback (odd
+    leading dimension).  Errors against the FP64 oracle on the float-rounded input are of the
+    order of single precision."""
+    e = 4
+    V = wl.glued_blocks(n, 3, w, e).astype(np.float32).astype(np.float64)
+    buf = torch.zeros((3 * w, n + pad), dtype=torch.float32, device="cuda")
+    buf[:, :n] = torch.from_numpy(np.ascontiguousarray(V.T)).to("cuda", torch.float32)
+    Vd = buf.t()[:n]
+    Q, R, st, col = ctx.orth_blocks(Vd, w, precision="mixed", intra="randcholqr",
+                                    sketch=B.make_sketch("sparse_sign", 64, 8, 0))
+    torch.cuda.synchronize()
+    assert st == B.SKO_OK
+    Qh = Q.double().cpu().numpy()
+    ref = orth.orth_blocks_one_stage(V, w, "randcholqr", Sketch.sparse_sign(64, 8, 0))
+    assert metrics.orth_error(Qh)[0] <= 1e-5
+    assert metrics.backward_error(V, Qh, R) <= 1e-6
+    assert metrics.rel_diff(R, ref.R) <= 1e-5
