@@ -66,7 +66,7 @@ def alg_bytes_two_stage(n: int, nb: int, w: int, ppb: int, eb: int = 8) -> float
     return float(cols) * n * eb
 
 
-def c3_suite(B, torch, wl, n: int) -> dict:
+def c3_suite(B, torch, wl, n: int, no_autotune: bool = False) -> dict:
     """Mixed precision at the config-2 shape with w = 11 (s = 10): the same blocks stored in
     FP32 and in FP64, one-stage RandCholQR-BCGS2, sparse-sign k = 64; errors of the FP32 run
     measured in FP64 on the device (||I - Q^T Q||_2 and ||V - QR||_F / ||V||_F, V the FP32
@@ -93,6 +93,10 @@ def c3_suite(B, torch, wl, n: int) -> dict:
             Q = torch.empty_like(V)
             R = np.zeros((N, N), order="F")
             o = B.orth_opts(intra="randcholqr", precision=prec, sketch=sk)
+            if not no_autotune:
+                st = ctx.sko_autotune_orth(n, nb, w, o)
+                if st != B.SKO_OK:
+                    raise B.SkoError(st, "sko_autotune_orth")
 
             def step():
                 st, col = ctx.sko_orth_blocks(n, nb, w, V.data_ptr(), n, Q.data_ptr(), n, R, N, o)
@@ -107,6 +111,15 @@ def c3_suite(B, torch, wl, n: int) -> dict:
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) / 3 * 1e3
             ab = alg_bytes_one_stage(n, nb, w, 4 if prec == "mixed" else 8)
+            top = None
+            if e == 6.0:   # a profiled run for the kernel breakdown (its events slow short launches)
+                ctx.sko_profile_enable(True)
+                step()
+                torch.cuda.synchronize()
+                ctx.sko_profile_enable(False)
+                top = [{"name": q["name"], "ms": round(q["total_ms"], 3), "launches": q["launches"],
+                        "GBps": round(q["bytes"] / (q["total_ms"] * 1e-3) / 1e9, 1) if q["total_ms"] > 0
+                        else None} for q in ctx.sko_profile_read()[:8]]
             Qd = Q.t().double()            # n x N
             G = (Qd.t() @ Qd).cpu().numpy()
             orth = float(np.linalg.norm(np.eye(N) - G, 2))
@@ -118,6 +131,8 @@ def c3_suite(B, torch, wl, n: int) -> dict:
                 den += float((Vc ** 2).sum())
             res[prec] = {"ms_per_step": round(ms, 3), "GBps": round(ab / (ms * 1e-3) / 1e9, 1),
                          "orth_error": orth, "backward_error": (num / den) ** 0.5}
+            if top:
+                res[prec]["kernels_top_profiled_run"] = top
             del Q, Qd, Rt
             log(f"config3 kappa 1e{e:g} {prec}: {res[prec]}")
         out[f"kappa_1e{int(e)}"] = res
@@ -465,7 +480,7 @@ def main() -> int:
         del Vd
         torch.cuda.empty_cache()
     if not args.skip_c3:
-        extra["config3_mixed_blockorth"] = c3_suite(B, torch, wl, n)
+        extra["config3_mixed_blockorth"] = c3_suite(B, torch, wl, n, args.no_autotune)
     if not args.skip_gmres:
         extra["gmres"] = gmres_suite(B, torch, wl, args)
 

@@ -47,6 +47,40 @@ struct Cfg {
     static constexpr int ROWS = MF ? 16 * MT : NWAVE * MAXA;
 };
 
+// Read-only uniform operands (update coefficients, triangular factors) are addressed
+// through the constant address space: every lane reads the same entry, so the loads go
+// through the scalar cache into SGPRs and the FMAs take them as scalar operands.  Through
+// LDS each entry would be a full wave-wide read, one per FMA, and the LDS read rate, not
+// HBM, would bound the wide passes.  The arrays are written by earlier launches only.
+typedef const __attribute__((address_space(4))) double* CD;
+
+// The pointer is the same for the whole workgroup; readfirstlane puts it in SGPRs even
+// where it was computed with vector instructions (the batched kernels' relocation).
+__device__ __forceinline__ CD as_uniform(const double* p) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (CD)(((unsigned long long)hi << 32) | lo);
+}
+
+// Hides from the compiler that the pointer is the same in every strip, so the entries it
+// addresses are loaded again per strip instead of being held in registers for the whole
+// sweep (which for wide blocks costs more registers than the kernel can spare).
+__device__ __forceinline__ CD per_strip(CD p) {
+    unsigned long long v = (unsigned long long)p;
+    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return (CD)(((unsigned long long)hi << 32) | lo);
+}
+
+// A wave-uniform double moved into SGPRs.
+__device__ __forceinline__ double uniform_d(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <typename T>
 __device__ __forceinline__ double ldv(const T* p) {
     return static_cast<double>(*p);
@@ -140,6 +174,92 @@ __device__ __forceinline__ bool pair_aligned(const void* p, int64_t ld) {
     return p == nullptr || (((uintptr_t)p % (2 * sizeof(T))) == 0 && (ld % 2) == 0);
 }
 
+// R consecutive rows of one column in the storage type, loaded as one access (R == 2:
+// pair-aligned).  Kept unconverted until use, so a load issued ahead stays in flight.
+template <int R, typename T>
+struct RawRows {
+    T v[R];
+};
+template <int R, typename T>
+__device__ __forceinline__ RawRows<R, T> load_raw(const T* p) {
+    RawRows<R, T> r;
+    if constexpr (R == 2) {
+        if constexpr (sizeof(T) == 4) {
+            const float2 f = *reinterpret_cast<const float2*>(p);
+            r.v[0] = f.x;
+            r.v[1] = f.y;
+        } else {
+            const double2 f = *reinterpret_cast<const double2*>(p);
+            r.v[0] = f.x;
+            r.v[1] = f.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i) r.v[i] = p[i];
+    }
+    return r;
+}
+
+// x[r][c] -= sum_{u<4} Q(r, j + u) C(j + u, c): one group of four update columns.
+template <int W, int R, typename T>
+__device__ __forceinline__ void update_group(double (&x)[R][W], const RawRows<R, T> (&q)[4], CD C, int j, int pu) {
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        double cu[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cu[u] = C[j + u + c * pu];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double v = x[r][c];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v -= static_cast<double>(q[u].v[r]) * cu[u];
+            x[r][c] = v;
+        }
+    }
+}
+
+template <int R, typename T>
+__device__ __forceinline__ void load_group(RawRows<R, T> (&q)[4], const T* Q, int64_t ldq, int j) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = load_raw<R>(Q + (int64_t)(j + u) * ldq);
+    // keep the loads here: the scheduler would otherwise sink them to their first use
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// x[r][c] -= sum_j Q(r, j) C(j, c) over the pu columns of Q (Q points at this thread's
+// first row; all R rows lie below n).  Columns go in groups of four, and the next group's
+// loads are issued before the current group's FMAs (two register buffers in turn), so each
+// wave keeps a group of loads in flight while it computes.  The subtraction order (j
+// ascending per output column) is the same as in the generic path.
+template <int W, int R, typename T>
+__device__ __forceinline__ void update_rows(double (&x)[R][W], const T* Q, int64_t ldq, int pu, CD C) {
+    int j = 0;
+    if (pu >= 4) {
+        RawRows<R, T> qa[4], qb[4];
+        load_group<R, T>(qa, Q, ldq, 0);
+        // the last group's look-ahead loads it again (from cache) instead of branching
+        while (true) {
+            load_group<R, T>(qb, Q, ldq, min(j + 4, pu - 4));
+            update_group<W, R, T>(x, qa, C, j, pu);
+            j += 4;
+            if (j + 4 > pu) break;
+            load_group<R, T>(qa, Q, ldq, min(j + 4, pu - 4));
+            update_group<W, R, T>(x, qb, C, j, pu);
+            j += 4;
+            if (j + 4 > pu) break;
+        }
+    }
+    for (; j < pu; ++j) {
+        const RawRows<R, T> q = load_raw<R>(Q + (int64_t)j * ldq);
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            const double cj = C[j + c * pu];
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r][c] -= static_cast<double>(q.v[r]) * cj;
+        }
+    }
+}
+
 // One pass over the rows of `a` by workgroup wg of nwg.
 template <int W, typename T, int RED, bool UPD, int NTRSM, bool WRITE, int MTX>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const int nwg) {
@@ -162,32 +282,22 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
     using XS = typename std::conditional<sizeof(T) == 4, float, double>::type;
     __shared__ XS xs[HAS_RED ? W * LDX : 1];
     __shared__ uint64_t hs[RED == RED_SKETCH_SPARSE ? STRIP : 1];
-    __shared__ double sR[NTRSM > 0 ? NTRSM * W * W : 1];
     __shared__ double pred[MF ? 4 * 64 * C::NWAVE : 1];  // cross-wave tile sums
-    extern __shared__ double sC[];  // UPD coefficients, pu * W doubles (dynamic LDS)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int64_t n = a.n;
 
-    if constexpr (NTRSM > 0) {
-        for (int i = tid; i < W * W; i += NT) {
-            sR[i] = a.R1[i];
-            if constexpr (NTRSM > 1) sR[W * W + i] = a.R2[i];
-        }
-    }
-    if constexpr (UPD) {
-        for (int i = tid; i < a.pu * W; i += NT) sC[i] = a.Cu[i];
-    }
-    if constexpr (NTRSM > 0 || UPD) __syncthreads();
-
+    // triangular factors (W x W, column-major) and update coefficients (pu x W)
+    const CD gR0[2] = {as_uniform(a.R1), as_uniform(a.R2)};
+    const CD gC0 = as_uniform(a.Cu);
     double rinv[NTRSM > 0 ? NTRSM * W : 1];
     if constexpr (NTRSM > 0) {
 #pragma unroll
         for (int t = 0; t < NTRSM; ++t)
 #pragma unroll
-            for (int c = 0; c < W; ++c) rinv[t * W + c] = 1.0 / sR[t * W * W + c * W + c];
+            for (int c = 0; c < W; ++c) rinv[t * W + c] = uniform_d(1.0 / gR0[t][c * W + c]);
     }
 
     // Gram: this wave accumulates output rows [a_lo, a_lo + MAXA)
@@ -227,47 +337,29 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
     const int64_t nstrips = (n + STRIP - 1) / STRIP;
     for (int64_t s = wg; s < nstrips; s += nwg) {
         const int64_t base = s * STRIP;
-        // keep the triangular factors and update coefficients in LDS for wide blocks: the
-        // compiler would hoist every entry into registers for the whole sweep (w(w-1)/2 per
-        // factor), which for w >= 10 halves the resident waves; narrow blocks keep them
-        if constexpr ((NTRSM > 0 || UPD) && W >= 10) asm volatile("" ::: "memory");
+        // wide blocks load the factor and coefficient entries again per strip (w(w-1)/2 per
+        // factor would not fit the SGPRs for the whole sweep); narrow blocks may hold them
+        CD gR[2] = {gR0[0], gR0[1]};
+        CD gC = gC0;
+        if constexpr (W >= 10) {
+            gR[0] = per_strip(gR[0]);
+            gR[1] = per_strip(gR[1]);
+            gC = per_strip(gC);
+        }
         // ---------------- phase A: RPT consecutive rows per thread ----------------
         if constexpr (RPT == 1)
         {
             const int64_t row = base + tid;
-            double x[W];
+            double xa[1][W];
+            double(&x)[W] = xa[0];
             if (row < n) {
                 const T* Y = static_cast<const T*>(a.Y);
 #pragma unroll
                 for (int c = 0; c < W; ++c) x[c] = ldv(Y + row + c * a.ldy);
-                if constexpr (UPD) {
-                    const T* Q = static_cast<const T*>(a.Qu) + row;
-                    const int pu = a.pu;
-                    int j = 0;
-                    for (; j + 4 <= pu; j += 4) {
-                        const double q0 = ldv(Q + (int64_t)(j + 0) * a.ldqu);
-                        const double q1 = ldv(Q + (int64_t)(j + 1) * a.ldqu);
-                        const double q2 = ldv(Q + (int64_t)(j + 2) * a.ldqu);
-                        const double q3 = ldv(Q + (int64_t)(j + 3) * a.ldqu);
-#pragma unroll
-                        for (int c = 0; c < W; ++c) {
-                            double v = x[c];
-                            v -= q0 * sC[j + 0 + c * pu];
-                            v -= q1 * sC[j + 1 + c * pu];
-                            v -= q2 * sC[j + 2 + c * pu];
-                            v -= q3 * sC[j + 3 + c * pu];
-                            x[c] = v;
-                        }
-                    }
-                    for (; j < pu; ++j) {
-                        const double q = ldv(Q + (int64_t)j * a.ldqu);
-#pragma unroll
-                        for (int c = 0; c < W; ++c) x[c] -= q * sC[j + c * pu];
-                    }
-                }
+                if constexpr (UPD) update_rows<W, 1, T>(xa, static_cast<const T*>(a.Qu) + row, a.ldqu, a.pu, gC);
 #pragma unroll
                 for (int t = 0; t < NTRSM; ++t) {
-                    const double* R = sR + t * W * W;
+                    const CD R = gR[t];
 #pragma unroll
                     for (int c = 0; c < W; ++c) {
                         double v = x[c];
@@ -306,6 +398,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                     for (int r = 0; r < RPT; ++r) x[r][c] = v[r];
                 }
                 if constexpr (UPD) {
+                  if (vec && row0 + RPT - 1 < n) {
+                    update_rows<W, RPT, T>(x, static_cast<const T*>(a.Qu) + row0, a.ldqu, a.pu, gC);
+                  } else {
                     const T* Q = static_cast<const T*>(a.Qu);
                     const int pu = a.pu;
                     int j = 0;
@@ -315,8 +410,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                         for (int u = 0; u < 4; ++u) load_rows<RPT>(Q + (int64_t)(j + u) * a.ldqu, vec, row0, n, q[u]);
 #pragma unroll
                         for (int c = 0; c < W; ++c) {
-                            const double c0 = sC[j + 0 + c * pu], c1 = sC[j + 1 + c * pu];
-                            const double c2 = sC[j + 2 + c * pu], c3 = sC[j + 3 + c * pu];
+                            const double c0 = gC[j + 0 + c * pu], c1 = gC[j + 1 + c * pu];
+                            const double c2 = gC[j + 2 + c * pu], c3 = gC[j + 3 + c * pu];
 #pragma unroll
                             for (int r = 0; r < RPT; ++r) {
                                 double v = x[r][c];
@@ -333,15 +428,16 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                         load_rows<RPT>(Q + (int64_t)j * a.ldqu, vec, row0, n, q);
 #pragma unroll
                         for (int c = 0; c < W; ++c) {
-                            const double cj = sC[j + c * pu];
+                            const double cj = gC[j + c * pu];
 #pragma unroll
                             for (int r = 0; r < RPT; ++r) x[r][c] -= q[r] * cj;
                         }
                     }
+                  }
                 }
 #pragma unroll
                 for (int t = 0; t < NTRSM; ++t) {
-                    const double* R = sR + t * W * W;
+                    const CD R = gR[t];
 #pragma unroll
                     for (int c = 0; c < W; ++c) {
 #pragma unroll

@@ -59,12 +59,11 @@ hipError_t launch_pass(const PassKey& key, const PassArgs& args, int grid, hipSt
     if (key.upd && args.pu * key.W > kMaxUpdCoef) return hipErrorInvalidValue;
     if (key.red != RED_NONE && args.red_rows > s.rows) return hipErrorInvalidValue;
     if (grid < 1) return hipErrorInvalidValue;
-    const size_t lds = key.upd ? sizeof(double) * (size_t)args.pu * key.W : 0;
     if (br) {
         if (br->nact < 1) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(s.fnb, dim3(grid, br->nact), dim3(s.threads), lds, stream, args, *br);
+        hipLaunchKernelGGL(s.fnb, dim3(grid, br->nact), dim3(s.threads), 0, stream, args, *br);
     } else {
-        hipLaunchKernelGGL(s.fn, dim3(grid), dim3(s.threads), lds, stream, args);
+        hipLaunchKernelGGL(s.fn, dim3(grid), dim3(s.threads), 0, stream, args);
     }
     return hipGetLastError();
 }

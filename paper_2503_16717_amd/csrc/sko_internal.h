@@ -86,7 +86,7 @@ int pass_strip_rows(const PassKey& key);
 int pass_grid_cap(const PassKey& key);
 constexpr int kPassThreads = 256;
 constexpr int kMaxPassW = 16;
-constexpr int kMaxUpdCoef = 4096;   // pu * W doubles staged in LDS by an update pass
+constexpr int kMaxUpdCoef = 4096;   // pu * W update coefficients of one pass (p * w of one block step)
 
 // ---------------------------------------------------------------------------
 // Reduction of pass partials + the small dense step that consumes it.
