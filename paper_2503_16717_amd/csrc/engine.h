@@ -68,7 +68,15 @@ struct Engine {
                          const void* Qp, int64_t ldqp, SmallArgs small, double scale) {
         const int rpl = pass_rows_per_launch(W, first.red);
         if (first.red == RED_PROJ) first.tiles = (std::min(rpl, rows_total) + 15) / 16;
-        PassKey rest{W, f32, first.red, false, 0, false, first.tiles};
+        PassKey rest{W, first.f32, first.red, false, 0, false, first.tiles};
+        if (first.panel) {
+            // the remaining rows read the (updated) FP64 panel: a projection still against
+            // the FP32 basis, a sketch of the panel alone in FP64
+            if (first.red == RED_PROJ)
+                rest.panel = 1;
+            else
+                rest.f32 = false;
+        }
         const int G = (rows_total > rpl) ? grid_for({first, rest}) : grid_for({first});
         a.partials = partials;
         a.part_stride = part_stride;
@@ -178,15 +186,19 @@ struct Engine {
         const int mt = k.red == RED_PROJ ? (k.tiles >= 1 && k.tiles <= 4 ? 4 : k.tiles >= 5 && k.tiles <= 6 ? 6 : 8) : 0;
         char tl[16] = "";
         if (mt) snprintf(tl, sizeof tl, "/mt%d", mt);
-        snprintf(buf, sizeof buf, "pass W=%d %s red=%s%s upd=%d trsm=%d write=%d", k.W, k.f32 ? "f32" : "f64",
-                 reds[k.red], tl, (int)k.upd, k.ntrsm, (int)k.write);
+        const char* ty = k.panel == 1 ? "f64|f32" : k.panel == 2 ? "f64>f32" : k.f32 ? "f32" : "f64";
+        snprintf(buf, sizeof buf, "pass W=%d %s red=%s%s upd=%d trsm=%d write=%d", k.W, ty, reds[k.red], tl,
+                 (int)k.upd, k.ntrsm, (int)k.write);
         return buf;
     }
     // Algorithmic HBM bytes of one launch: every tall operand once (read or written).
     double pass_bytes(const PassKey& k, const PassArgs& a) const {
-        const double eb = f32 ? 4.0 : 8.0;
-        double cols = W + (k.write ? W : 0) + (k.upd ? a.pu : 0) + (k.red == RED_PROJ ? a.red_rows : 0);
-        double per_row = cols * eb + (k.red == RED_SKETCH_DENSE ? 8.0 * a.red_rows : 0.0);
+        const double eq = k.f32 ? 4.0 : 8.0;               // basis operand
+        const double ey = k.panel ? 8.0 : eq;              // input block
+        const double ex = k.panel == 1 ? 8.0 : eq;         // written block
+        double per_row = W * ey + (k.write ? W * ex : 0.0) +
+                         ((k.upd ? a.pu : 0) + (k.red == RED_PROJ ? a.red_rows : 0)) * eq +
+                         (k.red == RED_SKETCH_DENSE ? 8.0 * a.red_rows : 0.0);
         return per_row * rows_bytes;
     }
 };

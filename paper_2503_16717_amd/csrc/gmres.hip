@@ -39,6 +39,10 @@ struct GmCtx {
     sko_sketch sk;
     // device
     void* Q;
+    // mixed precision, two-stage: the FP64 panel (s + 1 columns, leading dimension ld) that
+    // holds a panel's start vector and its matrix-powers vectors until the panel step writes
+    // the orthogonalised columns into the FP32 basis (null otherwise)
+    double* P = nullptr;
     double* dinv;
     CsrView A;
     double *Tin, *Tout, *g, *gw, *H, *y, *res, *beta, *bnorm, *coef;
@@ -156,6 +160,23 @@ sko_status mpk(GmCtx& g, int from, int s) {
     return SKO_OK;
 }
 
+// Mixed precision, two-stage: the start vector (FP32 basis column `from`) widened into
+// column 0 of the FP64 panel and the s monomial vectors computed in FP64 from it.  Rounding
+// the nearly parallel monomial vectors to FP32 before they are orthogonalised would lose the
+// small components that carry the new Krylov directions; the panel step rounds only the
+// orthogonalised columns.
+sko_status mpk_panel(GmCtx& g, int from, int s) {
+    double* P = g.P;
+    SKO_HIP(launch_widen(g.n, static_cast<const float*>(col_ptr(g, from)), P, g.grid_cap, g.st));
+    for (int i = 1; i <= s; ++i) {
+        const int ev = g.c->prof.begin("spmv f32 values, f64 vectors",
+                                       (double)g.A.nnz * 8.0 + (double)g.n * 20.0, g.st);
+        SKO_HIP(launch_spmv_panel(g.A, P + (int64_t)(i - 1) * g.ld, P + (int64_t)i * g.ld, g.grid_cap, g.st));
+        g.c->prof.end(ev, g.st);
+    }
+    return SKO_OK;
+}
+
 sko_status gm_op(GmCtx& g, GmSmallArgs a) {
     a.m = g.m;
     a.s = g.s;
@@ -214,9 +235,11 @@ sko_status two_stage_panel(GmCtx& g, Engine& e, int k0, int i) {
     const double sk_scale = g.sk.kind == SKO_SKETCH_SPARSE_SIGN ? 1.0 / std::sqrt((double)g.sk.zeta) : 1.0;
     void* Qb = col_ptr(g, k0);
     const int loc = i * S, kk = k0 + loc;
-    if ((s = mpk(g, kk, S))) return s;
-    void* V = col_ptr(g, kk);
-    PassKey key{W, g.f32, red_sk, false, 0, false};
+    // the panel V: in the basis itself, or (mixed precision) in the FP64 panel buffer
+    const bool p64 = g.P != nullptr;
+    if ((s = p64 ? mpk_panel(g, kk, S) : mpk(g, kk, S))) return s;
+    void* V = p64 ? static_cast<void*>(g.P) : col_ptr(g, kk);
+    PassKey key{W, g.f32 && !p64, red_sk, false, 0, false};
     PassArgs a{};
     a.Y = V;
     a.ldy = g.ld;
@@ -228,7 +251,11 @@ sko_status two_stage_panel(GmCtx& g, Engine& e, int k0, int i) {
         sm.op = OP_STORE;
         sm.w = W;
         sm.out = g.Cpan;
-        if ((s = e.reduction({W, g.f32, RED_PROJ, false, 0, false}, pa, k0, V, g.ld, g.Q, g.ld, sm, 1.0))) return s;
+        PassKey pkey{W, g.f32, RED_PROJ, false, 0, false};
+        pkey.panel = p64 ? 1 : 0;
+        if ((s = e.reduction(pkey, pa, k0, V, g.ld, g.Q, g.ld, sm, 1.0))) return s;
+        key.f32 = g.f32;
+        key.panel = p64 ? 1 : 0;
         key.upd = true;
         key.write = true;
         a.Qu = g.Q;
@@ -256,9 +283,10 @@ sko_status two_stage_panel(GmCtx& g, Engine& e, int k0, int i) {
     fa.Y = V;
     fa.ldy = g.ld;
     fa.R1 = g.rho;
-    fa.X = V;
+    fa.X = col_ptr(g, kk);
     fa.ldx = g.ld;
     PassKey fkey{W, g.f32, RED_NONE, false, 1, true};
+    fkey.panel = p64 ? 2 : 0;
     if (loc > 0) {
         fkey.upd = true;
         fa.Qu = Qb;
@@ -415,6 +443,8 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     // ---- workspace
     Arena ar(c);
     const size_t o_Q = ar.reserve((size_t)eb * g.ld * (m + 1));
+    const bool panel64 = g.f32 && g.two;
+    const size_t o_P = panel64 ? ar.reserve(sizeof(double) * g.ld * g.W) : 0;
     const bool own_vals = g.jacobi || g.f32;
     const size_t o_val = own_vals ? ar.reserve((size_t)eb * A->nnz) : 0;
     const size_t o_dinv = g.jacobi ? ar.reserve(sizeof(double) * A->n) : 0;
@@ -433,6 +463,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     if ((s = ensure_pinned(c, 64))) return s;
     g.host = static_cast<double*>(c->pinned);
     g.Q = ar.at<void>(o_Q);
+    g.P = panel64 ? ar.at<double>(o_P) : nullptr;
     g.dinv = g.jacobi ? ar.at<double>(o_dinv) : nullptr;
     carve_small(g, ar.at<char>(o_small), L, k);
 

@@ -22,6 +22,10 @@ struct CsrView {
 };
 
 hipError_t launch_spmv(const CsrView& A, bool f32, const void* x, void* y, int grid_cap, hipStream_t st);
+// Mixed precision: one matrix-powers step of the FP64 panel (FP32 operator values, FP64
+// vectors), and the widening copy of an FP32 basis column into the panel.
+hipError_t launch_spmv_panel(const CsrView& A, const double* x, double* y, int grid_cap, hipStream_t st);
+hipError_t launch_widen(int64_t n, const float* x, double* y, int grid_cap, hipStream_t st);
 int residual_grid(int64_t n, int grid_cap);
 hipError_t launch_residual(const CsrView& A, const double* x, const double* b, bool f32, void* r, double* partials,
                            int grid, hipStream_t st);

@@ -246,6 +246,12 @@ __global__ void scale_values_kernel(int64_t nnz, const int32_t* __restrict__ col
     out[e] = static_cast<TV>(v);
 }
 
+// y = (double) x, grid-stride.
+__global__ void __launch_bounds__(NT) widen_kernel(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        y[i] = static_cast<double>(x[i]);
+}
+
 // ---------------------------------------------------------------------------
 // Hessenberg bookkeeping (one workgroup).  Column-major (m+1) x m arrays Tin, Tout;
 // g (m+1); scratch H ((m+1) x m).
@@ -548,6 +554,18 @@ hipError_t launch_spmv(const CsrView& A, bool f32, const void* x, void* y, int g
                                                   static_cast<const float*>(x), static_cast<float*>(y), grid_cap, st);
     return spmv_dispatch<double, double, double>(A.n, avg, A.rowptr, A.colind, static_cast<const double*>(A.val_op),
                                                  static_cast<const double*>(x), static_cast<double*>(y), grid_cap, st);
+}
+
+hipError_t launch_spmv_panel(const CsrView& A, const double* x, double* y, int grid_cap, hipStream_t st) {
+    const double avg = (double)A.nnz / (double)std::max<int64_t>(1, A.n);
+    return spmv_dispatch<float, double, double>(A.n, avg, A.rowptr, A.colind, static_cast<const float*>(A.val_op), x,
+                                                y, grid_cap, st);
+}
+
+hipError_t launch_widen(int64_t n, const float* x, double* y, int grid_cap, hipStream_t st) {
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + NT - 1) / NT, grid_cap));
+    hipLaunchKernelGGL(widen_kernel, dim3(grid), dim3(NT), 0, st, n, x, y);
+    return hipGetLastError();
 }
 
 int residual_grid(int64_t n, int grid_cap) {

@@ -25,6 +25,7 @@
 #include <type_traits>
 #include "batch.h"
 #include "sko_internal.h"
+#include "uniform.h"
 
 namespace sko {
 namespace passk {
@@ -46,40 +47,6 @@ struct Cfg {
     static constexpr int MT = SK ? 4 : 8;
     static constexpr int ROWS = MF ? 16 * MT : NWAVE * MAXA;
 };
-
-// Read-only uniform operands (update coefficients, triangular factors) are addressed
-// through the constant address space: every lane reads the same entry, so the loads go
-// through the scalar cache into SGPRs and the FMAs take them as scalar operands.  Through
-// LDS each entry would be a full wave-wide read, one per FMA, and the LDS read rate, not
-// HBM, would bound the wide passes.  The arrays are written by earlier launches only.
-typedef const __attribute__((address_space(4))) double* CD;
-
-// The pointer is the same for the whole workgroup; readfirstlane puts it in SGPRs even
-// where it was computed with vector instructions (the batched kernels' relocation).
-__device__ __forceinline__ CD as_uniform(const double* p) {
-    const unsigned long long v = (unsigned long long)p;
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-    return (CD)(((unsigned long long)hi << 32) | lo);
-}
-
-// Hides from the compiler that the pointer is the same in every strip, so the entries it
-// addresses are loaded again per strip instead of being held in registers for the whole
-// sweep (which for wide blocks costs more registers than the kernel can spare).
-__device__ __forceinline__ CD per_strip(CD p) {
-    unsigned long long v = (unsigned long long)p;
-    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
-    asm volatile("" : "+s"(lo), "+s"(hi));
-    return (CD)(((unsigned long long)hi << 32) | lo);
-}
-
-// A wave-uniform double moved into SGPRs.
-__device__ __forceinline__ double uniform_d(double v) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
 template <typename T>
 __device__ __forceinline__ double ldv(const T* p) {
@@ -174,100 +141,28 @@ __device__ __forceinline__ bool pair_aligned(const void* p, int64_t ld) {
     return p == nullptr || (((uintptr_t)p % (2 * sizeof(T))) == 0 && (ld % 2) == 0);
 }
 
-// R consecutive rows of one column in the storage type, loaded as one access (R == 2:
-// pair-aligned).  Kept unconverted until use, so a load issued ahead stays in flight.
-template <int R, typename T>
-struct RawRows {
-    T v[R];
+// Element types of a pass: TY the input block Y, TQ the basis operand (Qu of the update,
+// Qp of the projection), TX the written block X.  Plain passes use one storage type for
+// all three; the mixed-precision GMRES panel reads an FP64 panel against the FP32 basis.
+template <typename TY_, typename TQ_, typename TX_>
+struct Tys {
+    using TY = TY_;
+    using TQ = TQ_;
+    using TX = TX_;
 };
-template <int R, typename T>
-__device__ __forceinline__ RawRows<R, T> load_raw(const T* p) {
-    RawRows<R, T> r;
-    if constexpr (R == 2) {
-        if constexpr (sizeof(T) == 4) {
-            const float2 f = *reinterpret_cast<const float2*>(p);
-            r.v[0] = f.x;
-            r.v[1] = f.y;
-        } else {
-            const double2 f = *reinterpret_cast<const double2*>(p);
-            r.v[0] = f.x;
-            r.v[1] = f.y;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < R; ++i) r.v[i] = p[i];
-    }
-    return r;
-}
-
-// x[r][c] -= sum_{u<4} Q(r, j + u) C(j + u, c): one group of four update columns.
-template <int W, int R, typename T>
-__device__ __forceinline__ void update_group(double (&x)[R][W], const RawRows<R, T> (&q)[4], CD C, int j, int pu) {
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-        double cu[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) cu[u] = C[j + u + c * pu];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            double v = x[r][c];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v -= static_cast<double>(q[u].v[r]) * cu[u];
-            x[r][c] = v;
-        }
-    }
-}
-
-template <int R, typename T>
-__device__ __forceinline__ void load_group(RawRows<R, T> (&q)[4], const T* Q, int64_t ldq, int j) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) q[u] = load_raw<R>(Q + (int64_t)(j + u) * ldq);
-    // keep the loads here: the scheduler would otherwise sink them to their first use
-    __builtin_amdgcn_sched_barrier(0);
-}
-
-// x[r][c] -= sum_j Q(r, j) C(j, c) over the pu columns of Q (Q points at this thread's
-// first row; all R rows lie below n).  Columns go in groups of four, and the next group's
-// loads are issued before the current group's FMAs (two register buffers in turn), so each
-// wave keeps a group of loads in flight while it computes.  The subtraction order (j
-// ascending per output column) is the same as in the generic path.
-template <int W, int R, typename T>
-__device__ __forceinline__ void update_rows(double (&x)[R][W], const T* Q, int64_t ldq, int pu, CD C) {
-    int j = 0;
-    if (pu >= 4) {
-        RawRows<R, T> qa[4], qb[4];
-        load_group<R, T>(qa, Q, ldq, 0);
-        // the last group's look-ahead loads it again (from cache) instead of branching
-        while (true) {
-            load_group<R, T>(qb, Q, ldq, min(j + 4, pu - 4));
-            update_group<W, R, T>(x, qa, C, j, pu);
-            j += 4;
-            if (j + 4 > pu) break;
-            load_group<R, T>(qa, Q, ldq, min(j + 4, pu - 4));
-            update_group<W, R, T>(x, qb, C, j, pu);
-            j += 4;
-            if (j + 4 > pu) break;
-        }
-    }
-    for (; j < pu; ++j) {
-        const RawRows<R, T> q = load_raw<R>(Q + (int64_t)j * ldq);
-#pragma unroll
-        for (int c = 0; c < W; ++c) {
-            const double cj = C[j + c * pu];
-#pragma unroll
-            for (int r = 0; r < R; ++r) x[r][c] -= static_cast<double>(q.v[r]) * cj;
-        }
-    }
-}
 
 // One pass over the rows of `a` by workgroup wg of nwg.
-template <int W, typename T, int RED, bool UPD, int NTRSM, bool WRITE, int MTX>
+template <int W, typename TS, int RED, bool UPD, int NTRSM, bool WRITE, int MTX>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const int nwg) {
+    using TY = typename TS::TY;
+    using TQ = typename TS::TQ;
+    using TX = typename TS::TX;
     using C = Cfg<W, RED>;
     constexpr int NT = C::NT;
+    constexpr bool F32 = sizeof(TY) == 4 && sizeof(TQ) == 4 && sizeof(TX) == 4;
     // rows per thread in phase A: two for float storage (8-byte accesses), except for wide
-    // blocks with triangular solves, whose two rows would not fit the registers
-    constexpr int RPT = (sizeof(T) == 4 && (W <= 8 || NTRSM == 0)) ? 2 : 1;
+    // blocks with triangular solves or updates, whose two rows would not fit the registers
+    constexpr int RPT = (F32 && (W <= 8 || (NTRSM == 0 && !UPD))) ? 2 : 1;
     constexpr int STRIP = NT * RPT;
     constexpr int LDX = STRIP + 1;  // padded LDS leading dimension of the strip
     constexpr int RPL = STRIP / 64;
@@ -279,7 +174,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
     constexpr bool GRAM = RED == RED_GRAM;
     // the strip in LDS, in the storage type: float storage reduces the rounded values it
     // stores (and halves the LDS)
-    using XS = typename std::conditional<sizeof(T) == 4, float, double>::type;
+    using XS = typename std::conditional<sizeof(typename std::conditional<WRITE, TX, TY>::type) == 4, float,
+                                         double>::type;
     __shared__ XS xs[HAS_RED ? W * LDX : 1];
     __shared__ uint64_t hs[RED == RED_SKETCH_SPARSE ? STRIP : 1];
     __shared__ double pred[MF ? 4 * 64 * C::NWAVE : 1];  // cross-wave tile sums
@@ -332,8 +228,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
     }
 
     // 2-row vector accesses need every tall operand's column starts 2-element aligned
-    const bool vec = RPT == 2 && pair_aligned<T>(a.Y, a.ldy) && (!UPD || pair_aligned<T>(a.Qu, a.ldqu)) &&
-                     (!WRITE || pair_aligned<T>(a.X, a.ldx));
+    const bool vec = RPT == 2 && pair_aligned<TY>(a.Y, a.ldy) && (!UPD || pair_aligned<TQ>(a.Qu, a.ldqu)) &&
+                     (!WRITE || pair_aligned<TX>(a.X, a.ldx));
     const int64_t nstrips = (n + STRIP - 1) / STRIP;
     for (int64_t s = wg; s < nstrips; s += nwg) {
         const int64_t base = s * STRIP;
@@ -353,10 +249,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
             double xa[1][W];
             double(&x)[W] = xa[0];
             if (row < n) {
-                const T* Y = static_cast<const T*>(a.Y);
+                const TY* Y = static_cast<const TY*>(a.Y);
 #pragma unroll
                 for (int c = 0; c < W; ++c) x[c] = ldv(Y + row + c * a.ldy);
-                if constexpr (UPD) update_rows<W, 1, T>(xa, static_cast<const T*>(a.Qu) + row, a.ldqu, a.pu, gC);
+                if constexpr (UPD) update_rows<W, 1, TQ>(xa, static_cast<const TQ*>(a.Qu) + row, a.ldqu, a.pu, gC);
 #pragma unroll
                 for (int t = 0; t < NTRSM; ++t) {
                     const CD R = gR[t];
@@ -369,7 +265,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                     }
                 }
                 if constexpr (WRITE) {
-                    T* X = static_cast<T*>(a.X);
+                    TX* X = static_cast<TX*>(a.X);
 #pragma unroll
                     for (int c = 0; c < W; ++c) stv(X + row + c * a.ldx, x[c]);
                 }
@@ -389,7 +285,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
             const int64_t row0 = base + (int64_t)RPT * tid;
             double x[RPT][W];
             if (row0 < n) {
-                const T* Y = static_cast<const T*>(a.Y);
+                const TY* Y = static_cast<const TY*>(a.Y);
 #pragma unroll
                 for (int c = 0; c < W; ++c) {
                     double v[RPT];
@@ -399,9 +295,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                 }
                 if constexpr (UPD) {
                   if (vec && row0 + RPT - 1 < n) {
-                    update_rows<W, RPT, T>(x, static_cast<const T*>(a.Qu) + row0, a.ldqu, a.pu, gC);
+                    update_rows<W, RPT, TQ>(x, static_cast<const TQ*>(a.Qu) + row0, a.ldqu, a.pu, gC);
                   } else {
-                    const T* Q = static_cast<const T*>(a.Qu);
+                    const TQ* Q = static_cast<const TQ*>(a.Qu);
                     const int pu = a.pu;
                     int j = 0;
                     for (; j + 4 <= pu; j += 4) {
@@ -450,7 +346,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                     }
                 }
                 if constexpr (WRITE) {
-                    T* X = static_cast<T*>(a.X);
+                    TX* X = static_cast<TX*>(a.X);
 #pragma unroll
                     for (int c = 0; c < W; ++c) {
                         double v[RPT];
@@ -503,12 +399,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
             if constexpr (MF) {
                 // ---------------- phase B, MFMA tiles ----------------
                 const int g = lane >> 4, ci = lane & 15;
-                const T* Qp = static_cast<const T*>(a.Qp);
+                const TQ* Qp = static_cast<const TQ*>(a.Qp);
                 const double* Th = a.theta;
                 // 32-byte row pieces can be read as two 16-byte vectors when aligned
                 bool vec = false;
                 if constexpr (RED == RED_PROJ)
-                    vec = (a.ldqp % 4) == 0 && ((uintptr_t)Qp % (4 * sizeof(T))) == 0;
+                    vec = (a.ldqp % 4) == 0 && ((uintptr_t)Qp % (4 * sizeof(TQ))) == 0;
                 if constexpr (RED == RED_SKETCH_DENSE) vec = (a.ldtheta % 4) == 0 && ((uintptr_t)Th % 32) == 0;
                 constexpr int GPW = STRIP / 16 / C::NWAVE;  // 16-row groups per wave
                 const int g0 = WAVE_LOCAL ? wave * GPW : wave, gstep = WAVE_LOCAL ? 1 : C::NWAVE;
@@ -619,7 +515,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
 
 template <int W, typename T, int RED, bool UPD, int NTRSM, bool WRITE, int MTX = 0>
 __global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel(const PassArgs a) {
-    pass_body<W, T, RED, UPD, NTRSM, WRITE, MTX>(a, blockIdx.x, gridDim.x);
+    pass_body<W, Tys<T, T, T>, RED, UPD, NTRSM, WRITE, MTX>(a, blockIdx.x, gridDim.x);
+}
+
+// FP64 panel (Y) against the FP32 basis (Q), written as TX.
+template <int W, typename TX, int RED, bool UPD, int NTRSM, bool WRITE, int MTX = 0>
+__global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel_panel(const PassArgs a) {
+    pass_body<W, Tys<double, float, TX>, RED, UPD, NTRSM, WRITE, MTX>(a, blockIdx.x, gridDim.x);
 }
 
 // Batched form: the template arguments are moved to the system of blockIdx.y.
@@ -642,7 +544,7 @@ __global__ void __launch_bounds__((Cfg<W, RED>::NT)) pass_kernel_batched(const P
     a.ldqp = batch_ld(br, d, t.ldqp);
     a.partials = batch_ptr(br, sys, d, t.partials);
     a.sk_seed = d.seed;
-    pass_body<W, T, RED, UPD, NTRSM, WRITE, MTX>(a, blockIdx.x, gridDim.x);
+    pass_body<W, Tys<T, T, T>, RED, UPD, NTRSM, WRITE, MTX>(a, blockIdx.x, gridDim.x);
 }
 
 using KernelPtr = void (*)(const PassArgs);
@@ -683,6 +585,31 @@ KernelPtr select_w(const PassKey& k) {
         if (!u) return &pass_kernel<W, T, RED_NONE, false, 1, true>;
         return &pass_kernel<W, T, RED_NONE, true, 1, true>;
     }
+    return nullptr;
+}
+
+// The variants of the mixed-precision GMRES panel step: panel 1 reads the FP64 panel
+// against the FP32 basis and writes the panel (projection; update + sketch); panel 2 writes
+// the finished columns into the FP32 basis (update + solve).
+template <int W>
+KernelPtr select_w_panel(const PassKey& k) {
+    const int r = k.red;
+    const bool u = k.upd, wr = k.write;
+    const int t = k.ntrsm;
+    const int mt = (k.tiles >= 1 && k.tiles <= 4) ? 4 : (k.tiles >= 5 && k.tiles <= 6) ? 6 : 8;
+    if (k.panel == 1) {
+        if (!u && t == 0 && !wr && r == RED_PROJ)
+            return mt == 4   ? &pass_kernel_panel<W, double, RED_PROJ, false, 0, false, 4>
+                   : mt == 6 ? &pass_kernel_panel<W, double, RED_PROJ, false, 0, false, 6>
+                             : &pass_kernel_panel<W, double, RED_PROJ, false, 0, false>;
+        if (u && t == 0 && wr) {
+            if (r == RED_SKETCH_SPARSE) return &pass_kernel_panel<W, double, RED_SKETCH_SPARSE, true, 0, true>;
+            if (r == RED_SKETCH_DENSE) return &pass_kernel_panel<W, double, RED_SKETCH_DENSE, true, 0, true>;
+        }
+    }
+    if (k.panel == 2 && r == RED_NONE && t == 1 && wr)
+        return u ? &pass_kernel_panel<W, float, RED_NONE, true, 1, true>
+                 : &pass_kernel_panel<W, float, RED_NONE, false, 1, true>;
     return nullptr;
 }
 

@@ -70,6 +70,9 @@ struct PassKey {
     int ntrsm;
     bool write;
     int tiles = 0;     // projection: 16-row MFMA tiles one launch needs (0: the maximum)
+    // mixed-precision GMRES panel (f32 basis): 1 = FP64 panel Y read against the basis, FP64
+    // X; 2 = FP64 panel Y, X written into the FP32 basis; 0 = one storage type throughout
+    int panel = 0;
 };
 
 // Launch one pass over all n rows with `grid` workgroups (grid <= pass_grid_cap()).  With

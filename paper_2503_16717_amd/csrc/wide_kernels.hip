@@ -2,7 +2,8 @@
 // (Figs. 5 and 6: CholQR of the big panel, BCGS against the previous big panels).
 //
 //  wide_rowop   X = (Y - Qu Cu) R^{-1} row by row, one row per thread, the row kept in
-//               registers (compile-time maximum width, runtime width).
+//               registers (compile-time maximum width, runtime width); R and Cu are read
+//               through the scalar cache.
 //  wide_gemm_tn per-workgroup partials of C = A^T B for tall A (n x ma), B (n x nb),
 //               ma, nb <= 64, on v_mfma_f64_16x16x4 tiles.  A wave walks 16-row groups;
 //               lane l loads rows 4(l/16)..+3 of column 16t + l%16 of every 16-column tile
@@ -12,8 +13,11 @@
 //               t is the A operand of output tile row t and the B operand of output tile
 //               column t: no LDS staging.  For the Gram matrix (A == B) only output tiles on
 //               or above the diagonal are accumulated.
+#include <algorithm>
+
 #include "batch.h"
 #include "sko_internal.h"
+#include "uniform.h"
 
 namespace sko {
 namespace {
@@ -39,60 +43,82 @@ struct RowopArgs {
     int64_t ldx;
 };
 
+// v - sum_{q < c} x[q] Rc[q] for column c of a triangular solve, the factor entries loaded
+// in chunks of 8 (one chunk ahead of the FMAs that use it) so that only two chunks occupy
+// SGPRs at a time.
+template <int WB, int C>
+__device__ __forceinline__ double solve_col(const double (&x)[WB], CD Rc, double v) {
+    constexpr int NCH = (C + 7) / 8;
+    if constexpr (NCH > 0) {
+        double r[2][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (u < C) r[0][u] = Rc[u];
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            if (k + 1 < NCH) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (8 * (k + 1) + u < C) r[(k + 1) & 1][u] = Rc[8 * (k + 1) + u];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (8 * k + u < C) v -= x[8 * k + u] * r[k & 1][u];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return v;
+}
+
+template <int WB, int C>
+__device__ __forceinline__ void solve_cols(double (&x)[WB], CD Rs, int w, const double* sD) {
+    if constexpr (C < WB) {
+        if (C < w) {
+            x[C] = solve_col<WB, C>(x, Rs + (int64_t)C * w, x[C]) * sD[C];
+            solve_cols<WB, C + 1>(x, Rs, w, sD);
+        }
+    }
+}
+
+// One row per thread, grid-stride over strips of ROW_NT rows.  The factor R and the update
+// coefficients are read through the scalar cache (every lane uses the same entry), loaded
+// again per strip; only the diagonal reciprocals sit in LDS.
 template <int WB, typename T, bool UPD, bool TRSM>
-__device__ __forceinline__ void rowop_body(const RowopArgs& ra) {
+__device__ __forceinline__ void rowop_body(const RowopArgs& ra, const int wg, const int nwg) {
     const int64_t n = ra.n;
-    const int w = ra.w, pu = ra.pu;
+    const int w0 = ra.w, pu = ra.pu;
     const T* __restrict__ Y = static_cast<const T*>(ra.Y);
     const T* __restrict__ Qu = static_cast<const T*>(ra.Qu);
-    const double* __restrict__ Cu = ra.Cu;
-    const double* __restrict__ R = ra.R;
     T* X = static_cast<T*>(ra.X);
-    const int64_t ldy = ra.ldy, ldqu = ra.ldqu, ldx = ra.ldx;
-    extern __shared__ double lds[];
-    double* sR = lds;                              // w * w, then the w diagonal reciprocals
-    double* sD = lds + w * w;
-    double* sC = lds + (TRSM ? w * w + w : 0);     // pu * w
+    __shared__ double sD[TRSM ? WB : 1];
     const int tid = threadIdx.x;
-    if (TRSM) {
-        for (int i = tid; i < w * w; i += ROW_NT) sR[i] = R[i];
-        for (int i = tid; i < w; i += ROW_NT) sD[i] = 1.0 / R[i + i * w];
+    if constexpr (TRSM) {
+        for (int i = tid; i < w0; i += ROW_NT) sD[i] = 1.0 / ra.R[i + i * w0];
+        __syncthreads();
     }
-    if (UPD)
-        for (int i = tid; i < pu * w; i += ROW_NT) sC[i] = Cu[i];
-    __syncthreads();
-    for (int64_t row = (int64_t)blockIdx.x * ROW_NT + tid; row < n; row += (int64_t)gridDim.x * ROW_NT) {
-    double x[WB];
+    const CD R0 = as_uniform(ra.R), C0 = as_uniform(ra.Cu);
+    for (int64_t row = (int64_t)wg * ROW_NT + tid; row < n; row += (int64_t)nwg * ROW_NT) {
+        const CD Rs = per_strip(R0), Cs = per_strip(C0);
+        // column offsets from leading dimensions re-derived per strip (held for the sweep,
+        // 64 of them would not fit the SGPRs)
+        const int64_t ldy = per_strip(ra.ldy), ldx = per_strip(ra.ldx), ldqu = per_strip(ra.ldqu);
+        const int w = per_strip(w0);
+        double xa[1][WB];
+        double(&x)[WB] = xa[0];
 #pragma unroll
-    for (int c = 0; c < WB; ++c) x[c] = (c < w) ? ldv(Y + row + (int64_t)c * ldy) : 0.0;
-    if (UPD) {
-        for (int a = 0; a < pu; ++a) {
-            const double q = ldv(Qu + row + (int64_t)a * ldqu);
+        for (int c = 0; c < WB; ++c) x[c] = (c < w) ? ldv(Y + row + (int64_t)c * ldy) : 0.0;
+        if constexpr (UPD) update_rows<WB, 1, T>(xa, Qu + row, ldqu, pu, Cs, w);
+        if constexpr (TRSM) solve_cols<WB, 0>(x, Rs, w, sD);
 #pragma unroll
-            for (int c = 0; c < WB; ++c)
-                if (c < w) x[c] -= q * sC[a + c * pu];
-        }
-    }
-    if (TRSM) {
-#pragma unroll
-        for (int c = 0; c < WB; ++c) {
-            if (c < w) {
-                double v = x[c];
-#pragma unroll
-                for (int q = 0; q < c; ++q) v -= x[q] * sR[q + c * w];
-                x[c] = v * sD[c];
-            }
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < WB; ++c)
-        if (c < w) X[row + (int64_t)c * ldx] = static_cast<T>(x[c]);
+        for (int c = 0; c < WB; ++c)
+            if (c < w) X[row + (int64_t)c * ldx] = static_cast<T>(x[c]);
     }
 }
 
 template <int WB, typename T, bool UPD, bool TRSM>
 __global__ void __launch_bounds__(ROW_NT) wide_rowop_kernel(const RowopArgs ra) {
-    rowop_body<WB, T, UPD, TRSM>(ra);
+    rowop_body<WB, T, UPD, TRSM>(ra, blockIdx.x, gridDim.x);
 }
 
 template <int WB, typename T, bool UPD, bool TRSM>
@@ -109,7 +135,7 @@ __global__ void __launch_bounds__(ROW_NT) wide_rowop_kernel_batched(const RowopA
     ra.R = batch_ptr(br, sys, d, t.R);
     ra.X = batch_ptr(br, sys, d, t.X);
     ra.ldx = batch_ld(br, d, t.ldx);
-    rowop_body<WB, T, UPD, TRSM>(ra);
+    rowop_body<WB, T, UPD, TRSM>(ra, blockIdx.x, gridDim.x);
 }
 
 constexpr int GT = 256;   // threads (4 waves)
@@ -249,27 +275,40 @@ __global__ void __launch_bounds__(GT) wide_gemm_tn_kernel_batched(const GemmArgs
 }
 
 template <int WB, typename T, bool UPD, bool TRSM>
-void rowop_launch(const RowopArgs& ra, int grid, size_t lds, hipStream_t st, const BatchReloc* br) {
-    if (br)
-        hipLaunchKernelGGL((wide_rowop_kernel_batched<WB, T, UPD, TRSM>), dim3(grid, br->nact), dim3(ROW_NT), lds, st,
+void rowop_launch(const RowopArgs& ra, hipStream_t st, const BatchReloc* br) {
+    const int64_t strips = (ra.n + ROW_NT - 1) / ROW_NT;
+    if (br) {
+        // many systems at once: each workgroup takes up to 8 strips of its system
+        const int grid = (int)((strips + 7) / 8);
+        hipLaunchKernelGGL((wide_rowop_kernel_batched<WB, T, UPD, TRSM>), dim3(grid, br->nact), dim3(ROW_NT), 0, st,
                            ra, *br);
-    else
-        hipLaunchKernelGGL((wide_rowop_kernel<WB, T, UPD, TRSM>), dim3(grid), dim3(ROW_NT), lds, st, ra);
+        return;
+    }
+    // resident workgroups only: each walks its strips
+    static int cap = 0;
+    if (cap == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(&wide_rowop_kernel<WB, T, UPD, TRSM>), ROW_NT, 0) ==
+                hipSuccess)
+            cap = std::max(1, per_cu) * std::max(1, cus);
+        else
+            cap = 1024;
+    }
+    const int grid = (int)std::min<int64_t>(strips, cap);
+    hipLaunchKernelGGL((wide_rowop_kernel<WB, T, UPD, TRSM>), dim3(grid), dim3(ROW_NT), 0, st, ra);
 }
 
 template <int WB, typename T>
 hipError_t rowop_dispatch(const RowopArgs& ra, hipStream_t st, const BatchReloc* br) {
-    // one row per thread; in a batched launch (many systems at once) each workgroup takes
-    // up to 8 strips of its system
-    const int64_t strips = (ra.n + ROW_NT - 1) / ROW_NT;
-    const int grid = (int)(br ? (strips + 7) / 8 : strips);
-    const size_t lds = sizeof(double) * ((ra.R ? (size_t)ra.w * ra.w + ra.w : 0) + (ra.pu > 0 ? (size_t)ra.pu * ra.w : 0));
     if (ra.pu > 0 && ra.R)
-        rowop_launch<WB, T, true, true>(ra, grid, lds, st, br);
+        rowop_launch<WB, T, true, true>(ra, st, br);
     else if (ra.pu > 0)
-        rowop_launch<WB, T, true, false>(ra, grid, lds, st, br);
+        rowop_launch<WB, T, true, false>(ra, st, br);
     else if (ra.R)
-        rowop_launch<WB, T, false, true>(ra, grid, lds, st, br);
+        rowop_launch<WB, T, false, true>(ra, st, br);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -290,8 +329,6 @@ hipError_t launch_wide_rowop(int64_t n, int W, bool f32, const void* Y, int64_t 
                              const BatchReloc* br) {
     if (W < 1 || W > 64 || n < 1) return hipErrorInvalidValue;
     if (br && br->nact < 1) return hipErrorInvalidValue;
-    if (sizeof(double) * ((R ? (size_t)W * W + W : 0) + (size_t)(pu > 0 ? pu : 0) * W) > 60 * 1024)
-        return hipErrorInvalidValue;
     const RowopArgs ra{n, W, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx};
     if (W <= 16) return f32 ? rowop_dispatch<16, float>(ra, st, br) : rowop_dispatch<16, double>(ra, st, br);
     if (W <= 24) return f32 ? rowop_dispatch<24, float>(ra, st, br) : rowop_dispatch<24, double>(ra, st, br);

@@ -117,6 +117,24 @@ def test_mixed_precision_reaches_fp64_tolerance(B, ctx, two_stage):
     assert explicit_relres(A, x.cpu().numpy(), b) <= 1.01e-10
 
 
+@pytest.mark.parametrize("s,shat,m", [(5, 20, 60), (10, 60, 60)])
+def test_mixed_two_stage_tracks_fp64_iterations(B, ctx, s, shat, m):
+    """Mixed precision, two-stage: the matrix-powers vectors of a panel stay in FP64 until
+    the panel step writes the orthogonalised columns into the FP32 basis, so the iteration
+    count follows the FP64 solve (to one check interval) instead of growing with the
+    conditioning of the monomial panel.  k = 128 sketch rows take two sketch launches;
+    s_hat < m projects panels on earlier big panels of the FP32 basis."""
+    A = wl.convdiff_3d(16, (10.0, 20.0, 30.0))
+    b = np.ones(A.n)
+    kw = dict(s=s, m=m, shat=shat, two_stage=True, precond=1, tol=1e-10,
+              sketch=B.make_sketch("sparse_sign", 128, 8, 0))
+    x64, i64, st64 = ctx.gmres(A, b, **kw)
+    x32, i32, st32 = ctx.gmres(A, b, precision="mixed", **kw)
+    assert st64 == B.SKO_OK and st32 == B.SKO_OK, (i64, i32)
+    assert explicit_relres(A, x32.cpu().numpy(), b) <= 1.01e-10
+    assert i32["iters"] <= i64["iters"] + shat, (i32["iters"], i64["iters"])
+
+
 def test_maxiter_and_resume(B, ctx):
     """ENOCONV at maxiter with a valid partial x; resuming from it converges (restart = resume)."""
     A = wl.convdiff_2d(24, 30.0, 10.0)
