@@ -36,7 +36,11 @@ def common_flags() -> list[str]:
             f"-I{INCLUDE}", f"-I{CSRC}"]
 
 
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=fast"]
+# MFMA accumulators in ordinary VGPRs: the loops that carry them across strips otherwise copy
+# every accumulator between AGPRs and VGPRs per iteration, and the split register classes
+# cost resident waves.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=fast",
+                "-mllvm", "--amdgpu-mfma-vgpr-form"]
 
 
 def sources() -> list[str]:

@@ -210,20 +210,28 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
     for (int m = 0; m < (MF ? MT : 1); ++m) dacc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
 
     // Sparse sketch: the MFMA A operand of lane l is Theta[row][16m + l % 16]; that sketch
-    // row is slot j of hash byte t, so the lane keeps (8t, j) per tile.
-    int sk_shift[RED == RED_SKETCH_SPARSE ? MT : 1];
-    int sk_slot[RED == RED_SKETCH_SPARSE ? MT : 1];
-    unsigned sk_B = 1;
+    // row is slot j of hash byte t (B = k / zeta slots per byte).  Byte b selects slot
+    // floor((b >> 1) B / 128), which equals j exactly when 2 ceil(128 j / B) <= b <
+    // 2 ceil(128 (j + 1) / B); the lane keeps, per tile, which 32-bit half of the hash holds
+    // byte t, the byte's bit offset there, and that range (empty for lanes past the sketch).
+    unsigned sk_half[RED == RED_SKETCH_SPARSE ? MT : 1];
+    unsigned sk_off[RED == RED_SKETCH_SPARSE ? MT : 1];
+    unsigned sk_lo[RED == RED_SKETCH_SPARSE ? MT : 1];
+    unsigned sk_wid[RED == RED_SKETCH_SPARSE ? MT : 1];
     if constexpr (RED == RED_SKETCH_SPARSE) {
-        sk_B = (unsigned)(a.sk_k / a.sk_zeta);
+        const int B = a.sk_k / a.sk_zeta;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             const int loc = 16 * m + (lane & 15);
             const int g = a.red_row0 + loc;
-            const int t = g / (int)sk_B;
+            const int t = g / B;
+            const int j = g - t * B;
             const bool live = loc < a.red_rows && t < a.sk_zeta;
-            sk_shift[m] = live ? 8 * t : 0;
-            sk_slot[m] = live ? g - t * (int)sk_B : -1;  // -1 never matches a slot
+            const unsigned lo = (unsigned)((128 * j + B - 1) / B), hi = (unsigned)((128 * (j + 1) + B - 1) / B);
+            sk_half[m] = live ? (unsigned)(t >> 2) : 0u;
+            sk_off[m] = live ? 8u * (unsigned)(t & 3) : 0u;
+            sk_lo[m] = 2u * lo;
+            sk_wid[m] = live ? 2u * (hi - lo) : 0u;
         }
     }
 
@@ -417,24 +425,42 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                     double bv[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) bv[u] = (ci < W) ? xs[ci * LDX + r0 + u] : 0.0;
-                    uint64_t h[RED == RED_SKETCH_SPARSE ? 4 : 1];
+                    unsigned hl[RED == RED_SKETCH_SPARSE ? 4 : 1], hh[RED == RED_SKETCH_SPARSE ? 4 : 1];
                     if constexpr (RED == RED_SKETCH_SPARSE) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) h[u] = hs[r0 + u];
+                        for (int u = 0; u < 4; ++u) {
+                            const uint64_t h = hs[r0 + u];
+                            hl[u] = (unsigned)h;
+                            hh[u] = (unsigned)(h >> 32);
+                        }
                     }
+                    if constexpr (RED == RED_SKETCH_SPARSE) {
+                        // decode every tile's operand first (high words of +-1.0 / 0.0), then
+                        // issue the MFMAs row step by row step across the tiles, so consecutive
+                        // MFMAs accumulate into different tiles.  Tiles past the launch's rows
+                        // decode to zero (no lane holds a live slot) and are not written out.
+                        unsigned top[MT][4];
+#pragma unroll
+                        for (int m = 0; m < MT; ++m)
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const unsigned b = ((sk_half[m] ? hh[u] : hl[u]) >> sk_off[m]) & 0xffu;
+                                // +-1.0 from the sign bit (bit 0 of the byte), 0.0 off the slot
+                                top[m][u] = (b - sk_lo[m]) < sk_wid[m] ? ((b << 31) | 0x3FF00000u) : 0u;
+                            }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int m = 0; m < MT; ++m)
+                                dacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double((int)top[m][u], 0),
+                                                                              bv[u], dacc[m], 0, 0, 0);
+                    } else {
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
                         if (m < ntiles) {
                             const int col = 16 * m + ci;
                             double av[4] = {0.0, 0.0, 0.0, 0.0};
-                            if constexpr (RED == RED_SKETCH_SPARSE) {
-#pragma unroll
-                                for (int u = 0; u < 4; ++u) {
-                                    const unsigned b = (unsigned)(h[u] >> sk_shift[m]) & 0xffu;
-                                    const int slot = (int)(((b >> 1) * sk_B) >> 7);
-                                    av[u] = (slot == sk_slot[m]) ? ((b & 1u) ? -1.0 : 1.0) : 0.0;
-                                }
-                            } else if (col < a.red_rows) {
+                            if (col < a.red_rows) {
                                 if constexpr (RED == RED_PROJ)
                                     load_col4(Qp + (int64_t)col * a.ldqp + base + r0, vec, full, base + r0, n, av);
                                 else
@@ -444,6 +470,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                             for (int u = 0; u < 4; ++u)
                                 dacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], dacc[m], 0, 0, 0);
                         }
+                    }
                     }
                 }
             } else if constexpr (GRAM) {
