@@ -204,7 +204,16 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[i][c] = 0.0;
     // MFMA accumulators: tile m covers output rows 16m..16m+15 of this launch
-    double4_t dacc[MF ? MT : 1];
+    // The sparse sketch runs on v_mfma_f64_4x4x4 (four independent 4 x 4 x 4 blocks per
+    // instruction, the same FP64 rate as 16 x 16 x 4): a block covers 4 sketch rows x 4 columns
+    // of x, so narrow panels do not pay for 16 padded columns.  Instruction (m, cb) holds the
+    // sketch rows 16m..16m+15 (block b: rows 16m + 4b..+3) and the columns 4cb..4cb+3.
+    constexpr bool SP4 = RED == RED_SKETCH_SPARSE;
+    constexpr int CB = (W + 3) / 4;
+    double4_t dacc[(MF && !SP4) ? MT : 1];
+    double acc4[SP4 ? MT * CB : 1];
+#pragma unroll
+    for (int i = 0; i < (SP4 ? MT * CB : 1); ++i) acc4[i] = 0.0;
     const int ntiles = (a.red_rows + 15) / 16;
 #pragma unroll
     for (int m = 0; m < (MF ? MT : 1); ++m) dacc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
@@ -422,9 +431,21 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                 for (int gam = g0, it = 0; it < GPW; gam += gstep, ++it) {
                     const int r0 = gam * 16 + 4 * g;  // strip-local rows r0..r0+3 for this lane
                     const bool full = base + r0 + 3 < n;
-                    double bv[4];
+                    // B operands: 16 x 16 x 4 tiles take column ci of the 4 rows; 4 x 4 x 4 blocks
+                    // take column 4cb + lane % 4
+                    double bv[SP4 ? 1 : 4];
+                    double bq[SP4 ? CB : 1][4];
+                    if constexpr (SP4) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) bv[u] = (ci < W) ? xs[ci * LDX + r0 + u] : 0.0;
+                        for (int cb = 0; cb < CB; ++cb) {
+                            const int col = 4 * cb + (lane & 3);
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) bq[cb][u] = (col < W) ? (double)xs[col * LDX + r0 + u] : 0.0;
+                        }
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) bv[u] = (ci < W) ? xs[ci * LDX + r0 + u] : 0.0;
+                    }
                     unsigned hl[RED == RED_SKETCH_SPARSE ? 4 : 1], hh[RED == RED_SKETCH_SPARSE ? 4 : 1];
                     if constexpr (RED == RED_SKETCH_SPARSE) {
 #pragma unroll
@@ -451,9 +472,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
 #pragma unroll
-                            for (int m = 0; m < MT; ++m)
-                                dacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double((int)top[m][u], 0),
-                                                                              bv[u], dacc[m], 0, 0, 0);
+                            for (int m = 0; m < MT; ++m) {
+                                const double av = __hiloint2double((int)top[m][u], 0);
+#pragma unroll
+                                for (int cb = 0; cb < CB; ++cb)
+                                    acc4[m * CB + cb] =
+                                        __builtin_amdgcn_mfma_f64_4x4x4f64(av, bq[cb][u], acc4[m * CB + cb], 0, 0, 0);
+                            }
                     } else {
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
@@ -502,7 +527,32 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
         }
     }
 
-    if constexpr (MF) {
+    if constexpr (SP4) {
+        // v_mfma_f64_4x4x4 output layout (measured on gfx950): D[i][j] of block b sits in lane
+        // 4b + j + 16i, so lane l holds sketch row 16m + 4((l % 16) / 4) + l / 16 and column
+        // 4cb + l % 4 of instruction (m, cb).  The waves' values are summed through LDS in wave
+        // order.
+        double* out = a.partials + (int64_t)wg * a.part_stride;
+        const int srow = 4 * ((lane & 15) >> 2) + (lane >> 4);
+        const int col = lane & 3;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if (m >= ntiles) break;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) pred[(wave * 4 + cb) * 64 + lane] = acc4[m * CB + cb];
+            __syncthreads();
+            if (wave == 0) {
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    double v = 0.0;
+                    for (int w2 = 0; w2 < C::NWAVE; ++w2) v += pred[(w2 * 4 + cb) * 64 + lane];
+                    const int r = 16 * m + srow, c = 4 * cb + col;
+                    if (r < a.red_rows && c < W) out[(a.red_row0 + r) + (int64_t)c * a.part_rows_total] = v;
+                }
+            }
+            __syncthreads();
+        }
+    } else if constexpr (MF) {
         // v_mfma_f64_16x16x4 output layout (measured on gfx950): D[i][j] of a tile sits in
         // lane j + 16 * (i % 4), element i / 4.  The waves' tiles are summed through LDS in
         // wave order.
