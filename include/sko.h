@@ -108,8 +108,14 @@ typedef struct {
  *  two_stage      0 one-stage BCGS2 per s-step block; 1 two-stage with RandBCGS2.
  *  precond        0 none, 1 right Jacobi (M = diag(A)).
  *  intra, sketch  as for sko_orth_opts.
- *  precision      SKO_F64, or SKO_MIXED_F32 (basis and MPK in float, x and the
- *                 explicit residual in double).
+ *  precision      SKO_F64, or SKO_MIXED_F32 (basis in float; x and the explicit
+ *                 residual in double; the matrix-powers values in float.  The
+ *                 two-stage solver keeps each panel's start vector and s monomial
+ *                 vectors in a double panel buffer until the panel step writes the
+ *                 orthogonalised columns to the float basis: rounding the nearly
+ *                 parallel monomial vectors to float would cost iterations.  The
+ *                 one-stage and batched solvers write the monomial vectors to the
+ *                 float basis directly.)
  *  tol            stop when ||b - A x||_2 / ||b||_2 <= tol (explicit, double).
  *  maxiter        cap on generated basis vectors (0: 50000).
  */
