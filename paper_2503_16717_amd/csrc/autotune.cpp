@@ -82,7 +82,7 @@ sko_status autotune_orth_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const
     int pmax = 1, rows_max = w;
     for (Use& u : uses) {
         const int rpl = u.key.red != RED_NONE ? pass_rows_per_launch(w, u.key.red) : 0;
-        if (u.key.red == RED_PROJ) u.key.tiles = (std::min(rpl, u.rows) + 15) / 16;
+        if (u.key.red == RED_PROJ || u.key.red == RED_SKETCH_SPARSE) u.key.tiles = (std::min(rpl, u.rows) + 15) / 16;
         const void* id = pass_kernel_id(u.key);
         if (!id) return SKO_EUNSUPPORTED;
         groups[id].push_back(u);

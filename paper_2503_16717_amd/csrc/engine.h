@@ -67,7 +67,7 @@ struct Engine {
     sko_status reduction(PassKey first, PassArgs a, int rows_total, const void* Xsrc, int64_t ldxs,
                          const void* Qp, int64_t ldqp, SmallArgs small, double scale) {
         const int rpl = pass_rows_per_launch(W, first.red);
-        if (first.red == RED_PROJ) first.tiles = (std::min(rpl, rows_total) + 15) / 16;
+        if (first.red == RED_PROJ || first.red == RED_SKETCH_SPARSE) first.tiles = (std::min(rpl, rows_total) + 15) / 16;
         PassKey rest{W, first.f32, first.red, false, 0, false, first.tiles};
         if (first.panel) {
             // the remaining rows read the (updated) FP64 panel: a projection still against

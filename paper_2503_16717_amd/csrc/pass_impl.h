@@ -42,9 +42,10 @@ struct Cfg {
     static constexpr int NWAVE = NT / 64;
     // Gram: output rows per wave (accumulators per lane = MAXA * W), spread over all waves
     static constexpr int MAXA = (W + NWAVE - 1) / NWAVE;
-    // MFMA tiles of 16 output rows held by every wave (sketch sizes up to 64 rows in one
-    // launch; projections up to 128 previous columns)
-    static constexpr int MT = SK ? 4 : 8;
+    // MFMA tiles of 16 output rows held by every wave (a dense sketch up to 64 rows in one
+    // launch; a sparse sketch up to 128 rows; projections up to 128 previous columns).  Fewer
+    // tiles are instantiated for launches that need fewer (more resident waves).
+    static constexpr int MT = RED == RED_SKETCH_DENSE ? 4 : 8;
     static constexpr int ROWS = MF ? 16 * MT : NWAVE * MAXA;
 };
 
@@ -641,13 +642,17 @@ KernelPtr select_w(const PassKey& k) {
                    : mt == 6 ? &pass_kernel<W, T, RED_PROJ, false, 0, false, 6>
                              : &pass_kernel<W, T, RED_PROJ, false, 0, false>;
         if (r == RED_GRAM) return &pass_kernel<W, T, RED_GRAM, false, 0, false>;
-        if (r == RED_SKETCH_SPARSE) return &pass_kernel<W, T, RED_SKETCH_SPARSE, false, 0, false>;
+        if (r == RED_SKETCH_SPARSE)
+            return mt == 4 ? &pass_kernel<W, T, RED_SKETCH_SPARSE, false, 0, false, 4>
+                           : &pass_kernel<W, T, RED_SKETCH_SPARSE, false, 0, false>;
         if (r == RED_SKETCH_DENSE) return &pass_kernel<W, T, RED_SKETCH_DENSE, false, 0, false>;
     }
     if (u && t == 0 && wr) {
         if (r == RED_NONE) return &pass_kernel<W, T, RED_NONE, true, 0, true>;
         if (r == RED_GRAM) return &pass_kernel<W, T, RED_GRAM, true, 0, true>;
-        if (r == RED_SKETCH_SPARSE) return &pass_kernel<W, T, RED_SKETCH_SPARSE, true, 0, true>;
+        if (r == RED_SKETCH_SPARSE)
+            return mt == 4 ? &pass_kernel<W, T, RED_SKETCH_SPARSE, true, 0, true, 4>
+                           : &pass_kernel<W, T, RED_SKETCH_SPARSE, true, 0, true>;
         if (r == RED_SKETCH_DENSE) return &pass_kernel<W, T, RED_SKETCH_DENSE, true, 0, true>;
     }
     if (!u && t == 1 && !wr && r == RED_GRAM) return &pass_kernel<W, T, RED_GRAM, false, 1, false>;
@@ -680,7 +685,9 @@ KernelPtr select_w_panel(const PassKey& k) {
                    : mt == 6 ? &pass_kernel_panel<W, double, RED_PROJ, false, 0, false, 6>
                              : &pass_kernel_panel<W, double, RED_PROJ, false, 0, false>;
         if (u && t == 0 && wr) {
-            if (r == RED_SKETCH_SPARSE) return &pass_kernel_panel<W, double, RED_SKETCH_SPARSE, true, 0, true>;
+            if (r == RED_SKETCH_SPARSE)
+                return mt == 4 ? &pass_kernel_panel<W, double, RED_SKETCH_SPARSE, true, 0, true, 4>
+                               : &pass_kernel_panel<W, double, RED_SKETCH_SPARSE, true, 0, true>;
             if (r == RED_SKETCH_DENSE) return &pass_kernel_panel<W, double, RED_SKETCH_DENSE, true, 0, true>;
         }
     }
@@ -701,9 +708,13 @@ BatchedKernelPtr select_w_batched(const PassKey& k) {
         if (r == RED_PROJ)
             return few ? &pass_kernel_batched<W, T, RED_PROJ, false, 0, false, 4>
                        : &pass_kernel_batched<W, T, RED_PROJ, false, 0, false>;
-        if (r == RED_SKETCH_SPARSE) return &pass_kernel_batched<W, T, RED_SKETCH_SPARSE, false, 0, false>;
+        if (r == RED_SKETCH_SPARSE)
+            return few ? &pass_kernel_batched<W, T, RED_SKETCH_SPARSE, false, 0, false, 4>
+                       : &pass_kernel_batched<W, T, RED_SKETCH_SPARSE, false, 0, false>;
     }
-    if (u && t == 0 && wr && r == RED_SKETCH_SPARSE) return &pass_kernel_batched<W, T, RED_SKETCH_SPARSE, true, 0, true>;
+    if (u && t == 0 && wr && r == RED_SKETCH_SPARSE)
+        return few ? &pass_kernel_batched<W, T, RED_SKETCH_SPARSE, true, 0, true, 4>
+                   : &pass_kernel_batched<W, T, RED_SKETCH_SPARSE, true, 0, true>;
     if (r == RED_NONE && t == 1 && wr) {
         if (!u) return &pass_kernel_batched<W, T, RED_NONE, false, 1, true>;
         return &pass_kernel_batched<W, T, RED_NONE, true, 1, true>;
