@@ -198,3 +198,51 @@ def test_mixed_precision_layouts(B, ctx, w, n, pad):
     assert metrics.orth_error(Qh)[0] <= 1e-5
     assert metrics.backward_error(V, Qh, R) <= 1e-6
     assert metrics.rel_diff(R, ref.R) <= 1e-5
+
+
+@pytest.mark.parametrize("k", [96, 128])
+@pytest.mark.parametrize("w", [6, 11])
+def test_sketch_beyond_four_tiles(B, ctx, k, w):
+    """Sparse sketches of 96 and 128 rows run as one launch of 8 tiles of 16 sketch rows (for
+    96 rows two tiles hold no live slot and are not written out)."""
+    n, nb, e = 20001, 3, 6
+    V = wl.glued_blocks(n, nb, w, e)
+    Q, R, st, col = gpu_orth(B, ctx, V, w, intra="randcholqr", sketch=B.make_sketch("sparse_sign", k, 8, 2))
+    assert st == B.SKO_OK
+    ref = orth.orth_blocks_one_stage(V, w, "randcholqr", Sketch.sparse_sign(k, 8, 2))
+    check_against_oracle(V, Q, R, ref, e)
+
+
+@pytest.mark.parametrize("n,nb", [(12, 2), (13, 2), (255, 3), (257, 3)])
+@pytest.mark.parametrize("intra", ["randcholqr", "cholqr2"])
+def test_few_rows(B, ctx, n, nb, intra):
+    """Fewer rows than one strip, down to a square matrix (n = nb w).  The R tolerance uses
+    the condition number of the whole matrix, which for so few rows exceeds the blocks' own."""
+    w = 6
+    V = wl.glued_blocks(n, nb, w, 3)
+    kw = dict(sketch=B.make_sketch("sparse_sign", 64, 8, 4)) if intra == "randcholqr" else {}
+    Q, R, st, col = gpu_orth(B, ctx, V, w, intra=intra, **kw)
+    assert st == B.SKO_OK
+    ref = orth.orth_blocks_one_stage(V, w, intra, Sketch.sparse_sign(64, 8, 4) if kw else None)
+    assert ref.info == 0
+    kappa = np.linalg.cond(V)
+    assert np.all(np.diag(R) > 0) and np.allclose(np.tril(R, -1), 0.0, atol=0.0)
+    assert metrics.rel_diff(R, ref.R) <= max(1e-12, 10.0 * kappa * U)
+    assert metrics.orth_error(Q)[0] <= 1e-13
+    assert metrics.backward_error(V, Q, R) <= 1e-14
+
+
+@pytest.mark.parametrize("intra", ["randcholqr", "cholqr2"])
+def test_zero_block_reports_breakdown(B, ctx, intra):
+    """An all-zero block has no QR with a positive diagonal: the call reports breakdown at a
+    column of that block (1-based), as the oracle does."""
+    n, w = 5000, 6
+    V = wl.glued_blocks(n, 3, w, 3)
+    V[:, w:2 * w] = 0.0
+    kw = dict(sketch=B.make_sketch("sparse_sign", 64, 8, 0)) if intra == "randcholqr" else {}
+    _, _, st, col = gpu_orth(B, ctx, V, w, intra=intra, raise_on_error=False, **kw)
+    assert st == B.SKO_EBREAKDOWN
+    assert w + 1 <= col <= 2 * w
+    ref = orth.orth_blocks_one_stage(V, w, intra, Sketch.sparse_sign(64, 8, 0) if kw else None)
+    assert ref.info != 0
+
