@@ -348,7 +348,6 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     const int N = nb * w;
     const int k = o->sketch.k;
     const int pmax = N - Wb;  // largest previous-basis width
-    if ((int64_t)pmax * Wb * 8 + (int64_t)Wb * Wb * 8 > 60 * 1024) return SKO_EUNSUPPORTED;
     if ((int64_t)(Wb - w) * w > kMaxUpdCoef || (int64_t)pmax * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
 
     // workspace

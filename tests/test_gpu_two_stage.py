@@ -107,3 +107,19 @@ def test_two_stage_rejects_small_sketch(B, ctx):
     V = wl.glued_blocks(1000, 6, 6, 2)
     _, _, st, _ = run(B, ctx, V, 6, 6, k=24)
     assert st == B.SKO_EINVAL
+
+
+def test_two_stage_many_big_panels(B, ctx):
+    """Six big panels of 36 columns (216 columns): the last big panel is projected on 180
+    previous columns, whose coefficients the wide row operation reads through the scalar
+    cache (no staging buffer bounds their number)."""
+    n, w, nb, ppb, e = 3000, 6, 36, 6, 4
+    V = wl.glued_blocks(n, nb, w, e)
+    Q, R, st, col = run(B, ctx, V, w, ppb)
+    assert st == B.SKO_OK, (st, col)
+    ref = orth.orth_blocks_two_stage(V, w, ppb, Sketch.sparse_sign(64, 8, 0))
+    assert ref.info == 0
+    kappa = np.linalg.cond(V)
+    assert metrics.rel_diff(R, ref.R) <= max(tol_r(e), 10.0 * kappa * U)
+    assert metrics.orth_error(Q)[0] <= 1e-13
+    assert metrics.backward_error(V, Q, R) <= 1e-14
