@@ -119,7 +119,8 @@ struct Engine {
         ra.ldo = ra.count;
         ra.small = small;
         ra.small.status = status;
-        const int ev = c->prof.begin("reduce+small", 8.0 * G * ra.count, st);
+        ra.unit_rows = kPassThreads;  // a strip is at least this many rows
+        const int ev = c->prof.begin(reduce_name(small.op), 8.0 * G * ra.count, st);
         SKO_HIP(launch_reduce(ra, st, br));
         c->prof.end(ev, st);
         return SKO_OK;
@@ -148,7 +149,8 @@ struct Engine {
         ra.ldo = ldo;
         ra.small = small;
         ra.small.status = status;
-        const int ev2 = c->prof.begin("reduce+small", 8.0 * G * ra.count, st);
+        ra.unit_rows = kGemmUnitRows;
+        const int ev2 = c->prof.begin(reduce_name(small.op), 8.0 * G * ra.count, st);
         SKO_HIP(launch_reduce(ra, st, br));
         c->prof.end(ev2, st);
         return SKO_OK;
@@ -178,6 +180,17 @@ struct Engine {
         const int64_t ns32 = (n + 31) / 32;
         const int64_t want = br ? (ns32 + 63) / 64 : ns32;
         return (int)std::max<int64_t>(1, std::min<int64_t>(want, skinny_gemm_grid_cap()));
+    }
+
+    // Profiler name of a reduction launch: the partial sums and the small step that ends it.
+    static const char* reduce_name(int op) {
+        switch (op) {
+            case OP_STORE: return "reduce+store";
+            case OP_HH: return "reduce+householder";
+            case OP_CHOL: return "reduce+cholesky";
+            case OP_SKETCH_BCGS2: return "reduce+sketch-space bcgs2";
+            default: return "reduce+small";
+        }
     }
 
     static std::string pass_name(const PassKey& k) {

@@ -147,7 +147,14 @@ struct ReduceArgs {
     int rows;
     int64_t ldo;
     SmallArgs small;
+    // Rows the producing launch assigns to each workgroup index (workgroup g has rows only
+    // if g * unit_rows < n).  Batched launches size their grid for the largest system, so
+    // a smaller system's trailing workgroups wrote zero partials; its reduction sums only
+    // the first ceil(n / unit_rows).  0: all G.
+    int unit_rows = 0;
 };
+// Rows per workgroup index of the wide Gram / projection kernel (16-row groups, 4 waves).
+constexpr int kGemmUnitRows = 64;
 
 // Number of workgroups launch_reduce uses for `count` reduced values.
 int reduce_grid(int count);

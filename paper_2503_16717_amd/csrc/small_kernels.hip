@@ -397,6 +397,10 @@ __global__ void __launch_bounds__(RT) reduce_kernel_batched(const ReduceArgs t, 
     const int sys = batch_system(br);
     const BatchSys& d = br.sys[sys];
     ReduceArgs a = t;
+    if (t.unit_rows > 0) {
+        const int64_t units = (d.n + t.unit_rows - 1) / t.unit_rows;
+        if (units < a.G) a.G = (int)units;
+    }
     a.partials = batch_ptr(br, sys, d, t.partials);
     a.counter = batch_ptr(br, sys, d, t.counter);
     SmallArgs& m = a.small;

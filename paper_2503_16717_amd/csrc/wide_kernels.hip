@@ -139,6 +139,7 @@ __global__ void __launch_bounds__(ROW_NT) wide_rowop_kernel_batched(const RowopA
 }
 
 constexpr int GT = 256;   // threads (4 waves)
+static_assert(16 * (GT / 64) == kGemmUnitRows, "a workgroup index covers 16 rows per wave");
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
