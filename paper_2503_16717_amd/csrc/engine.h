@@ -156,12 +156,13 @@ struct Engine {
         return SKO_OK;
     }
 
+    // Rpk: the triangular factor packed by the Cholesky step that produced it (SmallArgs::Rpk)
     sko_status rowop(int Wd, const void* Y, int64_t ldy, const void* Qu, int64_t ldqu, int pu, const double* Cu,
-                     const double* R, void* X, int64_t ldx) {
+                     const double* Rpk, void* X, int64_t ldx) {
         const int ev = c->prof.begin(std::string("wide_rowop f") + (f32 ? "32" : "64") + (pu > 0 ? " upd" : "") +
-                                         (R ? " trsm" : ""),
+                                         (Rpk ? " trsm" : ""),
                                      rows_bytes * (2 * Wd + pu) * (f32 ? 4.0 : 8.0), st);
-        SKO_HIP(launch_wide_rowop(n, Wd, f32, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx, st, br));
+        SKO_HIP(launch_wide_rowop(n, Wd, f32, Y, ldy, Qu, ldqu, pu, Cu, Rpk, X, ldx, st, br));
         c->prof.end(ev, st);
         return SKO_OK;
     }

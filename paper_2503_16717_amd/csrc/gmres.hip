@@ -47,6 +47,7 @@ struct GmCtx {
     CsrView A;
     double *Tin, *Tout, *g, *gw, *H, *y, *res, *beta, *bnorm, *coef;
     double *Cpan, *Yacc, *rt, *rho, *Gb, *Rh, *Rt, *C2b;
+    double* Rpk;  // packed copy of Rh, then of Rt, for the row solves
     BlockBufs bb;
     int* status;
     int grid_cap;
@@ -73,7 +74,7 @@ SmallLayout small_layout(int m, int W, int k, int Wb, bool two) {
     L.gm = up(L.bb + sizeof(double) * (2 * mW + (size_t)std::max(k, W) * W + 5 * (size_t)W * W));
     L.ts = up(L.gm + sizeof(double) * (3 * (size_t)(m + 1) * m + 3 * (size_t)(m + 1) + 8 + (size_t)(m + 1) * W));
     L.st = up(L.ts + (two ? sizeof(double) * (mW + (size_t)k * Wb + (size_t)Wb * W + (size_t)W * W +
-                                              3 * (size_t)Wb * Wb + (size_t)m * Wb)
+                                              3 * (size_t)Wb * Wb + (size_t)m * Wb + (size_t)Wb * (Wb + 1) / 2)
                           : 0));
     L.bytes = up(L.st + 256);
     return L;
@@ -114,6 +115,7 @@ void carve_small(GmCtx& g, char* base, const SmallLayout& L, int k) {
         g.Rh = g.Gb + g.Wb * g.Wb;
         g.Rt = g.Rh + g.Wb * g.Wb;
         g.C2b = g.Rt + g.Wb * g.Wb;
+        g.Rpk = g.C2b + (int64_t)m * g.Wb;
     }
     g.status = reinterpret_cast<int*>(base + L.st);
 }
@@ -318,8 +320,9 @@ sko_status two_stage_bigclose(GmCtx& g, Engine& e, int k0) {
         sm.col0 = k0;
         sm.out = g.Gb;
         sm.R = g.Rh;
+        sm.Rpk = g.Rpk;
         if ((s = e.gemm_reduction(Qb, g.ld, Wb, Qb, g.ld, Wb, sm, Wb))) return s;
-        if ((s = e.rowop(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rh, Qb, g.ld))) return s;
+        if ((s = e.rowop(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rpk, Qb, g.ld))) return s;
     }
     const bool proj2 = g.reorth && k0 > 0;
     if (g.reorth) {
@@ -340,8 +343,9 @@ sko_status two_stage_bigclose(GmCtx& g, Engine& e, int k0) {
         sm.col0 = k0;
         sm.out = g.Gb;
         sm.R = g.Rt;
+        sm.Rpk = g.Rpk;
         if ((s = e.gemm_reduction(Qb, g.ld, Wb, Qb, g.ld, Wb, sm, Wb))) return s;
-        if ((s = e.rowop(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rt, Qb, g.ld))) return s;
+        if ((s = e.rowop(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rpk, Qb, g.ld))) return s;
     }
     GmSmallArgs ga{};
     ga.op = GM_BIGCLOSE;

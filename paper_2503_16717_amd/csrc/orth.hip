@@ -370,6 +370,7 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     const size_t o_G = ar.reserve(sizeof(double) * (size_t)Wb * Wb);
     const size_t o_Rh = ar.reserve(sizeof(double) * (size_t)Wb * Wb);
     const size_t o_Rt = ar.reserve(sizeof(double) * (size_t)Wb * Wb);
+    const size_t o_Rpk = ar.reserve(sizeof(double) * (size_t)Wb * (Wb + 1) / 2);
     const size_t o_Rf = ar.reserve(sizeof(double) * (size_t)N * N);
     const size_t o_st = ar.reserve(256);
     sko_status s = ensure_workspace(c, ar.used());
@@ -390,6 +391,7 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     double* Gb = ar.at<double>(o_G);
     double* Rh = ar.at<double>(o_Rh);
     double* Rt = ar.at<double>(o_Rt);
+    double* Rpk = ar.at<double>(o_Rpk);  // packed copy of Rh, then of Rt, for the row solves
     double* Rfull = ar.at<double>(o_Rf);
     SKO_HIP(hipMemsetAsync(e.status, 0, 256, c->stream));
     c->tickets = 0;
@@ -481,6 +483,7 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
             sm.col0 = p_old;
             sm.out = Gb;
             sm.R = Rh;
+            sm.Rpk = Rpk;
             if (!reorth) {
                 sm.assemble = 1;
                 sm.r_identity = 1;
@@ -492,7 +495,7 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
                 sm.ldr = N;
             }
             if ((s = e.gemm_reduction(Qb, ldq, Wb, Qb, ldq, Wb, sm, Wb))) return s;
-            if ((s = e.rowop(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rh, Qb, ldq))) return s;
+            if ((s = e.rowop(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rpk, Qb, ldq))) return s;
         }
         if (reorth) {
             if (p_old > 0) {
@@ -513,6 +516,7 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
             sm.col0 = p_old;
             sm.out = Gb;
             sm.R = Rt;
+            sm.Rpk = Rpk;
             sm.assemble = 1;
             sm.Ra = Rh;
             sm.Rb = Rbar;
@@ -522,7 +526,7 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
             sm.Rout = Rfull + (int64_t)p_old * N;
             sm.ldr = N;
             if ((s = e.gemm_reduction(Qb, ldq, Wb, Qb, ldq, Wb, sm, Wb))) return s;
-            if ((s = e.rowop(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rt, Qb, ldq))) return s;
+            if ((s = e.rowop(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rpk, Qb, ldq))) return s;
         }
     }
     double* Rhost = nullptr;

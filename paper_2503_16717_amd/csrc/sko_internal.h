@@ -108,6 +108,9 @@ struct SmallArgs {
     int col0;            // global 1-based column offset for breakdown reports
     double* out;         // reduced values (count doubles); OP_HH/OP_SKETCH_BCGS2: k x w sketch
     double* R;           // OP_HH / OP_CHOL / OP_SKETCH_BCGS2: w x w result (ld w)
+    // OP_CHOL, optional: R packed for the wide row solve, w reciprocal diagonal entries then
+    // the strictly upper part column by column (column c's c entries at w + c(c-1)/2)
+    double* Rpk;
     int* status;         // first breakdown column (0 = none)
     // OP_SKETCH_BCGS2
     double* Yacc;        // k x cap, column-major (ld k): accumulated orthonormal sketches
@@ -170,10 +173,11 @@ hipError_t launch_skinny_gemm_tn(int64_t n, const void* A, int64_t lda, int ma,
 int skinny_gemm_grid_cap();
 
 // Row-wise X = (Y - Qu Cu) * R^{-1} for wide blocks (w <= 64); used by the big-panel
-// close of the two-stage scheme.
+// close of the two-stage scheme.  Rpk is R in the packed form of SmallArgs::Rpk (null: no
+// solve).
 hipError_t launch_wide_rowop(int64_t n, int W, bool f32, const void* Y, int64_t ldy,
                              const void* Qu, int64_t ldqu, int pu, const double* Cu,
-                             const double* R, void* X, int64_t ldx, hipStream_t stream,
+                             const double* Rpk, void* X, int64_t ldx, hipStream_t stream,
                              const BatchReloc* br = nullptr);
 
 // Small matrix helpers on the device (single workgroup).

@@ -215,8 +215,9 @@ __device__ void householder_wave(double* A, int k, int w, double* E, double* R, 
 
 // Right-looking upper Cholesky of the w x w matrix G (LDS, column-major), w <= 64, run by
 // one wave: each column's pivot, row scaling and trailing update are wave-parallel and
-// ordered by wave-level fences only.  The caller synchronises the workgroup afterwards.
-__device__ void cholesky_wave(double* G, int w, double* R, int* status, int col0, double* scal) {
+// ordered by wave-level fences only.  Rpk (optional) receives the packed copy described at
+// SmallArgs::Rpk.  The caller synchronises the workgroup afterwards.
+__device__ void cholesky_wave(double* G, int w, double* R, double* Rpk, int* status, int col0, double* scal) {
     const int lane = threadIdx.x & 63;
     for (int idx = lane; idx < w * w; idx += 64) R[idx] = 0.0;
     for (int j = 0; j < w; ++j) {
@@ -227,6 +228,12 @@ __device__ void cholesky_wave(double* G, int w, double* R, int* status, int col0
             const double v = (c == j) ? r : G[j + c * w] / r;
             R[j + c * w] = v;
             scal[8 + c] = v;  // row j of R for the trailing update
+            if (Rpk) {
+                if (c == j)
+                    Rpk[j] = 1.0 / r;
+                else
+                    Rpk[w + c * (c - 1) / 2 + j] = v;
+            }
         }
         wave_sync();
         const int m = w - j - 1;
@@ -376,7 +383,7 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
         double* G = lds;
         for (int idx = tid; idx < s.w * s.w; idx += RT) G[idx] = load_coherent(s.out + idx);
         __syncthreads();
-        if (tid < 64) cholesky_wave(G, s.w, s.R, s.status, s.col0, scal);
+        if (tid < 64) cholesky_wave(G, s.w, s.R, s.Rpk, s.status, s.col0, scal);
         __syncthreads();
         if (s.assemble) {
             __threadfence();
@@ -406,6 +413,7 @@ __global__ void __launch_bounds__(RT) reduce_kernel_batched(const ReduceArgs t, 
     SmallArgs& m = a.small;
     m.out = batch_ptr(br, sys, d, t.small.out);
     m.R = batch_ptr(br, sys, d, t.small.R);
+    m.Rpk = batch_ptr(br, sys, d, t.small.Rpk);
     m.status = batch_ptr(br, sys, d, t.small.status);
     m.Yacc = batch_ptr(br, sys, d, t.small.Yacc);
     m.r = batch_ptr(br, sys, d, t.small.r);

@@ -3,7 +3,10 @@
 //
 //  wide_rowop   X = (Y - Qu Cu) R^{-1} row by row, one row per thread, the row kept in
 //               registers (compile-time maximum width, runtime width); R and Cu are read
-//               through the scalar cache.
+//               through the scalar cache.  R comes packed (reciprocal diagonal, then the
+//               strictly upper columns back to back): for 61 columns that is 14.6 KB, which
+//               the scalar cache holds, where the column-major square spans 18.6 KB of lines
+//               and a strip's sweep over it would miss on every chunk.
 //  wide_gemm_tn per-workgroup partials of C = A^T B for tall A (n x ma), B (n x nb),
 //               ma, nb <= 64, on v_mfma_f64_16x16x4 tiles.  A wave walks 16-row groups;
 //               lane l loads rows 4(l/16)..+3 of column 16t + l%16 of every 16-column tile
@@ -14,6 +17,7 @@
 //               column t: no LDS staging.  For the Gram matrix (A == B) only output tiles on
 //               or above the diagonal are accumulated.
 #include <algorithm>
+#include <type_traits>
 
 #include "batch.h"
 #include "sko_internal.h"
@@ -38,7 +42,8 @@ struct RowopArgs {
     int64_t ldqu;
     int pu;
     const double* Cu;
-    const double* R;
+    const double* Rpk;   // packed factor: w reciprocal diagonal entries, then column c's c
+                         // strictly upper entries at w + c(c-1)/2
     void* X;
     int64_t ldx;
 };
@@ -75,10 +80,19 @@ template <int WB, int C>
 __device__ __forceinline__ void solve_cols(double (&x)[WB], CD Rs, int w, const double* sD) {
     if constexpr (C < WB) {
         if (C < w) {
-            x[C] = solve_col<WB, C>(x, Rs + (int64_t)C * w, x[C]) * sD[C];
+            x[C] = solve_col<WB, C>(x, Rs + w + C * (C - 1) / 2, x[C]) * sD[C];
             solve_cols<WB, C + 1>(x, Rs, w, sD);
         }
     }
+}
+
+// The element a lane handles in a column, given the column's address at the strip's first
+// row (the same for the whole workgroup, so it is formed in SGPRs) and the lane's byte
+// offset in the strip (one VGPR shared by every column).
+template <typename T>
+__device__ __forceinline__ T* lane_elem(T* strip_col, uint32_t lane_bytes) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(strip_col) + lane_bytes);
 }
 
 // One row per thread, grid-stride over strips of ROW_NT rows.  The factor R and the update
@@ -93,12 +107,15 @@ __device__ __forceinline__ void rowop_body(const RowopArgs& ra, const int wg, co
     T* X = static_cast<T*>(ra.X);
     __shared__ double sD[TRSM ? WB : 1];
     const int tid = threadIdx.x;
+    const uint32_t lane_bytes = (uint32_t)tid * (uint32_t)sizeof(T);
     if constexpr (TRSM) {
-        for (int i = tid; i < w0; i += ROW_NT) sD[i] = 1.0 / ra.R[i + i * w0];
+        for (int i = tid; i < w0; i += ROW_NT) sD[i] = ra.Rpk[i];
         __syncthreads();
     }
-    const CD R0 = as_uniform(ra.R), C0 = as_uniform(ra.Cu);
-    for (int64_t row = (int64_t)wg * ROW_NT + tid; row < n; row += (int64_t)nwg * ROW_NT) {
+    const CD R0 = as_uniform(ra.Rpk), C0 = as_uniform(ra.Cu);
+    for (int64_t r0 = (int64_t)wg * ROW_NT; r0 < n; r0 += (int64_t)nwg * ROW_NT) {
+        const int64_t row = r0 + tid;
+        if (row >= n) continue;
         const CD Rs = per_strip(R0), Cs = per_strip(C0);
         // column offsets from leading dimensions re-derived per strip (held for the sweep,
         // 64 of them would not fit the SGPRs)
@@ -106,13 +123,17 @@ __device__ __forceinline__ void rowop_body(const RowopArgs& ra, const int wg, co
         const int w = per_strip(w0);
         double xa[1][WB];
         double(&x)[WB] = xa[0];
+        // Every slot loads, without a branch: slots past the width read the last live column
+        // again (same lines, no extra HBM traffic) and are never used.  A per-column branch
+        // around the load would hold the FP32-to-FP64 conversion, and with it a wait for
+        // that load, inside the branch, one column at a time.
 #pragma unroll
-        for (int c = 0; c < WB; ++c) x[c] = (c < w) ? ldv(Y + row + (int64_t)c * ldy) : 0.0;
+        for (int c = 0; c < WB; ++c) x[c] = ldv(lane_elem(Y + r0 + (int64_t)(c < w ? c : w - 1) * ldy, lane_bytes));
         if constexpr (UPD) update_rows<WB, 1, T>(xa, Qu + row, ldqu, pu, Cs, w);
         if constexpr (TRSM) solve_cols<WB, 0>(x, Rs, w, sD);
 #pragma unroll
         for (int c = 0; c < WB; ++c)
-            if (c < w) X[row + (int64_t)c * ldx] = static_cast<T>(x[c]);
+            if (c < w) *lane_elem(X + r0 + (int64_t)c * ldx, lane_bytes) = static_cast<T>(x[c]);
     }
 }
 
@@ -132,7 +153,7 @@ __global__ void __launch_bounds__(ROW_NT) wide_rowop_kernel_batched(const RowopA
     ra.Qu = batch_ptr(br, sys, d, t.Qu);
     ra.ldqu = batch_ld(br, d, t.ldqu);
     ra.Cu = batch_ptr(br, sys, d, t.Cu);
-    ra.R = batch_ptr(br, sys, d, t.R);
+    ra.Rpk = batch_ptr(br, sys, d, t.Rpk);
     ra.X = batch_ptr(br, sys, d, t.X);
     ra.ldx = batch_ld(br, d, t.ldx);
     rowop_body<WB, T, UPD, TRSM>(ra, blockIdx.x, gridDim.x);
@@ -304,11 +325,11 @@ void rowop_launch(const RowopArgs& ra, hipStream_t st, const BatchReloc* br) {
 
 template <int WB, typename T>
 hipError_t rowop_dispatch(const RowopArgs& ra, hipStream_t st, const BatchReloc* br) {
-    if (ra.pu > 0 && ra.R)
+    if (ra.pu > 0 && ra.Rpk)
         rowop_launch<WB, T, true, true>(ra, st, br);
     else if (ra.pu > 0)
         rowop_launch<WB, T, true, false>(ra, st, br);
-    else if (ra.R)
+    else if (ra.Rpk)
         rowop_launch<WB, T, false, true>(ra, st, br);
     else
         return hipErrorInvalidValue;
@@ -326,11 +347,11 @@ void gemm_launch(const GemmArgs& ga, int grid, hipStream_t st, const BatchReloc*
 }  // namespace
 
 hipError_t launch_wide_rowop(int64_t n, int W, bool f32, const void* Y, int64_t ldy, const void* Qu, int64_t ldqu,
-                             int pu, const double* Cu, const double* R, void* X, int64_t ldx, hipStream_t st,
+                             int pu, const double* Cu, const double* Rpk, void* X, int64_t ldx, hipStream_t st,
                              const BatchReloc* br) {
     if (W < 1 || W > 64 || n < 1) return hipErrorInvalidValue;
     if (br && br->nact < 1) return hipErrorInvalidValue;
-    const RowopArgs ra{n, W, Y, ldy, Qu, ldqu, pu, Cu, R, X, ldx};
+    const RowopArgs ra{n, W, Y, ldy, Qu, ldqu, pu, Cu, Rpk, X, ldx};
     if (W <= 16) return f32 ? rowop_dispatch<16, float>(ra, st, br) : rowop_dispatch<16, double>(ra, st, br);
     if (W <= 24) return f32 ? rowop_dispatch<24, float>(ra, st, br) : rowop_dispatch<24, double>(ra, st, br);
     if (W <= 32) return f32 ? rowop_dispatch<32, float>(ra, st, br) : rowop_dispatch<32, double>(ra, st, br);
