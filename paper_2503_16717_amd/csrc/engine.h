@@ -113,8 +113,7 @@ struct Engine {
         ra.count = rows_total * W;
         ra.scale = scale;
         ra.counter = counter;
-        ra.ticket0 = c->tickets;
-        c->tickets += (unsigned)reduce_grid(ra.count);
+        ra.ticket0 = take_tickets(c->tickets, ra.count, br);
         ra.rows = ra.count;
         ra.ldo = ra.count;
         ra.small = small;
@@ -143,8 +142,7 @@ struct Engine {
         ra.count = ma * nbc;
         ra.scale = 1.0;
         ra.counter = counter;
-        ra.ticket0 = c->tickets;
-        c->tickets += (unsigned)reduce_grid(ra.count);
+        ra.ticket0 = take_tickets(c->tickets, ra.count, br);
         ra.rows = ma;
         ra.ldo = ldo;
         ra.small = small;

@@ -543,8 +543,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
                 ra.count = 1;
                 ra.scale = 1.0;
                 ra.counter = e.counter;
-                ra.ticket0 = c->tickets;
-                c->tickets += (unsigned)reduce_grid(1);
+                ra.ticket0 = take_tickets(c->tickets, 1, nullptr);
                 ra.rows = 1;
                 ra.ldo = 1;
                 ra.small.op = OP_CHOL;
@@ -884,8 +883,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
             ra.count = 1;
             ra.scale = 1.0;
             ra.counter = e.counter;
-            ra.ticket0 = c->tickets;
-            c->tickets += (unsigned)reduce_grid(1);
+            ra.ticket0 = take_tickets(c->tickets, 1, &br);
             ra.rows = 1;
             ra.ldo = 1;
             ra.small.op = OP_CHOL;

@@ -162,6 +162,10 @@ constexpr int kGemmUnitRows = 64;
 // Number of workgroups launch_reduce uses for `count` reduced values.
 int reduce_grid(int count);
 
+// Ticket0 for a reduction launch over `count` values: the host's running count of arrivals
+// on the counter, advanced by the launch's workgroups when they take tickets (single-system
+// launches; batched launches run their small steps in a launch of their own, without one).
+unsigned take_tickets(unsigned& tickets, int count, const BatchReloc* br);
 hipError_t launch_reduce(const ReduceArgs& args, hipStream_t stream, const BatchReloc* br = nullptr);
 
 // Small dense kernels used outside a reduction.

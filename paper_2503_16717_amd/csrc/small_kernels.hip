@@ -24,6 +24,22 @@ __device__ __forceinline__ double load_coherent(const double* p) {
     return __longlong_as_double(static_cast<long long>(bits));
 }
 
+// put(i, src[i]) for i = tid, tid + RT, ... < count, with eight of each thread's loads in
+// flight before the first is used (a plain loop waits for every load before the next).
+// COHERENT: the source was written by other workgroups of this launch.
+template <bool COHERENT, typename Put>
+__device__ __forceinline__ void fill_from(const double* src, int count, Put&& put) {
+    int i = threadIdx.x;
+    for (; i + 7 * RT < count; i += 8 * RT) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = COHERENT ? load_coherent(src + i + u * RT) : src[i + u * RT];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) put(i + u * RT, t[u]);
+    }
+    for (; i < count; i += RT) put(i, COHERENT ? load_coherent(src + i) : src[i]);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -289,8 +305,8 @@ __device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* Y
     const int tid = threadIdx.x;
     const int k = s.k, w = s.w, na = s.nacc;
     const int ldy = k + 1;
-    for (int idx = tid; idx < k * w; idx += RT) Z[idx] = load_coherent(s.out + idx);
-    for (int idx = tid; idx < k * na; idx += RT) Ys[idx % k + (idx / k) * ldy] = s.Yacc[idx];
+    fill_from<true>(s.out, k * w, [&](int i, double v) { Z[i] = v; });
+    fill_from<false>(s.Yacc, k * na, [&](int i, double v) { Ys[i % k + (i / k) * ldy] = v; });
     __syncthreads();
     if (na > 0) {
         for (int pass = 0; pass < 2; ++pass) {
@@ -335,18 +351,26 @@ __device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* Y
     __syncthreads();
 }
 
-__device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
-    extern __shared__ double lds[];
+// Sums this workgroup's EPW reduced values over the G partials and stores them (scaled)
+// into small.out.  Only threads of wave 0 store.
+__device__ __forceinline__ void reduce_partials(const ReduceArgs& a) {
     __shared__ double part[RT];
-    __shared__ double red[4 * 16];
-    __shared__ double scal[128];
-    __shared__ int s_last;
     const int tid = threadIdx.x;
     const int el = tid % EPW, pt = tid / EPW;
     const int e = blockIdx.x * EPW + el;
     double v = 0.0;
     if (e < a.count) {
-        for (int g = pt; g < a.G; g += PARTS) v += a.partials[(int64_t)g * a.stride + e];
+        // partial g's of this thread in ascending order; eight loads in flight at a time
+        const double* p = a.partials + e;
+        int g = pt;
+        for (; g + 7 * PARTS < a.G; g += 8 * PARTS) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = p[(int64_t)(g + u * PARTS) * a.stride];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v += t[u];
+        }
+        for (; g < a.G; g += PARTS) v += p[(int64_t)g * a.stride];
     }
     part[tid] = v;
     __syncthreads();
@@ -358,20 +382,17 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
             a.small.out[(ee % a.rows) + (int64_t)(ee / a.rows) * a.ldo] = s * a.scale;
         }
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned prev = atomicAdd(a.counter, 1u);
-        s_last = (prev == a.ticket0 + gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+}
 
-    const SmallArgs& s = a.small;
+// The small dense step on the reduced values in s.out (one workgroup).
+__device__ __forceinline__ void small_step(const SmallArgs& s) {
+    extern __shared__ double lds[];
+    __shared__ double red[4 * 16];
+    __shared__ double scal[128];
+    const int tid = threadIdx.x;
     if (s.op == OP_HH) {
         double* A = lds;
-        for (int idx = tid; idx < s.k * s.w; idx += RT) A[idx] = load_coherent(s.out + idx);
+        fill_from<true>(s.out, s.k * s.w, [&](int i, double v) { A[i] = v; });
         __syncthreads();
         if (s.k <= 64) {
             if (tid < 64) householder_wave(A, s.k, s.w, nullptr, s.R, s.w, s.status, s.col0, scal);
@@ -381,7 +402,7 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
         }
     } else if (s.op == OP_CHOL) {
         double* G = lds;
-        for (int idx = tid; idx < s.w * s.w; idx += RT) G[idx] = load_coherent(s.out + idx);
+        fill_from<true>(s.out, s.w * s.w, [&](int i, double v) { G[i] = v; });
         __syncthreads();
         if (tid < 64) cholesky_wave(G, s.w, s.R, s.Rpk, s.status, s.col0, scal);
         __syncthreads();
@@ -397,9 +418,31 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
     }
 }
 
+// Reduction and small step in one launch: the last workgroup to arrive runs the step.
+// Only wave 0 stored sums, so it alone makes them visible device-wide before taking its
+// ticket (a device-scope release writes back the L2 once per wave that executes it).
+__device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
+    __shared__ int s_last;
+    const int tid = threadIdx.x;
+    reduce_partials(a);
+    if (tid < 64) __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned prev = atomicAdd(a.counter, 1u);
+        s_last = (prev == a.ticket0 + gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    small_step(a.small);
+}
+
 __global__ void __launch_bounds__(RT) reduce_kernel(const ReduceArgs a) { reduce_body(a); }
 
-// Batched form: the template arguments are moved to the system of blockIdx.y.
+// Batched form, in two launches: the reductions of every active system (blockIdx.y), with
+// no device-scope fence or ticket per workgroup (thousands of workgroups per launch), then
+// one workgroup per system for the small step, ordered after them by the launch boundary.
+// The template arguments are moved to the system of blockIdx.y.
 __global__ void __launch_bounds__(RT) reduce_kernel_batched(const ReduceArgs t, const BatchReloc br) {
     const int sys = batch_system(br);
     const BatchSys& d = br.sys[sys];
@@ -409,21 +452,27 @@ __global__ void __launch_bounds__(RT) reduce_kernel_batched(const ReduceArgs t, 
         if (units < a.G) a.G = (int)units;
     }
     a.partials = batch_ptr(br, sys, d, t.partials);
-    a.counter = batch_ptr(br, sys, d, t.counter);
-    SmallArgs& m = a.small;
-    m.out = batch_ptr(br, sys, d, t.small.out);
-    m.R = batch_ptr(br, sys, d, t.small.R);
-    m.Rpk = batch_ptr(br, sys, d, t.small.Rpk);
-    m.status = batch_ptr(br, sys, d, t.small.status);
-    m.Yacc = batch_ptr(br, sys, d, t.small.Yacc);
-    m.r = batch_ptr(br, sys, d, t.small.r);
-    m.Rbar = batch_ptr(br, sys, d, t.small.Rbar);
-    m.Ra = batch_ptr(br, sys, d, t.small.Ra);
-    m.Rb = batch_ptr(br, sys, d, t.small.Rb);
-    m.C1 = batch_ptr(br, sys, d, t.small.C1);
-    m.C2 = batch_ptr(br, sys, d, t.small.C2);
-    m.Rout = batch_ptr(br, sys, d, t.small.Rout);
-    reduce_body(a);
+    a.small.out = batch_ptr(br, sys, d, t.small.out);
+    reduce_partials(a);
+}
+
+__global__ void __launch_bounds__(RT) small_step_kernel_batched(const SmallArgs t, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    SmallArgs m = t;
+    m.out = batch_ptr(br, sys, d, t.out);
+    m.R = batch_ptr(br, sys, d, t.R);
+    m.Rpk = batch_ptr(br, sys, d, t.Rpk);
+    m.status = batch_ptr(br, sys, d, t.status);
+    m.Yacc = batch_ptr(br, sys, d, t.Yacc);
+    m.r = batch_ptr(br, sys, d, t.r);
+    m.Rbar = batch_ptr(br, sys, d, t.Rbar);
+    m.Ra = batch_ptr(br, sys, d, t.Ra);
+    m.Rb = batch_ptr(br, sys, d, t.Rb);
+    m.C1 = batch_ptr(br, sys, d, t.C1);
+    m.C2 = batch_ptr(br, sys, d, t.C2);
+    m.Rout = batch_ptr(br, sys, d, t.Rout);
+    small_step(m);
 }
 
 __global__ void matmul_upper_kernel(int w, const double* A, const double* B, double* C) {
@@ -461,7 +510,7 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream, const BatchRel
     if (lds > 60 * 1024 && !raised) {
         if (hipFuncSetAttribute(reinterpret_cast<const void*>(reduce_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void*>(reduce_kernel_batched),
+            hipFuncSetAttribute(reinterpret_cast<const void*>(small_step_kernel_batched),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess)
             return hipErrorInvalidValue;
         raised = true;
@@ -469,11 +518,21 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream, const BatchRel
     const int grid = reduce_grid(a.count);
     if (br) {
         if (br->nact < 1) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(reduce_kernel_batched, dim3(grid, br->nact), dim3(RT), lds, stream, a, *br);
+        hipLaunchKernelGGL(reduce_kernel_batched, dim3(grid, br->nact), dim3(RT), 0, stream, a, *br);
+        if (s.op != OP_STORE) {
+            if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+            hipLaunchKernelGGL(small_step_kernel_batched, dim3(1, br->nact), dim3(RT), lds, stream, s, *br);
+        }
     } else {
         hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(RT), lds, stream, a);
     }
     return hipGetLastError();
+}
+
+unsigned take_tickets(unsigned& tickets, int count, const BatchReloc* br) {
+    const unsigned t0 = tickets;
+    if (!br) tickets += (unsigned)reduce_grid(count);
+    return t0;
 }
 
 hipError_t launch_small_matmul_upper(int w, const double* A, const double* B, double* C, hipStream_t stream) {
