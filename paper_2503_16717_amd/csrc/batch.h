@@ -49,6 +49,12 @@ struct BatchReloc {
     int64_t part_bytes;
     const char* cnt0;        // template reduction counters
     int64_t cnt_bytes;
+    // Flat launches (one workgroup per `chunk` rows of a system, no idle workgroups): the
+    // first workgroup of active slot j is blk0[j] (nact + 1 entries, device; blk0[nact] ==
+    // nblk, the launch's grid).  Null: none set up.
+    const int* blk0;
+    int nblk;
+    int chunk;
 };
 
 #ifdef __HIPCC__
@@ -73,6 +79,21 @@ __device__ __forceinline__ P* batch_ptr(const BatchReloc& br, int sys, const Bat
     o = c - br.cnt0;
     if (o >= 0 && o < br.cnt_bytes) return reinterpret_cast<P*>(const_cast<char*>(c) + (int64_t)sys * br.cnt_bytes);
     return p;
+}
+
+// Active slot of this workgroup in a flat launch: the j with blk0[j] <= blockIdx.x <
+// blk0[j + 1] (every active system has at least one workgroup).
+__device__ __forceinline__ int flat_slot(const BatchReloc& br) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = br.nact;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (br.blk0[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
 }
 
 // A tall leading dimension of the template becomes the system's.

@@ -696,22 +696,26 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     const size_t o_part = ar.reserve(part_bytes * nsys);
     const size_t o_tbl = ar.reserve(sizeof(BatchSys) * nsys);
     const size_t o_act = ar.reserve(sizeof(int) * nsys);
+    const size_t o_blk = ar.reserve(sizeof(int) * (nsys + 1));
     sko_status s = ensure_workspace(c, ar.used());
     if (s) return s;
     const size_t pin_tbl = 0, pin_act = sizeof(BatchSys) * nsys, pin_dbl = pin_act + ((sizeof(int) * nsys + 63) / 64) * 64,
-                 pin_int = pin_dbl + sizeof(double) * nsys, pin_end = pin_int + sizeof(int) * nsys + 64;
+                 pin_int = pin_dbl + sizeof(double) * nsys, pin_blk = pin_int + ((sizeof(int) * nsys + 63) / 64) * 64,
+                 pin_end = pin_blk + sizeof(int) * (nsys + 1) + 64;
     if ((s = ensure_pinned(c, pin_end))) return s;
     char* pin = static_cast<char*>(c->pinned);
     BatchSys* tbl_h = reinterpret_cast<BatchSys*>(pin + pin_tbl);
     int* act_h = reinterpret_cast<int*>(pin + pin_act);
     double* dbl_h = reinterpret_cast<double*>(pin + pin_dbl);
     int* int_h = reinterpret_cast<int*>(pin + pin_int);
+    int* blk_h = reinterpret_cast<int*>(pin + pin_blk);
     g.host = dbl_h;
 
     char* small0 = ar.at<char>(o_small);
     double* part0 = ar.at<double>(o_part);
     BatchSys* tbl_d = ar.at<BatchSys>(o_tbl);
     int* act_d = ar.at<int>(o_act);
+    int* blk_d = ar.at<int>(o_blk);
     auto small_of = [&](int i) { return small0 + (size_t)i * L.bytes; };
     auto part_of = [&](int i) { return reinterpret_cast<double*>(reinterpret_cast<char*>(part0) + (size_t)i * part_bytes); };
 
@@ -826,6 +830,8 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     br.part_bytes = (int64_t)part_bytes;
     br.cnt0 = nullptr;
     br.cnt_bytes = 0;
+    br.blk0 = blk_d;
+    const int flat_unit = spmv_flat_unit(g.f32, g.avg_nnz);
     g.br = &br;
 
     Engine e(c, max_n, g.W, g.f32, g.sk);
@@ -853,11 +859,21 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
             nr += (double)A[list[j]].n;
             nz += (double)A[list[j]].nnz;
         }
+        // flat SpMV: about 16 workgroups per CU over the active rows, each 1 to 8 iterations
+        // (fewer rows per workgroup once only a few large systems are left)
+        const int64_t want = (int64_t)std::max(1, c->cus) * 16;
+        const int64_t iters = std::min<int64_t>(8, std::max<int64_t>(1, ((int64_t)nr / want + flat_unit - 1) / flat_unit));
+        br.chunk = (int)(iters * flat_unit);
+        blk_h[0] = 0;
+        for (size_t j = 0; j < list.size(); ++j)
+            blk_h[j + 1] = blk_h[j] + (int)((A[list[j]].n + br.chunk - 1) / br.chunk);
         br.nact = (int)list.size();
+        br.nblk = blk_h[list.size()];
         e.rows_bytes = e1f.rows_bytes = g.rows_bytes = nr;
         g.nnz_bytes = nz;
         if (list.empty()) return SKO_OK;
         SKO_HIP(hipMemcpyAsync(act_d, act_h, sizeof(int) * list.size(), hipMemcpyHostToDevice, g.st));
+        SKO_HIP(hipMemcpyAsync(blk_d, blk_h, sizeof(int) * (list.size() + 1), hipMemcpyHostToDevice, g.st));
         SKO_HIP(hipMemset2DAsync(small0 + st_off + 16 * sizeof(int), L.bytes, 0, sizeof(unsigned), nsys, g.st));
         SKO_HIP(hipStreamSynchronize(g.st));
         c->tickets = 0;

@@ -71,6 +71,9 @@ hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st, const BatchRelo
 
 // Batched forms (batch.h): one launch for every active system; x, y, r and Q are template
 // basis addresses, partials and y template workspace addresses.
+// Rows one workgroup iteration of the batched SpMV covers for this value type and mean row
+// length; the flat launch's BatchReloc::chunk is a multiple of it.
+int spmv_flat_unit(bool f32, double avg_nnz);
 hipError_t launch_spmv_batched(bool f32, double avg_nnz, int64_t max_n, const void* x, void* y, int grid_cap,
                                hipStream_t st, const BatchReloc& br);
 hipError_t launch_residual_batched(bool f32, double avg_nnz, void* r, double* partials, int grid, hipStream_t st,

@@ -27,15 +27,15 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// y = A x with L lanes per row (grid-stride over groups of NT/L rows).
+// y = A x with L lanes per row, workgroup wg of nwg striding over groups of NT/L rows.
 template <int L, typename TV, typename TX, typename TY>
-__global__ void __launch_bounds__(NT) spmv_kernel(int64_t n, const int32_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ colind, const TV* __restrict__ val,
-                                                  const TX* __restrict__ x, TY* __restrict__ y) {
+__device__ __forceinline__ void spmv_rows(int64_t n, const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ colind, const TV* __restrict__ val,
+                                          const TX* __restrict__ x, TY* __restrict__ y, int wg, int nwg) {
     const int tid = threadIdx.x;
     const int sub = tid % L;
     const int64_t rows_per_block = NT / L;
-    for (int64_t base = (int64_t)blockIdx.x * rows_per_block; base < n; base += (int64_t)gridDim.x * rows_per_block) {
+    for (int64_t base = (int64_t)wg * rows_per_block; base < n; base += (int64_t)nwg * rows_per_block) {
         const int64_t row = base + tid / L;
         double sum = 0.0;
         if (row < n) {
@@ -48,6 +48,13 @@ __global__ void __launch_bounds__(NT) spmv_kernel(int64_t n, const int32_t* __re
     }
 }
 
+template <int L, typename TV, typename TX, typename TY>
+__global__ void __launch_bounds__(NT) spmv_kernel(int64_t n, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colind, const TV* __restrict__ val,
+                                                  const TX* __restrict__ x, TY* __restrict__ y) {
+    spmv_rows<L, TV, TX, TY>(n, rowptr, colind, val, x, y, blockIdx.x, gridDim.x);
+}
+
 // One row per thread; each workgroup first copies the contiguous nonzero range of its NT
 // rows into LDS with coalesced loads (when it holds at most 8 entries per row on average,
 // else the rows read the arrays directly), so the per-row loops touch only LDS and x.
@@ -56,11 +63,11 @@ constexpr int STAGE = 8 * NT;
 template <typename TV, typename TX, typename TY>
 __device__ __forceinline__ void spmv_staged_body(int64_t n, const int32_t* __restrict__ rowptr,
                                                  const int32_t* __restrict__ colind, const TV* __restrict__ val,
-                                                 const TX* __restrict__ x, TY* __restrict__ y) {
+                                                 const TX* __restrict__ x, TY* __restrict__ y, int wg, int nwg) {
     __shared__ TV sv[STAGE];
     __shared__ int32_t sc[STAGE];
     const int tid = threadIdx.x;
-    for (int64_t base = (int64_t)blockIdx.x * NT; base < n; base += (int64_t)gridDim.x * NT) {
+    for (int64_t base = (int64_t)wg * NT; base < n; base += (int64_t)nwg * NT) {
         const int64_t rend = base + NT < n ? base + NT : n;
         const int32_t e0 = rowptr[base], cnt = rowptr[rend] - e0;
         const bool staged = cnt <= STAGE;
@@ -89,7 +96,7 @@ __global__ void __launch_bounds__(NT) spmv_staged_kernel(int64_t n, const int32_
                                                          const int32_t* __restrict__ colind,
                                                          const TV* __restrict__ val, const TX* __restrict__ x,
                                                          TY* __restrict__ y) {
-    spmv_staged_body<TV, TX, TY>(n, rowptr, colind, val, x, y);
+    spmv_staged_body<TV, TX, TY>(n, rowptr, colind, val, x, y, blockIdx.x, gridDim.x);
 }
 
 template <typename TV, typename TX, typename TY>
@@ -97,7 +104,43 @@ __global__ void __launch_bounds__(NT) spmv_staged_kernel_batched(const TX* x0, T
     const int sys = batch_system(br);
     const BatchSys& d = br.sys[sys];
     spmv_staged_body<TV, TX, TY>(d.n, d.rowptr, d.colind, static_cast<const TV*>(d.val_op),
-                                 batch_ptr(br, sys, d, x0), batch_ptr(br, sys, d, y0));
+                                 batch_ptr(br, sys, d, x0), batch_ptr(br, sys, d, y0), blockIdx.x, gridDim.x);
+}
+
+// Flat batched MPK step: workgroup b serves rows [r0, r0 + chunk) of the system of its
+// active slot; the row range is handed to the one-system bodies as a sub-matrix (row
+// pointers and y offset by r0; column indices and x stay absolute).
+template <typename TV, typename TX, typename TY>
+__device__ __forceinline__ void flat_range(const BatchReloc& br, const TX* x0, TY* y0, const BatchSys*& dp,
+                                           int64_t& r0, int64_t& nr, const TX*& x, TY*& y) {
+    const int slot = flat_slot(br);
+    const int sys = br.active[slot];
+    const BatchSys& d = br.sys[sys];
+    dp = &d;
+    r0 = (int64_t)(blockIdx.x - br.blk0[slot]) * br.chunk;
+    nr = d.n - r0 < br.chunk ? d.n - r0 : br.chunk;
+    x = batch_ptr(br, sys, d, x0);
+    y = batch_ptr(br, sys, d, y0) + r0;
+}
+
+template <int L, typename TV, typename TX, typename TY>
+__global__ void __launch_bounds__(NT) spmv_kernel_flat(const TX* x0, TY* y0, const BatchReloc br) {
+    const BatchSys* d;
+    int64_t r0, nr;
+    const TX* x;
+    TY* y;
+    flat_range<TV, TX, TY>(br, x0, y0, d, r0, nr, x, y);
+    spmv_rows<L, TV, TX, TY>(nr, d->rowptr + r0, d->colind, static_cast<const TV*>(d->val_op), x, y, 0, 1);
+}
+
+template <typename TV, typename TX, typename TY>
+__global__ void __launch_bounds__(NT) spmv_staged_kernel_flat(const TX* x0, TY* y0, const BatchReloc br) {
+    const BatchSys* d;
+    int64_t r0, nr;
+    const TX* x;
+    TY* y;
+    flat_range<TV, TX, TY>(br, x0, y0, d, r0, nr, x, y);
+    spmv_staged_body<TV, TX, TY>(nr, d->rowptr + r0, d->colind, static_cast<const TV*>(d->val_op), x, y, 0, 1);
 }
 
 // Batched MPK step: x and y are template basis columns.
@@ -256,22 +299,42 @@ __global__ void __launch_bounds__(NT) widen_kernel(int64_t n, const float* __res
 // Hessenberg bookkeeping (one workgroup).  Column-major (m+1) x m arrays Tin, Tout;
 // g (m+1); scratch H ((m+1) x m).
 // ---------------------------------------------------------------------------
+// Stored coefficient vector c of the replacement below: columns < row of T_in, then of
+// T_out, then g.
+__device__ __forceinline__ double* coef_vec(const GmSmallArgs& a, int row, int c) {
+    const int ld = a.m + 1;
+    if (c < row) return a.Tin + (int64_t)c * ld;
+    if (c < 2 * row) return a.Tout + (int64_t)(c - row) * ld;
+    return a.g;
+}
+
 __device__ void replace_row(const GmSmallArgs& a, int row, const double* sub) {
     // Old basis vector `row` = sum_{i <= row} sub[i] * new vector i: rewrite every stored
-    // coefficient vector (columns < row of T_in and T_out, and g).
-    const int ld = a.m + 1;
-    for (int c = threadIdx.x; c < 2 * row + 1; c += NT) {
-        double* col;
-        if (c < row)
-            col = a.Tin + (int64_t)c * ld;
-        else if (c < 2 * row)
-            col = a.Tout + (int64_t)(c - row) * ld;
-        else
-            col = a.g;
-        const double t = col[row];
-        if (t != 0.0) {
-            for (int i = 0; i < row; ++i) col[i] += t * sub[i];
-            col[row] = t * sub[row];
+    // coefficient vector (columns < row of T_in and T_out, and g).  Entry i of vector c
+    // becomes col[i] + t sub[i] (i < row) or t sub[row] (i == row), t = col[row]; the
+    // entries are spread over the threads, eight loads in flight per thread.
+    __shared__ double tv[2 * 256 + 1];
+    const int ncol = 2 * row + 1, len = row + 1, total = ncol * len;
+    for (int c = threadIdx.x; c < ncol; c += NT) tv[c] = coef_vec(a, row, c)[row];
+    __syncthreads();
+    for (int b = threadIdx.x; b < total; b += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = b + u * NT;
+            if (idx < total) {
+                const int c = idx / len, i = idx - c * len;
+                v[u] = coef_vec(a, row, c)[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = b + u * NT;
+            if (idx < total) {
+                const int c = idx / len, i = idx - c * len;
+                const double t = tv[c];
+                if (t != 0.0) coef_vec(a, row, c)[i] = (i < row) ? v[u] + t * sub[i] : t * sub[row];
+            }
         }
     }
     __syncthreads();
@@ -347,16 +410,34 @@ __device__ void lsq_lds(const GmSmallArgs& a, int k, double* lds) {
     double* Ts = lds + (int64_t)lh * k;
     double* gs = Ts + (int64_t)lh * k;
     __shared__ double cs[2];
-    for (int idx = threadIdx.x; idx < lh * k; idx += NT) {
-        const int r = idx % lh, c = idx / lh;
-        Ts[idx] = a.Tin[r + (int64_t)c * ld];
+    // T_in into Ts and T_out into Hs (each row of H then overwrites its own T_out row),
+    // eight loads of each in flight per thread
+    for (int b = threadIdx.x; b < lh * k; b += 8 * NT) {
+        double ti[8], to[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = b + u * NT;
+            if (idx < lh * k) {
+                const int r = idx % lh, c = idx / lh;
+                ti[u] = a.Tin[r + (int64_t)c * ld];
+                to[u] = a.Tout[r + (int64_t)c * ld];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = b + u * NT;
+            if (idx < lh * k) {
+                Ts[idx] = ti[u];
+                Hs[idx] = to[u];
+            }
+        }
     }
     for (int i = threadIdx.x; i <= k; i += NT) gs[i] = a.g[i];
     __syncthreads();
     // H[r, c] = (T_out[r, c] - sum_{q<c} H[r, q] T_in[q, c]) / T_in[c, c]
     for (int r = threadIdx.x; r <= k; r += NT) {
         for (int c = 0; c < k; ++c) {
-            double v = a.Tout[r + (int64_t)c * ld];
+            double v = Hs[r + c * lh];
             for (int q = 0; q < c; ++q) v -= Hs[r + q * lh] * Ts[q + c * lh];
             Hs[r + c * lh] = v / Ts[c + c * lh];
         }
@@ -648,10 +729,38 @@ hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st, const BatchRelo
     return hipGetLastError();
 }
 
+int spmv_flat_unit(bool f32, double avg_nnz) {
+    const SpmvKind k = f32 ? spmv_kind<float>(avg_nnz) : spmv_kind<double>(avg_nnz);
+    return spmv_rows_per_block(k);
+}
+
+template <typename TV, typename TX, typename TY>
+void spmv_flat_launch(SpmvKind k, const TX* x, TY* y, hipStream_t st, const BatchReloc& br) {
+    const dim3 g(br.nblk);
+    switch (k) {
+        case SPMV_L8: hipLaunchKernelGGL((spmv_kernel_flat<8, TV, TX, TY>), g, dim3(NT), 0, st, x, y, br); break;
+        case SPMV_L4: hipLaunchKernelGGL((spmv_kernel_flat<4, TV, TX, TY>), g, dim3(NT), 0, st, x, y, br); break;
+        case SPMV_L2: hipLaunchKernelGGL((spmv_kernel_flat<2, TV, TX, TY>), g, dim3(NT), 0, st, x, y, br); break;
+        case SPMV_STAGED:
+            hipLaunchKernelGGL((spmv_staged_kernel_flat<TV, TX, TY>), g, dim3(NT), 0, st, x, y, br);
+            break;
+    }
+}
+
 hipError_t launch_spmv_batched(bool f32, double avg_nnz, int64_t max_n, const void* x, void* y, int grid_cap,
                                hipStream_t st, const BatchReloc& br) {
     if (br.nact < 1) return hipErrorInvalidValue;
     const SpmvKind k = f32 ? spmv_kind<float>(avg_nnz) : spmv_kind<double>(avg_nnz);
+    if (br.blk0) {
+        if (br.nblk < br.nact || br.chunk < 1 || br.chunk % spmv_flat_unit(f32, avg_nnz) != 0)
+            return hipErrorInvalidValue;
+        if (f32)
+            spmv_flat_launch<float, float, float>(k, static_cast<const float*>(x), static_cast<float*>(y), st, br);
+        else
+            spmv_flat_launch<double, double, double>(k, static_cast<const double*>(x), static_cast<double*>(y), st,
+                                                     br);
+        return hipGetLastError();
+    }
     const int rpb = spmv_rows_per_block(k);
     const int64_t groups = (max_n + rpb - 1) / rpb;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, grid_cap));
