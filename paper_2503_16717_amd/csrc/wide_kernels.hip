@@ -202,6 +202,56 @@ __device__ __forceinline__ void load_piece(const T* col, bool live, bool vec, in
     }
 }
 
+// The four pieces (16-column tiles t) of one operand for a group of 16 rows.  In a full
+// group every lane loads every piece without a branch: a column past m reads column m - 1
+// (lines already requested) and is zeroed after the loads, so all loads of the group are in
+// flight together.  A branch per piece would wait for each load in turn.  The group at the
+// end of the rows keeps the guarded loads.
+template <typename T>
+__device__ __forceinline__ void load_pieces(const T* base, int64_t ld, int m, int ci, bool vec, bool full,
+                                            int64_t row0, int64_t n, double (&v)[4][4]) {
+    if (full && vec) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int c = 16 * t + ci;
+            const T* col = base + (int64_t)(c < m ? c : m - 1) * ld;
+            if constexpr (sizeof(T) == 8) {
+                const double2 p0 = *reinterpret_cast<const double2*>(col + row0);
+                const double2 p1 = *reinterpret_cast<const double2*>(col + row0 + 2);
+                v[t][0] = p0.x;
+                v[t][1] = p0.y;
+                v[t][2] = p1.x;
+                v[t][3] = p1.y;
+            } else {
+                const float4 p = *reinterpret_cast<const float4*>(col + row0);
+                v[t][0] = p.x;
+                v[t][1] = p.y;
+                v[t][2] = p.z;
+                v[t][3] = p.w;
+            }
+        }
+    } else if (full) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int c = 16 * t + ci;
+            const T* col = base + (int64_t)(c < m ? c : m - 1) * ld;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[t][u] = ldv(col + row0 + u);
+        }
+    } else {
+        const int tiles = (m + 15) / 16;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int c = 16 * t + ci;
+            if (t < tiles) load_piece(base + (int64_t)(c < m ? c : 0) * ld, c < m, vec, row0, n, v[t]);
+        }
+        return;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        if (16 * t + ci >= m) v[t][0] = v[t][1] = v[t][2] = v[t][3] = 0.0;
+}
+
 template <typename T, bool SYM>
 __device__ __forceinline__ void gemm_body(const GemmArgs& ga) {
     __shared__ double red[4 * 64 * (GT / 64)];
@@ -225,19 +275,10 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& ga) {
     const int64_t ngroups = (n + 15) / 16;
     for (int64_t grp = (int64_t)blockIdx.x * NW + wave; grp < ngroups; grp += (int64_t)gridDim.x * NW) {
         const int64_t row0 = grp * 16 + 4 * g;
+        const bool full = grp * 16 + 16 <= n;
         double a[4][4], b[SYM ? 1 : 4][4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int c = 16 * t + ci;
-            if (t < ta) load_piece(A + (int64_t)(c < ma ? c : 0) * ga.lda, c < ma, veca, row0, n, a[t]);
-        }
-        if constexpr (!SYM) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int c = 16 * t + ci;
-                if (t < tb) load_piece(B + (int64_t)(c < nb ? c : 0) * ga.ldb, c < nb, vecb, row0, n, b[t]);
-            }
-        }
+        load_pieces(A, ga.lda, ma, ci, veca, full, row0, n, a);
+        if constexpr (!SYM) load_pieces(B, ga.ldb, nb, ci, vecb, full, row0, n, b);
         // row step outermost: consecutive MFMAs go to different accumulator tiles
 #pragma unroll
         for (int u = 0; u < 4; ++u)
