@@ -123,3 +123,34 @@ def test_two_stage_many_big_panels(B, ctx):
     assert metrics.rel_diff(R, ref.R) <= max(tol_r(e), 10.0 * kappa * U)
     assert metrics.orth_error(Q)[0] <= 1e-13
     assert metrics.backward_error(V, Q, R) <= 1e-14
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("n", [4099, 20000])
+def test_two_stage_widest_big_panels(B, ctx, mixed, n):
+    """Two big panels of 55 columns (5 blocks of 11): the row solve runs its 64-column form
+    with 9 slots past the width, the packed triangular factor spans 55 columns, and the
+    second big panel is projected on the first (55 coefficients per column).  n = 4099
+    leaves a ragged last 16-row group in the wide Gram and projection and a partial last
+    strip in the row solve.  FP32 storage is compared with the oracle on the float-rounded
+    input to single-precision tolerances."""
+    w, nb, ppb, e = 11, 10, 5, 4
+    V = wl.glued_blocks(n, nb, w, e)
+    kw = {}
+    dtype = torch.float64
+    if mixed:
+        V = V.astype(np.float32).astype(np.float64)
+        kw["precision"] = "mixed"
+        dtype = torch.float32
+    Q, R, st, col = run(B, ctx, V, w, ppb, k=128, dtype=dtype, **kw)
+    assert st == B.SKO_OK, (st, col)
+    ref = orth.orth_blocks_two_stage(V, w, ppb, Sketch.sparse_sign(128, 8, 0))
+    assert ref.info == 0
+    if mixed:
+        assert metrics.orth_error(Q)[0] <= 1e-5
+        assert metrics.backward_error(V, Q, R) <= 1e-6
+        assert metrics.rel_diff(R, ref.R) <= 1e-5
+    else:
+        assert metrics.rel_diff(R, ref.R) <= tol_r(e)
+        assert metrics.orth_error(Q)[0] <= 1e-13
+        assert metrics.backward_error(V, Q, R) <= 1e-14
