@@ -164,9 +164,11 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// householder_lds for k <= 64, run by one wave (one row per lane): the column norms and
-// reflector products are shuffle reductions, and no step waits for the other waves.  The
-// caller synchronises the workgroup afterwards.
+// householder_lds for k <= 64 RPL, run by one wave (rows lane, lane + 64, ... of each
+// lane): the column norms and reflector products are per-lane partial sums then shuffle
+// reductions, and no step waits for the other waves.  The caller synchronises the
+// workgroup afterwards.
+template <int RPL>
 __device__ void householder_wave(double* A, int k, int w, double* E, double* R, int ldr, int* status, int col0,
                                  double* scal) {
     const int lane = threadIdx.x & 63;
@@ -174,8 +176,15 @@ __device__ void householder_wave(double* A, int k, int w, double* E, double* R, 
     double* beta = scal + 16;  // w
     double* sgn = scal + 48;   // w
     for (int j = 0; j < w; ++j) {
-        const double aj = (lane > j && lane < k) ? A[lane + j * k] : 0.0;
-        const double ss = wave_sum(aj * aj);
+        double aj[RPL], vi[RPL];
+        double sl = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            aj[r] = (i > j && i < k) ? A[i + j * k] : 0.0;
+            sl += aj[r] * aj[r];
+        }
+        const double ss = wave_sum(sl);
         const double x0 = A[j + j * k];
         const double normx = sqrt(x0 * x0 + ss);
         double alpha = 0.0, b = 0.0, v0 = 0.0;
@@ -184,11 +193,23 @@ __device__ void householder_wave(double* A, int k, int w, double* E, double* R, 
             v0 = x0 - alpha;
             b = 2.0 / (v0 * v0 + ss);
         }
-        const double vi = (lane == j) ? v0 : aj;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) vi[r] = (lane + 64 * r == j) ? v0 : aj[r];
         for (int c = j + 1; c < w; ++c) {
-            const double ac = lane < k ? A[lane + c * k] : 0.0;
-            const double d = wave_sum(vi * ac);
-            if (lane >= j && lane < k) A[lane + c * k] = ac - b * d * vi;
+            double ac[RPL];
+            double dl = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                ac[r] = i < k ? A[i + c * k] : 0.0;
+                dl += vi[r] * ac[r];
+            }
+            const double d = wave_sum(dl);
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                if (i >= j && i < k) A[i + c * k] = ac[r] - b * d * vi[r];
+            }
         }
         wave_sync();
         if (lane == 0) {
@@ -217,16 +238,46 @@ __device__ void householder_wave(double* A, int k, int w, double* E, double* R, 
     wave_sync();
     for (int j = w - 1; j >= 0; --j) {
         const double v0 = vhead[j], b = beta[j];
-        const double vi = (lane == j) ? v0 : ((lane > j && lane < k) ? A[lane + j * k] : 0.0);
+        double vi[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            vi[r] = (i == j) ? v0 : ((i > j && i < k) ? A[i + j * k] : 0.0);
+        }
         for (int c = 0; c < w; ++c) {
-            const double ec = lane < k ? E[lane + c * k] : 0.0;
-            const double d = wave_sum(vi * ec);
-            if (lane >= j && lane < k) E[lane + c * k] = ec - b * d * vi;
+            double ec[RPL];
+            double dl = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                ec[r] = i < k ? E[i + c * k] : 0.0;
+                dl += vi[r] * ec[r];
+            }
+            const double d = wave_sum(dl);
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                if (i >= j && i < k) E[i + c * k] = ec[r] - b * d * vi[r];
+            }
         }
         wave_sync();
     }
     for (int idx = lane; idx < k * w; idx += 64) E[idx] *= sgn[idx / k];
     wave_sync();
+}
+
+// Householder QR of the k x w matrix A in LDS by one wave (k <= 128) or the workgroup.
+__device__ __forceinline__ void householder(double* A, int k, int w, double* E, double* R, int ldr, int* status,
+                                            int col0, double* red, double* scal) {
+    if (k <= 64) {
+        if (threadIdx.x < 64) householder_wave<1>(A, k, w, E, R, ldr, status, col0, scal);
+        __syncthreads();
+    } else if (k <= 128) {
+        if (threadIdx.x < 64) householder_wave<2>(A, k, w, E, R, ldr, status, col0, scal);
+        __syncthreads();
+    } else {
+        householder_lds(A, k, w, E, R, ldr, status, col0, red, scal);
+    }
 }
 
 // Right-looking upper Cholesky of the w x w matrix G (LDS, column-major), w <= 64, run by
@@ -328,12 +379,7 @@ __device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* Y
             __syncthreads();
         }
     }
-    if (k <= 64) {
-        if (tid < 64) householder_wave(Z, k, w, E, s.R, w, s.status, s.col0, scal);
-        __syncthreads();
-    } else {
-        householder_lds(Z, k, w, E, s.R, w, s.status, s.col0, red, scal);
-    }
+    householder(Z, k, w, E, s.R, w, s.status, s.col0, red, scal);
     // append q to the accumulated sketches (replacing the boundary column at nacc)
     for (int idx = tid; idx < k * w; idx += RT) s.Yacc[(int64_t)na * k + idx] = E[idx];
     if (s.Rbar) {
@@ -394,12 +440,7 @@ __device__ __forceinline__ void small_step(const SmallArgs& s) {
         double* A = lds;
         fill_from<true>(s.out, s.k * s.w, [&](int i, double v) { A[i] = v; });
         __syncthreads();
-        if (s.k <= 64) {
-            if (tid < 64) householder_wave(A, s.k, s.w, nullptr, s.R, s.w, s.status, s.col0, scal);
-            __syncthreads();
-        } else {
-            householder_lds(A, s.k, s.w, nullptr, s.R, s.w, s.status, s.col0, red, scal);
-        }
+        householder(A, s.k, s.w, nullptr, s.R, s.w, s.status, s.col0, red, scal);
     } else if (s.op == OP_CHOL) {
         double* G = lds;
         fill_from<true>(s.out, s.w * s.w, [&](int i, double v) { G[i] = v; });
