@@ -10,6 +10,7 @@
 
 #include "batch.h"
 #include "gmres_internal.h"
+#include "uniform.h"
 
 namespace sko {
 namespace {
@@ -525,36 +526,81 @@ __device__ __forceinline__ void gm_small_body(const GmSmallArgs& a) {
         // rows k0..k0+W-1 of every stored vector refer to the pre-processed big panel:
         // t[:k0] += C2 Rh t[k0:], t[k0:] = Rt Rh t[k0:]  (Rt = I without the second pass)
         const int k0 = a.k0, W = a.Wb, kend = a.kend;
-        for (int c = threadIdx.x; c < 2 * kend + 1; c += NT) {
-            double* col;
-            if (c < kend)
-                col = a.Tin + (int64_t)c * ld;
-            else if (c < 2 * kend)
-                col = a.Tout + (int64_t)(c - kend) * ld;
-            else
-                col = a.g;
-            double u[64];
-            for (int i = 0; i < W; ++i) {
-                double v = 0.0;
-                for (int j = i; j < W; ++j) v += a.Rh[i + j * W] * col[k0 + j];
-                u[i] = v;
+        const int ncol = 2 * kend + 1;
+        if (lsq_lds_doubles(a.m) <= kLsqLdsMax) {
+            // Each thread's segment t[k0:k0+W] in LDS (X[j * ncol + c], (2 kend + 1) W <= the
+            // least squares' LDS), loaded eight at a time, then both triangular products in
+            // place (row i ascending reads only entries j >= i, which are still inputs); the
+            // sums run in the same order as the global-memory form below.
+            double* X = gm_dyn;
+            // the factors and C2 are read-only here: scalar loads, shared by the wave
+            const CD Rh = as_uniform(a.Rh), Rt = as_uniform(a.Rt), C2 = as_uniform(a.C2);
+            for (int c = threadIdx.x; c < ncol; c += NT) {
+                const double* col = coef_vec(a, kend, c);
+                for (int j0 = 0; j0 < W; j0 += 8) {
+                    double t[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (j0 + u < W) t[u] = col[k0 + j0 + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (j0 + u < W) X[(j0 + u) * ncol + c] = t[u];
+                }
+                // y = R x in place, column j of R at a time: entry i < j gains R[i, j] x[j],
+                // entry j starts as R[j, j] x[j] (x[j] read first), so each y[i] sums its
+                // terms in ascending j, as the row-wise form does
+                auto upper_times = [&](CD Rm) {
+                    for (int j = 0; j < W; ++j) {
+                        const double xj = X[j * ncol + c];
+                        const CD Rc = Rm + (int64_t)j * W;
+                        for (int i = 0; i < j; ++i) X[i * ncol + c] += Rc[i] * xj;
+                        X[j * ncol + c] = 0.0 + Rc[j] * xj;
+                    }
+                };
+                upper_times(Rh);
+                double* colw = coef_vec(a, kend, c);
+                if (a.C2) {
+                    for (int r = 0; r < k0; ++r) {
+                        double v = 0.0;
+                        for (int j = 0; j < W; ++j) v += C2[r + (int64_t)j * k0] * X[j * ncol + c];
+                        colw[r] += v;
+                    }
+                }
+                if (a.Rt) upper_times(Rt);
+                for (int i = 0; i < W; ++i) colw[k0 + i] = X[i * ncol + c];
             }
-            if (a.C2) {
-                for (int r = 0; r < k0; ++r) {
+        } else {
+            for (int c = threadIdx.x; c < 2 * kend + 1; c += NT) {
+                double* col;
+                if (c < kend)
+                    col = a.Tin + (int64_t)c * ld;
+                else if (c < 2 * kend)
+                    col = a.Tout + (int64_t)(c - kend) * ld;
+                else
+                    col = a.g;
+                double u[64];
+                for (int i = 0; i < W; ++i) {
                     double v = 0.0;
-                    for (int j = 0; j < W; ++j) v += a.C2[r + (int64_t)j * k0] * u[j];
-                    col[r] += v;
+                    for (int j = i; j < W; ++j) v += a.Rh[i + j * W] * col[k0 + j];
+                    u[i] = v;
                 }
-            }
-            for (int i = 0; i < W; ++i) {
-                double v;
-                if (a.Rt) {
-                    v = 0.0;
-                    for (int j = i; j < W; ++j) v += a.Rt[i + j * W] * u[j];
-                } else {
-                    v = u[i];
+                if (a.C2) {
+                    for (int r = 0; r < k0; ++r) {
+                        double v = 0.0;
+                        for (int j = 0; j < W; ++j) v += a.C2[r + (int64_t)j * k0] * u[j];
+                        col[r] += v;
+                    }
                 }
-                col[k0 + i] = v;
+                for (int i = 0; i < W; ++i) {
+                    double v;
+                    if (a.Rt) {
+                        v = 0.0;
+                        for (int j = i; j < W; ++j) v += a.Rt[i + j * W] * u[j];
+                    } else {
+                        v = u[i];
+                    }
+                    col[k0 + i] = v;
+                }
             }
         }
         __syncthreads();
@@ -719,6 +765,8 @@ hipError_t launch_scale_values(int64_t nnz, const int32_t* colind, const double*
 
 hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st, const BatchReloc* br) {
     if (a.m + 1 > 256 || a.Wb > 64) return hipErrorInvalidValue;
+    // the big-panel close stages (2 kend + 1) x Wb values in the least squares' LDS
+    if (a.op == GM_BIGCLOSE && (a.kend > a.m || a.k0 < 0 || a.k0 + a.Wb > a.m + 1)) return hipErrorInvalidValue;
     const size_t lds = lsq_lds_doubles(a.m) <= kLsqLdsMax ? sizeof(double) * lsq_lds_doubles(a.m) : 0;
     if (br) {
         if (br->nact < 1) return hipErrorInvalidValue;
