@@ -129,7 +129,7 @@ struct Engine {
     // handed to `small`.
     sko_status gemm_reduction(const void* A, int64_t lda, int ma, const void* B, int64_t ldb, int nbc,
                               SmallArgs small, int64_t ldo) {
-        const int G = gemm_grid();
+        const int G = gemm_grid(A == B && lda == ldb && ma == nbc);
         const int ev = c->prof.begin(std::string("wide_gemm_tn ") + (A == B ? "gram" : "proj") + " f" +
                                          (f32 ? "32" : "64"),
                                      rows_bytes * (A == B ? ma : ma + nbc) * (f32 ? 4.0 : 8.0), st);
@@ -175,10 +175,17 @@ struct Engine {
 
     // Workgroups of a wide Gram / projection launch (per system in batched mode, where a
     // launch already holds many systems).
-    int gemm_grid() const {
+    // One system: at most the resident workgroups, so no second, partly idle round of
+    // workgroups follows the first (each walks its 16-row groups).
+    int gemm_grid(bool sym) const {
         const int64_t ns32 = (n + 31) / 32;
         const int64_t want = br ? (ns32 + 63) / 64 : ns32;
-        return (int)std::max<int64_t>(1, std::min<int64_t>(want, skinny_gemm_grid_cap()));
+        int64_t cap = skinny_gemm_grid_cap();
+        if (!br) {
+            const int res = skinny_gemm_resident(sym, f32);
+            if (res > 0) cap = std::min<int64_t>(cap, res);
+        }
+        return (int)std::max<int64_t>(1, std::min<int64_t>(want, cap));
     }
 
     // Profiler name of a reduction launch: the partial sums and the small step that ends it.

@@ -401,6 +401,28 @@ hipError_t launch_wide_rowop(int64_t n, int W, bool f32, const void* Y, int64_t 
     return f32 ? rowop_dispatch<64, float>(ra, st, br) : rowop_dispatch<64, double>(ra, st, br);
 }
 
+template <typename T, bool SYM>
+int gemm_resident() {
+    static int cached = 0;
+    if (cached == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(&wide_gemm_tn_kernel<T, SYM>), GT, 0) == hipSuccess &&
+            per_cu > 0 && cus > 0)
+            cached = per_cu * cus;
+        else
+            cached = -1;
+    }
+    return cached;
+}
+
+int skinny_gemm_resident(bool sym, bool f32) {
+    if (f32) return sym ? gemm_resident<float, true>() : gemm_resident<float, false>();
+    return sym ? gemm_resident<double, true>() : gemm_resident<double, false>();
+}
+
 int skinny_gemm_grid_cap() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1;
