@@ -359,8 +359,9 @@ def main() -> int:
                           "copy_calibration_bytes_written_per_launch": a.numel() * 8, "launches": 5}))
         return 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; the path's multi-GPU sharding is "
-                                   "design-only (see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU: the library has no multi-GPU path (row "
+                                   "sharding with one all-reduce per reduction is a design, not code)",
+                          "n_gpus": args.gpus}))
         return 2
 
     import numpy as np
