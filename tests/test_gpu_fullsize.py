@@ -24,11 +24,16 @@ N_ROWS, NB, W, E = 1 << 24, 12, 6, 12.0
 
 
 @pytest.fixture(scope="module")
-def full():
+def full_input():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    return wl.glued_blocks(N_ROWS, NB, W, E, threads=min(12, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="module")
+def full(full_input):
     from paper_2503_16717_amd import binding as B
-    V = wl.glued_blocks(N_ROWS, NB, W, E, threads=min(12, os.cpu_count() or 1))
+    V = full_input
     Vd = B.colmajor_from_numpy(V, "cuda")
     ctx = B.Context(0)
     sk = B.make_sketch("sparse_sign", 64, 8, 0)
@@ -71,3 +76,39 @@ def test_fullsize_first_block_against_oracle(full):
     rd = metrics.rel_diff(R[:W, :W], ref.R)
     print(f"first block R rel diff {rd:.3e}")
     assert rd <= max(1e-12, 10 * 10.0 ** E * U)
+
+
+@pytest.fixture(scope="module")
+def full_two_stage(full_input):
+    """The same input through the two-stage scheme as the benchmark runs it: s_hat = 30, so
+    big panels of 6 blocks (36 columns), two big panels; twice."""
+    from paper_2503_16717_amd import binding as B
+    V = full_input
+    Vd = B.colmajor_from_numpy(V, "cuda")
+    ctx = B.Context(0)
+    sk = B.make_sketch("sparse_sign", 64, 8, 0)
+    outs = []
+    for _ in range(2):
+        Q, R, st, col = ctx.orth_blocks(Vd, W, two_stage=True, panels_per_big=6, sketch=sk)
+        torch.cuda.synchronize()
+        assert st == B.SKO_OK, (st, col)
+        outs.append((Q, R))
+    ctx.close()
+    return V, outs
+
+
+def test_fullsize_two_stage(full_two_stage):
+    """Bitwise repeatable, R upper triangular with a positive diagonal, and the properties that
+    hold at any size, measured by the oracle's compensated metrics."""
+    V, outs = full_two_stage
+    (Q0, R0), (Q, R) = outs
+    assert np.array_equal(R, R0)
+    assert torch.equal(Q, Q0)
+    assert np.allclose(np.tril(R, -1), 0.0, atol=0.0)
+    assert np.all(np.diag(R) > 0)
+    Qh = Q.cpu().numpy()
+    oe = metrics.orth_error(Qh)[0]
+    be = metrics.backward_error(V, Qh, R)
+    print(f"n=2^24 two-stage: ||I-Q^TQ||_2 = {oe:.3e}, backward error = {be:.3e}")
+    assert oe <= 1e-13
+    assert be <= 1e-14
