@@ -112,3 +112,38 @@ def test_fullsize_two_stage(full_two_stage):
     print(f"n=2^24 two-stage: ||I-Q^TQ||_2 = {oe:.3e}, backward error = {be:.3e}")
     assert oe <= 1e-13
     assert be <= 1e-14
+
+
+@pytest.fixture(scope="module")
+def full_mixed():
+    """The mixed-precision benchmark shape: n = 2^24, 12 blocks of 11 columns (kappa = 1e6 per
+    block) stored in FP32, one-stage RandCholQR-BCGS2 with the sparse-sign sketch."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_16717_amd import binding as B
+    w = 11
+    V = wl.glued_blocks(N_ROWS, NB, w, 6.0, threads=min(12, os.cpu_count() or 1))
+    V = V.astype(np.float32).astype(np.float64)
+    Vd = B.colmajor_from_numpy(V, "cuda", dtype=torch.float32)
+    ctx = B.Context(0)
+    Q, R, st, col = ctx.orth_blocks(Vd, w, precision="mixed", intra="randcholqr",
+                                    sketch=B.make_sketch("sparse_sign", 64, 8, 0))
+    torch.cuda.synchronize()
+    ctx.close()
+    assert st == B.SKO_OK, (st, col)
+    del Vd
+    return V, Q, R
+
+
+def test_fullsize_mixed_precision(full_mixed):
+    """Errors of the FP32-storage result, measured in FP64 against its own float-rounded input,
+    are of the order of single precision."""
+    V, Q, R = full_mixed
+    assert np.allclose(np.tril(R, -1), 0.0, atol=0.0)
+    assert np.all(np.diag(R) > 0)
+    Qh = Q.double().cpu().numpy()
+    oe = metrics.orth_error(Qh)[0]
+    be = metrics.backward_error(V, Qh, R)
+    print(f"n=2^24 FP32 storage: ||I-Q^TQ||_2 = {oe:.3e}, backward error = {be:.3e}")
+    assert oe <= 1e-6
+    assert be <= 1e-6
