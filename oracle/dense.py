@@ -98,14 +98,3 @@ def trsm_right_upper(V: np.ndarray, R: np.ndarray) -> np.ndarray:
         X[:, c] = acc / R[c, c]
     return X
 
-
-def solve_upper(R: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """Back substitution R y = b (R upper triangular, b a vector)."""
-    w = R.shape[0]
-    y = np.zeros(w)
-    for i in reversed(range(w)):
-        acc = b[i]
-        for j in range(i + 1, w):
-            acc -= R[i, j] * y[j]
-        y[i] = acc / R[i, i]
-    return y

@@ -138,25 +138,35 @@ def test_check_granularity_matches_time_to_solution_table():
 
 
 def test_mpk_laplacian_fig12():
-    """Fig. 12 (Section 9): monomial MPK basis of the 2-D Laplacian 128^2, v1 = b/||b||, b = A*1.
-    The paper reports CholQR2 failing at j = 11; under the unscaled-stencil reading used here the
-    equilibrated condition number only reaches 1e8 near j = 13 and the breakdown comes later
-    (j = 14..16 depending on rounding).  What is pinned is the reading-independent part: CholQR2
-    breaks down no earlier than the paper's j once the columns are that ill-conditioned, while
-    RandCholQR keeps O(eps) orthogonality throughout."""
-    j_paper = int(golden("mpk_laplace_cholqr2_fail_j"))
+    """Fig. 12 (Section 9): monomial MPK basis V_{1:j+1} of the 2-D Laplacian 128^2, v_1 = b/||b||,
+    b = A*1, v_{j+1} = A v_j.  What the prose fixes, independent of the unstated details: the
+    condition number grows quickly with j; CholQR2 keeps O(eps) orthogonality while the basis is
+    below eps^(-1/2) (Section 5.1) and breaks down once it is far beyond; RandCholQR keeps O(eps)
+    orthogonality as long as the basis is numerically full rank.
+
+    The printed breakdown index j = 11 is NOT reproduced (parity unpinned for that value).
+    Here CholQR2 first breaks down at j = 16, where the equilibrated condition number is about
+    2e10; at j = 11 it is 4.7e6 and CholQR2 is still at 6e-15.  Rescaling A does not move the
+    breakdown (it scales column j of V by c^j, a diagonal scaling), so the stencil scaling
+    cannot explain the difference."""
     A = wl.laplacian_2d(128)
     b = krylov.spmv(A, np.ones(A.n))
     V = krylov.mpk(A, None, b / np.linalg.norm(b), 17)
     th = Sketch.gaussian(wl.gaussian_theta(A.n, 40, 0))
     first_fail = None
+    prev = 1.0
     for j in range(2, 18):
         X = V[:, :j + 1]
-        _, _, info = orth.cholqr2(X)
+        keq = metrics.cond2(X / np.linalg.norm(X, axis=0))
+        assert keq > 2.0 * prev     # grows quickly (by more than 2x per added vector)
+        prev = keq
+        Qc, _, info = orth.cholqr2(X)
+        if keq < 1e7:               # below eps^(-1/2) ~ 6.7e7 with a margin
+            assert info == 0 and metrics.orth_error(Qc)[0] <= 1e-13
         if info and first_fail is None:
             first_fail = j
-            Xe = X / np.linalg.norm(X, axis=0)
-            assert metrics.cond2(Xe) >= 1e7
+        if keq > 1e11:              # far beyond: the Gram matrix is numerically singular
+            assert info != 0
         Qr, _, info_r = orth.randcholqr(X, th)
         assert info_r == 0 and metrics.orth_error(Qr)[0] <= 1e-13
-    assert first_fail is not None and j_paper <= first_fail <= 17
+    assert first_fail is not None
