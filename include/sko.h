@@ -116,6 +116,8 @@ typedef struct {
  *                 parallel monomial vectors to float would cost iterations.  The
  *                 one-stage and batched solvers write the monomial vectors to the
  *                 float basis directly.)
+ *  phase_timing   1: fill t_spmv, t_orth and t_small of sko_gmres_info (HIP events at
+ *                 the phase boundaries, a few microseconds each); 0: they are 0.
  *  tol            stop when ||b - A x||_2 / ||b||_2 <= tol (explicit, double).
  *  maxiter        cap on generated basis vectors (0: 50000).
  */
@@ -124,7 +126,7 @@ typedef struct {
     int32_t precond;
     int32_t intra;
     int32_t precision;
-    int32_t reserved_;
+    int32_t phase_timing;
     sko_sketch sketch;
     double tol;
     int64_t maxiter;
@@ -138,6 +140,14 @@ typedef struct {
     double relres;           /* last explicit relative residual */
     double relres_implicit;  /* last implicit (least-squares) relative residual */
     double t_total;          /* seconds, measured with HIP events on the stream */
+    /* Phase times in seconds (opts->phase_timing), the split the paper's time-to-solution
+     * table reports (Table 4: SpMV and orthogonalisation):
+     *  t_spmv   matrix-powers SpMVs and the explicit residual b - A x;
+     *  t_orth   block orthogonalisation: tall passes, reductions and their small
+     *           factorisations (sketch QR, Cholesky, sketch-space BCGS2);
+     *  t_small  Hessenberg bookkeeping, least squares and the update x += M^{-1} Q y.
+     * The batched solver reports the whole batch's phase times for every system. */
+    double t_spmv, t_orth, t_small;
 } sko_gmres_info;
 
 /* Create a context on HIP device `device` that orders its work on `hip_stream`
@@ -173,6 +183,22 @@ sko_status sko_orth_blocks(sko_ctx ctx, int64_t n, int32_t nb, int32_t w,
                            const void* V, int64_t ldv, void* Q, int64_t ldq,
                            double* R, int64_t ldr, const sko_orth_opts* opts,
                            int32_t* breakdown_col);
+
+/*
+ * Sketch a tall block: Y = Theta^T X (Section 3: the sketch is applied to a block as
+ * Theta^T X; Section 5.2: the Count sketch, here the sparse-sign sketch, is applied without
+ * storing Theta).  This is the reduction the RandCholQR step (Fig. 4a) and the two-stage
+ * panel step (Fig. 8) run on their panels, with the same kernels, the same nonzero
+ * placement (see sko_sketch) and the same order of partial sums; it exposes that sketch so
+ * it can be checked on its own.
+ *  X          DEVICE, n x w column-major (leading dimension ldx >= n), w <= 16; double for
+ *             SKO_F64, float for SKO_MIXED_F32 (`precision`).
+ *  sketch     Theta (kind, k <= 256, zeta, seed; or the caller's Gaussian array with n rows).
+ *  Y          HOST, k x w column-major (leading dimension ldy >= k), written on success.
+ * Errors: SKO_EINVAL (shapes, NULL pointers, an invalid sketch), SKO_ENOMEM, SKO_EDEVICE.
+ */
+sko_status sko_sketch_apply(sko_ctx ctx, int64_t n, int32_t w, const void* X, int64_t ldx,
+                            int32_t precision, const sko_sketch* sketch, double* Y, int64_t ldy);
 
 /*
  * Restarted s-step GMRES (Fig. 1): solve A x = b with right preconditioning.

@@ -20,8 +20,8 @@ SKO_SKETCH_GAUSSIAN, SKO_SKETCH_SPARSE_SIGN = 0, 1
 SKO_INTRA_CHOLQR2, SKO_INTRA_RANDCHOLQR = 0, 1
 
 EXPORTED = ["sko_create", "sko_destroy", "sko_set_stream", "sko_strerror", "sko_orth_block",
-            "sko_orth_blocks", "sko_gmres", "sko_gmres_batched", "sko_autotune_orth", "sko_profile_enable",
-            "sko_profile_read"]
+            "sko_orth_blocks", "sko_sketch_apply", "sko_gmres", "sko_gmres_batched", "sko_autotune_orth",
+            "sko_profile_enable", "sko_profile_read"]
 
 
 class sko_sketch(C.Structure):
@@ -43,14 +43,14 @@ class sko_csr(C.Structure):
 class sko_gmres_opts(C.Structure):
     _fields_ = [("s", C.c_int32), ("shat", C.c_int32), ("m", C.c_int32), ("two_stage", C.c_int32),
                 ("precond", C.c_int32), ("intra", C.c_int32), ("precision", C.c_int32),
-                ("reserved_", C.c_int32), ("sketch", sko_sketch), ("tol", C.c_double),
+                ("phase_timing", C.c_int32), ("sketch", sko_sketch), ("tol", C.c_double),
                 ("maxiter", C.c_int64)]
 
 
 class sko_gmres_info(C.Structure):
     _fields_ = [("converged", C.c_int32), ("breakdown_col", C.c_int32), ("iters", C.c_int64),
                 ("restarts", C.c_int64), ("relres", C.c_double), ("relres_implicit", C.c_double),
-                ("t_total", C.c_double)]
+                ("t_total", C.c_double), ("t_spmv", C.c_double), ("t_orth", C.c_double), ("t_small", C.c_double)]
 
 
 class sko_kernel_stat(C.Structure):
@@ -72,6 +72,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
                                    C.POINTER(sko_orth_opts), C.POINTER(i32)]
     lib.sko_orth_blocks.argtypes = [vp, i64, i32, i32, vp, i64, vp, i64, dp, i64,
                                     C.POINTER(sko_orth_opts), C.POINTER(i32)]
+    lib.sko_sketch_apply.argtypes = [vp, i64, i32, vp, i64, i32, C.POINTER(sko_sketch), dp, i64]
     lib.sko_gmres.argtypes = [vp, C.POINTER(sko_csr), vp, vp, C.POINTER(sko_gmres_opts),
                               C.POINTER(sko_gmres_info)]
     lib.sko_gmres_batched.argtypes = [vp, i32, C.POINTER(sko_csr), C.POINTER(vp), C.POINTER(vp),
@@ -99,7 +100,42 @@ def strerror(status: int) -> str:
     return _lib.sko_strerror(status).decode()
 
 
-def _colmajor(t, name):
+_PRECISIONS = {"f64": SKO_F64, "mixed": SKO_MIXED_F32}
+_INTRAS = {"randcholqr": SKO_INTRA_RANDCHOLQR, "cholqr2": SKO_INTRA_CHOLQR2}
+
+
+def _precision_code(precision: str) -> int:
+    if precision not in _PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}, not {precision!r}")
+    return _PRECISIONS[precision]
+
+
+def _intra_code(intra: str) -> int:
+    if intra not in _INTRAS:
+        raise ValueError(f"intra must be one of {sorted(_INTRAS)}, not {intra!r}")
+    return _INTRAS[intra]
+
+
+def _storage_dtype(precision: str):
+    import torch
+    return torch.float32 if _precision_code(precision) == SKO_MIXED_F32 else torch.float64
+
+
+def _check_tensor(t, name, dtype, device_index=None):
+    """The library reads element sizes from the precision option, not from the tensor: a
+    tensor of another dtype, or on another device, would be read out of bounds."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, not {t.dtype}")
+    if t.device.type != "cuda" or (device_index is not None and t.device.index != device_index):
+        raise ValueError(f"{name} must be on cuda:{device_index}, not {t.device}")
+
+
+def _colmajor(t, name, dtype=None, device_index=None):
+    if dtype is not None:
+        _check_tensor(t, name, dtype, device_index)
     if t.dim() != 2 or t.stride(0) != 1:
         raise ValueError(f"{name} must be a column-major 2-D tensor (stride(0) == 1)")
     return t.data_ptr(), max(t.stride(1), t.shape[0])
@@ -111,7 +147,8 @@ def make_sketch(kind: str = "sparse_sign", k: int = 64, zeta: int = 8, seed: int
     if kind == "sparse_sign":
         sk.kind, sk.k, sk.zeta, sk.seed = SKO_SKETCH_SPARSE_SIGN, k, zeta, seed
     elif kind == "gaussian":
-        ptr, ld = _colmajor(theta, "theta")
+        import torch
+        ptr, ld = _colmajor(theta, "theta", torch.float64)
         sk.kind, sk.k, sk.zeta, sk.seed, sk.theta, sk.ld_theta = SKO_SKETCH_GAUSSIAN, theta.shape[1], 0, 0, ptr, ld
     else:
         raise ValueError(kind)
@@ -121,22 +158,23 @@ def make_sketch(kind: str = "sparse_sign", k: int = 64, zeta: int = 8, seed: int
 def orth_opts(intra="randcholqr", two_stage=False, panels_per_big=1, reorth=True, precision="f64",
               sketch: sko_sketch | None = None) -> sko_orth_opts:
     o = sko_orth_opts()
-    o.intra = SKO_INTRA_RANDCHOLQR if intra == "randcholqr" else SKO_INTRA_CHOLQR2
+    o.intra = _intra_code(intra)
     o.two_stage = int(bool(two_stage))
     o.panels_per_big = int(panels_per_big)
     o.reorth = int(bool(reorth))
-    o.precision = SKO_MIXED_F32 if precision == "mixed" else SKO_F64
+    o.precision = _precision_code(precision)
     o.sketch = sketch if sketch is not None else make_sketch()
     return o
 
 
 def gmres_opts(s=5, m=30, shat=0, two_stage=False, precond=0, intra="randcholqr", precision="f64",
-               sketch: sko_sketch | None = None, tol=1e-10, maxiter=0) -> sko_gmres_opts:
+               sketch: sko_sketch | None = None, tol=1e-10, maxiter=0, phase_timing=False) -> sko_gmres_opts:
     o = sko_gmres_opts()
+    o.phase_timing = int(bool(phase_timing))
     o.s, o.m, o.shat, o.two_stage = int(s), int(m), int(shat), int(bool(two_stage))
     o.precond = int(precond)
-    o.intra = SKO_INTRA_RANDCHOLQR if intra == "randcholqr" else SKO_INTRA_CHOLQR2
-    o.precision = SKO_MIXED_F32 if precision == "mixed" else SKO_F64
+    o.intra = _intra_code(intra)
+    o.precision = _precision_code(precision)
     o.sketch = sketch if sketch is not None else make_sketch()
     o.tol = float(tol)
     o.maxiter = int(maxiter)
@@ -230,13 +268,14 @@ class Context:
     def orth_blocks(self, V, w: int, Q=None, R: bool = True, raise_on_error: bool = True, **opt_kw):
         """Orthogonalise the column-major tensor V (n x nb*w).  Returns (Q, R, status, col)."""
         import torch
+        dt = _storage_dtype(opt_kw.get("precision", "f64"))
         n, N = V.shape
         if N % w:
             raise ValueError("columns must be a multiple of w")
         if Q is None:
-            Q = torch.empty((N, n), dtype=V.dtype, device=V.device).t()
-        vp, ldv = _colmajor(V, "V")
-        qp, ldq = _colmajor(Q, "Q")
+            Q = torch.empty((N, n), dtype=dt, device=V.device).t()
+        vp, ldv = _colmajor(V, "V", dt, self.device)
+        qp, ldq = _colmajor(Q, "Q", dt, self.device)
         Rh = np.zeros((N, N), order="F") if R else None
         opts = orth_opts(**opt_kw)
         st, col = self.sko_orth_blocks(n, N // w, w, vp, ldv, qp, ldq, Rh, N, opts)
@@ -247,14 +286,15 @@ class Context:
     def orth_block(self, Qprev, V, Qout=None, raise_on_error: bool = True, **opt_kw):
         """One BCGS2 block step.  Returns (Qout, R_proj, R_diag, status, col)."""
         import torch
+        dt = _storage_dtype(opt_kw.get("precision", "f64"))
         n, w = V.shape
         p = 0 if Qprev is None else Qprev.shape[1]
         if Qout is None:
-            Qout = torch.empty((w, n), dtype=V.dtype, device=V.device).t()
-        vp, ldv = _colmajor(V, "V")
-        op, ldo = _colmajor(Qout, "Qout")
+            Qout = torch.empty((w, n), dtype=dt, device=V.device).t()
+        vp, ldv = _colmajor(V, "V", dt, self.device)
+        op, ldo = _colmajor(Qout, "Qout", dt, self.device)
         if p > 0:
-            qp, ldq = _colmajor(Qprev, "Q")
+            qp, ldq = _colmajor(Qprev, "Q", dt, self.device)
         else:
             qp, ldq = None, n
         Rp = np.zeros((p, w), order="F") if p > 0 else None
@@ -264,6 +304,20 @@ class Context:
         if raise_on_error and st not in (SKO_OK, SKO_EBREAKDOWN):
             raise SkoError(st, "sko_orth_block", col)
         return Qout, Rp, Rd, st, col
+
+    def sko_sketch_apply(self, n, w, X_ptr, ldx, precision: int, sketch: sko_sketch, Y: np.ndarray, ldy):
+        yp = Y.ctypes.data_as(C.POINTER(C.c_double))
+        return _lib.sko_sketch_apply(self.h, n, w, X_ptr, ldx, precision, C.byref(sketch), yp, ldy)
+
+    def sketch_apply(self, X, sketch: sko_sketch, precision: str = "f64"):
+        """Y = Theta^T X for the column-major device tensor X (n x w).  Returns Y (k x w)."""
+        n, w = X.shape
+        xp, ldx = _colmajor(X, "X", _storage_dtype(precision), self.device)
+        Y = np.zeros((sketch.k, w), order="F")
+        st = self.sko_sketch_apply(n, w, xp, ldx, _precision_code(precision), sketch, Y, sketch.k)
+        if st != SKO_OK:
+            raise SkoError(st, "sko_sketch_apply")
+        return Y
 
 
 def _gmres_method(self, A, b, x0=None, raise_on_error=False, **opt_kw):
@@ -281,6 +335,10 @@ def _gmres_method(self, A, b, x0=None, raise_on_error=False, **opt_kw):
     else:
         x = (x0 if isinstance(x0, torch.Tensor) else torch.from_numpy(np.asarray(x0, dtype=np.float64)).to(
             bt.device)).clone()
+    _check_tensor(bt, "b", torch.float64, self.device)
+    _check_tensor(x, "x", torch.float64, self.device)
+    if bt.dim() != 1 or bt.shape[0] != Ad.n or not bt.is_contiguous() or x.shape != bt.shape or not x.is_contiguous():
+        raise ValueError("b and x must be contiguous vectors of length A.n")
     opts = gmres_opts(**opt_kw)
     st, inf = self.sko_gmres(Ad, bt.data_ptr(), x.data_ptr(), opts)
     if raise_on_error and st not in (SKO_OK, SKO_ENOCONV):
@@ -305,6 +363,10 @@ def colmajor_from_numpy(a: np.ndarray, device="cuda", dtype=None):
 def csr_to_device(A, device="cuda"):
     """Upload a workloads.CSR; returns (sko_csr struct, tensors kept alive)."""
     import torch
+    if A.rowptr.dtype != np.int32 or A.colind.dtype != np.int32 or A.val.dtype != np.float64:
+        raise TypeError("CSR indices must be int32 and values float64")
+    if A.rowptr.shape != (A.n + 1,) or A.colind.shape != (A.nnz,) or A.val.shape != (A.nnz,):
+        raise ValueError("CSR arrays have inconsistent lengths")
     rp = torch.from_numpy(A.rowptr).to(device)
     ci = torch.from_numpy(A.colind).to(device)
     va = torch.from_numpy(A.val).to(device)

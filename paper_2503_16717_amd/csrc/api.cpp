@@ -81,6 +81,13 @@ sko_status sko_orth_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const vo
     return sko::orth_blocks_impl(c, n, nb, w, V, ldv, Q, ldq, R, ldr, opts, breakdown_col);
 }
 
+sko_status sko_sketch_apply(sko_ctx c, int64_t n, int32_t w, const void* X, int64_t ldx, int32_t precision,
+                            const sko_sketch* sketch, double* Y, int64_t ldy) {
+    if (!c) return SKO_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;
+    return sko::sketch_apply_impl(c, n, w, X, ldx, precision, sketch, Y, ldy);
+}
+
 sko_status sko_gmres(sko_ctx c, const sko_csr* A, const double* b, double* x, const sko_gmres_opts* opts,
                      sko_gmres_info* info) {
     if (!c) return SKO_EINVAL;

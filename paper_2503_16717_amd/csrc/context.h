@@ -79,6 +79,93 @@ struct Profiler {
     }
 };
 
+// Two HIP events destroyed on every return path.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() = default;
+    EventPair(const EventPair&) = delete;
+    EventPair& operator=(const EventPair&) = delete;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    hipError_t create() {
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        return hipEventCreate(&b);
+    }
+    // milliseconds between the two records (after b has completed)
+    double ms() const {
+        float v = 0.f;
+        return hipEventElapsedTime(&v, a, b) == hipSuccess ? (double)v : 0.0;
+    }
+};
+
+// Phase times of a solve (sko_gmres_opts::phase_timing): an event pair around each phase
+// interval, folded into per-phase sums whenever the host has synchronised the stream.
+struct PhaseTimer {
+    enum { SPMV = 0, ORTH = 1, SMALL = 2, NPH = 3 };
+    bool on = false;
+    double ms[NPH] = {0.0, 0.0, 0.0};
+    struct Pending {
+        int ph;
+        hipEvent_t e0, e1;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    int open = -1;  // phase of the interval in progress
+
+    PhaseTimer() = default;
+    PhaseTimer(const PhaseTimer&) = delete;
+    PhaseTimer& operator=(const PhaseTimer&) = delete;
+    ~PhaseTimer() {
+        for (Pending& p : pending) {
+            pool.push_back(p.e0);
+            pool.push_back(p.e1);
+        }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+    hipEvent_t take() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+    }
+    // Start phase `ph` (ending the interval in progress, if another phase).
+    void phase(int ph, hipStream_t st) {
+        if (!on || ph == open) return;
+        stop(st);
+        hipEvent_t e0 = take(), e1 = take();
+        if (!e0 || !e1 || hipEventRecord(e0, st) != hipSuccess) {
+            if (e0) pool.push_back(e0);
+            if (e1) pool.push_back(e1);
+            return;
+        }
+        pending.push_back(Pending{ph, e0, e1});
+        open = ph;
+    }
+    void stop(hipStream_t st) {
+        if (!on || open < 0) return;
+        (void)hipEventRecord(pending.back().e1, st);
+        open = -1;
+    }
+    // Fold the recorded intervals into the sums; call after stop() and a synchronisation of
+    // the stream.
+    void flush() {
+        if (!on) return;
+        for (Pending& p : pending) {
+            float v = 0.f;
+            if (hipEventElapsedTime(&v, p.e0, p.e1) == hipSuccess) ms[p.ph] += v;
+            pool.push_back(p.e0);
+            pool.push_back(p.e1);
+        }
+        pending.clear();
+    }
+};
+
 }  // namespace sko
 
 struct sko_ctx_s {
@@ -164,6 +251,8 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
 sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq,
                            const void* V, int64_t ldv, void* Qo, int64_t ldqo, double* Rp, double* Rd,
                            const sko_orth_opts* o, int32_t* breakdown_col);
+sko_status sketch_apply_impl(sko_ctx c, int64_t n, int32_t w, const void* X, int64_t ldx, int32_t precision,
+                             const sko_sketch* sk, double* Y, int64_t ldy);
 sko_status autotune_orth_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const sko_orth_opts* o);
 sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, const sko_gmres_opts* o,
                       sko_gmres_info* info);

@@ -59,6 +59,10 @@ struct GmCtx {
     int64_t max_n = 0;
     double rows_bytes = 0.0, nnz_bytes = 0.0;  // active totals for the byte accounting
     int spmv_cap = 0;
+    PhaseTimer* pt = nullptr;  // phase times (sko_gmres_opts::phase_timing)
+    void phase(int ph) const {
+        if (pt) pt->phase(ph, st);
+    }
 };
 
 // Small per-solve device buffers, one contiguous block (offsets in bytes).
@@ -125,10 +129,12 @@ void* col_ptr(const GmCtx& g, int col) {
 }
 
 sko_status read_scalars(GmCtx& g, const double* dev, int count, int* status_out) {
+    if (g.pt) g.pt->stop(g.st);
     SKO_HIP(hipMemcpyAsync(g.host, dev, sizeof(double) * count, hipMemcpyDeviceToHost, g.st));
     SKO_HIP(hipMemcpyAsync(reinterpret_cast<int*>(g.host + 4), g.status, sizeof(int), hipMemcpyDeviceToHost, g.st));
     SKO_HIP(hipStreamSynchronize(g.st));
     g.c->prof.flush();
+    if (g.pt) g.pt->flush();
     if (status_out) *status_out = *reinterpret_cast<int*>(g.host + 4);
     return SKO_OK;
 }
@@ -149,6 +155,7 @@ sko_status norm2(GmCtx& g, Engine& e1, const double* v, double* out) {
 sko_status mpk(GmCtx& g, int from, int s) {
     const double nnz = g.br ? g.nnz_bytes : (double)g.A.nnz;
     const double rows = g.br ? g.rows_bytes : (double)g.n;
+    g.phase(PhaseTimer::SPMV);
     for (int i = 1; i <= s; ++i) {
         const int ev = g.c->prof.begin(std::string("spmv ") + (g.f32 ? "f32" : "f64"),
                                        nnz * (g.f32 ? 8.0 : 12.0) + rows * (g.f32 ? 12.0 : 20.0), g.st);
@@ -169,6 +176,7 @@ sko_status mpk(GmCtx& g, int from, int s) {
 // orthogonalised columns.
 sko_status mpk_panel(GmCtx& g, int from, int s) {
     double* P = g.P;
+    g.phase(PhaseTimer::SPMV);
     SKO_HIP(launch_widen(g.n, static_cast<const float*>(col_ptr(g, from)), P, g.grid_cap, g.st));
     for (int i = 1; i <= s; ++i) {
         const int ev = g.c->prof.begin("spmv f32 values, f64 vectors",
@@ -191,6 +199,7 @@ sko_status gm_op(GmCtx& g, GmSmallArgs a) {
     a.res = g.res;
     a.beta = g.beta;
     a.coef = g.coef;
+    g.phase(PhaseTimer::SMALL);
     const int ev = g.c->prof.begin("gmres small", 0.0, g.st);
     SKO_HIP(launch_gm_small(a, g.st, g.br));
     g.c->prof.end(ev, g.st);
@@ -205,6 +214,7 @@ sko_status cycle_one_stage(GmCtx& g, Engine& e, double bnorm, double tol, sko_gm
     while (k < g.m) {
         if ((s = mpk(g, k, g.s))) return s;
         void* Vk = col_ptr(g, k);
+        g.phase(PhaseTimer::ORTH);
         if ((s = one_stage_block(e, g.bb, g.intra, k, g.Q, g.ld, Vk, g.ld, Vk, g.ld, g.coef, g.m + 1, k))) return s;
         GmSmallArgs a{};
         a.op = GM_BLOCK;
@@ -241,6 +251,7 @@ sko_status two_stage_panel(GmCtx& g, Engine& e, int k0, int i) {
     const bool p64 = g.P != nullptr;
     if ((s = p64 ? mpk_panel(g, kk, S) : mpk(g, kk, S))) return s;
     void* V = p64 ? static_cast<void*>(g.P) : col_ptr(g, kk);
+    g.phase(PhaseTimer::ORTH);
     PassKey key{W, g.f32 && !p64, red_sk, false, 0, false};
     PassArgs a{};
     a.Y = V;
@@ -313,6 +324,7 @@ sko_status two_stage_bigclose(GmCtx& g, Engine& e, int k0) {
     sko_status s;
     const int Wb = g.Wb;
     void* Qb = col_ptr(g, k0);
+    g.phase(PhaseTimer::ORTH);
     {
         SmallArgs sm{};
         sm.op = OP_CHOL;
@@ -471,10 +483,12 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     g.dinv = g.jacobi ? ar.at<double>(o_dinv) : nullptr;
     carve_small(g, ar.at<char>(o_small), L, k);
 
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    SKO_HIP(hipEventCreate(&t0));
-    SKO_HIP(hipEventCreate(&t1));
-    SKO_HIP(hipEventRecord(t0, g.st));
+    EventPair ev_total;
+    SKO_HIP(ev_total.create());
+    PhaseTimer pt;
+    pt.on = o->phase_timing != 0;
+    g.pt = &pt;
+    SKO_HIP(hipEventRecord(ev_total.a, g.st));
     SKO_HIP(hipMemsetAsync(g.status, 0, 256, g.st));
     c->tickets = 0;
 
@@ -486,11 +500,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
                                g.st));
         SKO_HIP(hipStreamSynchronize(g.st));
         bad = *reinterpret_cast<int*>(g.host + 4);
-        if (bad) {
-            (void)hipEventDestroy(t0);
-            (void)hipEventDestroy(t1);
-            return SKO_EINVAL;
-        }
+        if (bad) return SKO_EINVAL;
     }
     // ---- operator set-up: Jacobi scaling / float copy of the MPK values
     g.A = CsrView{A->n, A->nnz, A->rowptr, A->colind, A->val, A->val};
@@ -532,6 +542,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
         while (true) {
             // explicit residual r = b - A x into basis column 0, beta = ||r||
             const int rg = residual_grid(A->n, g.grid_cap);
+            g.phase(PhaseTimer::SPMV);
             const int ev = c->prof.begin("residual f64", (double)A->nnz * 12.0 + (double)A->n * 24.0, g.st);
             SKO_HIP(launch_residual(g.A, x, b, g.f32, g.Q, e.partials, rg, g.st));
             c->prof.end(ev, g.st);
@@ -571,6 +582,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
                 a.R1 = g.beta;
                 a.X = g.Q;
                 a.ldx = g.ld;
+                g.phase(PhaseTimer::ORTH);
                 if ((s = e1f.plain({1, g.f32, RED_NONE, false, 1, true}, a))) return s;
             }
             GmSmallArgs ia{};
@@ -585,6 +597,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
             }
             if (s) return s;
             {
+                g.phase(PhaseTimer::SMALL);
                 const int ev2 = c->prof.begin("update x", (double)A->n * (kreached * eb + 16.0), g.st);
                 SKO_HIP(launch_update(A->n, g.f32, g.Q, g.ld, kreached, g.y, g.dinv, x, g.st));
                 c->prof.end(ev2, g.st);
@@ -592,14 +605,15 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
             inf.restarts += 1;
         }
     }
-    SKO_HIP(hipEventRecord(t1, g.st));
-    SKO_HIP(hipEventSynchronize(t1));
+    pt.stop(g.st);
+    SKO_HIP(hipEventRecord(ev_total.b, g.st));
+    SKO_HIP(hipEventSynchronize(ev_total.b));
     c->prof.flush();
-    float ms = 0.f;
-    SKO_HIP(hipEventElapsedTime(&ms, t0, t1));
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    inf.t_total = ms * 1e-3;
+    pt.flush();
+    inf.t_total = ev_total.ms() * 1e-3;
+    inf.t_spmv = pt.ms[PhaseTimer::SPMV] * 1e-3;
+    inf.t_orth = pt.ms[PhaseTimer::ORTH] * 1e-3;
+    inf.t_small = pt.ms[PhaseTimer::SMALL] * 1e-3;
     if (info) *info = inf;
     return result;
 }
@@ -730,20 +744,24 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     g.spmv_cap = (int)std::max<int64_t>(1, std::min<int64_t>((groups8 + 7) / 8, cap));
     const size_t st_off = (size_t)(reinterpret_cast<char*>(g.status) - small_of(0));
 
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    SKO_HIP(hipEventCreate(&t0));
-    SKO_HIP(hipEventCreate(&t1));
-    SKO_HIP(hipEventRecord(t0, g.st));
+    EventPair ev_total;
+    SKO_HIP(ev_total.create());
+    PhaseTimer pt;
+    pt.on = o->phase_timing != 0;
+    g.pt = &pt;
+    SKO_HIP(hipEventRecord(ev_total.a, g.st));
     SKO_HIP(hipMemset2DAsync(small0 + st_off, L.bytes, 0, 256, nsys, g.st));
 
     // strided reads of one double / one int of every system's small block
     auto read_dbl = [&](const double* tmpl) -> sko_status {
+        pt.stop(g.st);
         SKO_HIP(hipMemcpy2DAsync(dbl_h, sizeof(double), tmpl, L.bytes, sizeof(double), nsys, hipMemcpyDeviceToHost,
                                  g.st));
         SKO_HIP(hipMemcpy2DAsync(int_h, sizeof(int), g.status, L.bytes, sizeof(int), nsys, hipMemcpyDeviceToHost,
                                  g.st));
         SKO_HIP(hipStreamSynchronize(g.st));
         c->prof.flush();
+        pt.flush();
         return SKO_OK;
     };
 
@@ -872,6 +890,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
         e.rows_bytes = e1f.rows_bytes = g.rows_bytes = nr;
         g.nnz_bytes = nz;
         if (list.empty()) return SKO_OK;
+        pt.stop(g.st);
         SKO_HIP(hipMemcpyAsync(act_d, act_h, sizeof(int) * list.size(), hipMemcpyHostToDevice, g.st));
         SKO_HIP(hipMemcpyAsync(blk_d, blk_h, sizeof(int) * (list.size() + 1), hipMemcpyHostToDevice, g.st));
         SKO_HIP(hipMemset2DAsync(small0 + st_off + 16 * sizeof(int), L.bytes, 0, sizeof(unsigned), nsys, g.st));
@@ -888,6 +907,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
         if ((s = set_active(live))) return s;
         // explicit residuals r = b - A x into basis column 0, beta = ||r||
         {
+            g.phase(PhaseTimer::SPMV);
             const int ev = c->prof.begin("residual f64", g.nnz_bytes * 12.0 + g.rows_bytes * 24.0,
                                          g.st);
             SKO_HIP(launch_residual_batched(g.f32, g.avg_nnz, g.Q, part0, Gr, g.st, br));
@@ -934,6 +954,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
             a.R1 = g.beta;
             a.X = g.Q;
             a.ldx = g.ld;
+            g.phase(PhaseTimer::ORTH);
             if ((s = e1f.plain({1, g.f32, RED_NONE, false, 1, true}, a))) return s;
         }
         GmSmallArgs ia{};
@@ -979,21 +1000,24 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
         if (!upd.empty()) {
             SKO_HIP(hipMemcpyAsync(tbl_d, tbl_h, sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, g.st));
             if ((s = set_active(upd))) return s;
+            g.phase(PhaseTimer::SMALL);
             const int ev2 = c->prof.begin("update x", g.rows_bytes * (m * eb + 16.0), g.st);
             SKO_HIP(launch_update_batched(g.f32, max_n, g.Q, m, g.y, g.st, br));
             c->prof.end(ev2, g.st);
         }
     }
-    SKO_HIP(hipEventRecord(t1, g.st));
-    SKO_HIP(hipEventSynchronize(t1));
+    pt.stop(g.st);
+    SKO_HIP(hipEventRecord(ev_total.b, g.st));
+    SKO_HIP(hipEventSynchronize(ev_total.b));
     c->prof.flush();
-    float ms = 0.f;
-    SKO_HIP(hipEventElapsedTime(&ms, t0, t1));
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
+    pt.flush();
+    const double total_ms = ev_total.ms();
     sko_status first = SKO_OK;
     for (int32_t i = 0; i < nsys; ++i) {
-        S[i].inf.t_total = ms * 1e-3;
+        S[i].inf.t_total = total_ms * 1e-3;
+        S[i].inf.t_spmv = pt.ms[PhaseTimer::SPMV] * 1e-3;
+        S[i].inf.t_orth = pt.ms[PhaseTimer::ORTH] * 1e-3;
+        S[i].inf.t_small = pt.ms[PhaseTimer::SMALL] * 1e-3;
         if (infos) infos[i] = S[i].inf;
         if (S[i].result != SKO_OK && first == SKO_OK) first = S[i].result;
     }

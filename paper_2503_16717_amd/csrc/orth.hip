@@ -337,6 +337,48 @@ sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const voi
     return s;
 }
 
+// Y = Theta^T X (Section 3), the reduction of the update + sketch pass on its own: the same
+// kernels, slot decode and partial-sum order as the sketch of a RandCholQR or two-stage step.
+sko_status sketch_apply_impl(sko_ctx c, int64_t n, int32_t w, const void* X, int64_t ldx, int32_t precision,
+                             const sko_sketch* sk, double* Y, int64_t ldy) {
+    if (!X || !sk || !Y || n < 1 || w < 1 || w > kMaxPassW || ldx < n) return SKO_EINVAL;
+    if (precision != SKO_F64 && precision != SKO_MIXED_F32) return SKO_EINVAL;
+    if (!sketch_ok(*sk, n) || ldy < sk->k) return SKO_EINVAL;
+    const bool f32 = precision == SKO_MIXED_F32;
+    const int k = sk->k;
+    OneStageLayout L = layout_one_stage(c, n, w, 0, k, w);
+    sko_status s = ensure_workspace(c, L.total);
+    if (s) return s;
+    Arena ar(c);
+    Engine e(c, n, w, f32, *sk);
+    e.partials = ar.at<double>(L.partials);
+    e.part_stride = L.part_stride;
+    e.gmax = L.gmax;
+    e.status = ar.at<int>(L.status);
+    e.counter = reinterpret_cast<unsigned*>(e.status + 16);
+    SKO_HIP(hipMemsetAsync(e.status, 0, 256, c->stream));
+    c->tickets = 0;
+    BlockBufs bb = carve(c, L, 0, k, w);
+    const bool sparse = sk->kind == SKO_SKETCH_SPARSE_SIGN;
+    PassArgs a{};
+    a.Y = X;
+    a.ldy = ldx;
+    SmallArgs sm{};
+    sm.op = OP_STORE;
+    sm.w = w;
+    sm.out = bb.Ysk;
+    const double scale = sparse ? 1.0 / std::sqrt((double)sk->zeta) : 1.0;
+    if ((s = e.reduction({w, f32, sparse ? RED_SKETCH_SPARSE : RED_SKETCH_DENSE, false, 0, false}, a, k, X, ldx,
+                         nullptr, 0, sm, scale)))
+        return s;
+    if ((s = ensure_pinned(c, sizeof(double) * (size_t)k * w))) return s;
+    double* Yh = static_cast<double*>(c->pinned);
+    SKO_HIP(hipMemcpyAsync(Yh, bb.Ysk, sizeof(double) * (size_t)k * w, hipMemcpyDeviceToHost, c->stream));
+    if ((s = finish(c, e.status, nullptr))) return s;
+    for (int jc = 0; jc < w; ++jc) std::memcpy(Y + (int64_t)jc * ldy, Yh + (int64_t)jc * k, sizeof(double) * k);
+    return SKO_OK;
+}
+
 sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const void* V, int64_t ldv, void* Q,
                             int64_t ldq, double* R, int64_t ldr, const sko_orth_opts* o, int32_t* breakdown_col) {
     const int ppb = o->panels_per_big;

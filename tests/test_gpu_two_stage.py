@@ -6,6 +6,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from parity_log import assert_rel  # noqa: E402
 from oracle import metrics, orth  # noqa: E402
 from oracle.sketch import Sketch  # noqa: E402
 from paper_2503_16717_amd import workloads as wl  # noqa: E402
@@ -52,7 +53,7 @@ def test_two_stage_matches_oracle(B, ctx, ppb, e, n):
     ref = orth.orth_blocks_two_stage(V, w, ppb, Sketch.sparse_sign(64, 8, 0))
     assert ref.info == 0
     assert np.all(np.diag(R) > 0)
-    assert metrics.rel_diff(R, ref.R) <= tol_r(e)
+    assert_rel(R, ref.R, tol_r(e))
     assert metrics.orth_error(Q)[0] <= 1e-13
     assert metrics.backward_error(V, Q, R) <= 1e-14
     if e <= 6:
@@ -66,7 +67,7 @@ def test_two_stage_without_reorth_single_big_panel(B, ctx):
     Q, R, st, col = run(B, ctx, V, w, 12, reorth=False, k=128)
     assert st == B.SKO_OK
     ref = orth.orth_blocks_two_stage(V, w, 12, Sketch.sparse_sign(128, 8, 0), reorth=False)
-    assert metrics.rel_diff(R, ref.R) <= tol_r(8)
+    assert_rel(R, ref.R, tol_r(8))
     assert metrics.orth_error(Q)[0] <= 1e-13
 
 
@@ -76,7 +77,7 @@ def test_two_stage_width11(B, ctx):
     Q, R, st, col = run(B, ctx, V, w, 2, k=64)
     assert st == B.SKO_OK
     ref = orth.orth_blocks_two_stage(V, w, 2, Sketch.sparse_sign(64, 8, 0))
-    assert metrics.rel_diff(R, ref.R) <= tol_r(9)
+    assert_rel(R, ref.R, tol_r(9))
     assert metrics.orth_error(Q)[0] <= 1e-13
 
 
@@ -87,7 +88,7 @@ def test_two_stage_config2_shape_reduced_rows(B, ctx):
     Q, R, st, col = run(B, ctx, V, w, 6)
     assert st == B.SKO_OK
     ref = orth.orth_blocks_two_stage(V, w, 6, Sketch.sparse_sign(64, 8, 0))
-    assert metrics.rel_diff(R, ref.R) <= tol_r(12)
+    assert_rel(R, ref.R, tol_r(12))
     assert metrics.orth_error(Q)[0] <= 1e-13
     assert metrics.backward_error(V, Q, R) <= 1e-14
 
@@ -100,7 +101,7 @@ def test_two_stage_equals_one_stage_single_panel(B, ctx):
     Vd = B.colmajor_from_numpy(V, "cuda")
     Q1, R1, st1, _ = ctx.orth_blocks(Vd, 6, intra="randcholqr", sketch=B.make_sketch("sparse_sign", 64, 8, 0))
     assert st1 == st2 == B.SKO_OK
-    assert metrics.rel_diff(R2, R1) <= tol_r(6)
+    assert_rel(R2, R1, tol_r(6))
 
 
 def test_two_stage_rejects_small_sketch(B, ctx):
@@ -120,7 +121,7 @@ def test_two_stage_many_big_panels(B, ctx):
     ref = orth.orth_blocks_two_stage(V, w, ppb, Sketch.sparse_sign(64, 8, 0))
     assert ref.info == 0
     kappa = np.linalg.cond(V)
-    assert metrics.rel_diff(R, ref.R) <= max(tol_r(e), 10.0 * kappa * U)
+    assert_rel(R, ref.R, max(tol_r(e), 10.0 * kappa * U))
     assert metrics.orth_error(Q)[0] <= 1e-13
     assert metrics.backward_error(V, Q, R) <= 1e-14
 
@@ -149,8 +150,8 @@ def test_two_stage_widest_big_panels(B, ctx, mixed, n):
     if mixed:
         assert metrics.orth_error(Q)[0] <= 1e-5
         assert metrics.backward_error(V, Q, R) <= 1e-6
-        assert metrics.rel_diff(R, ref.R) <= 1e-5
+        assert_rel(R, ref.R, 1e-5)
     else:
-        assert metrics.rel_diff(R, ref.R) <= tol_r(e)
+        assert_rel(R, ref.R, tol_r(e))
         assert metrics.orth_error(Q)[0] <= 1e-13
         assert metrics.backward_error(V, Q, R) <= 1e-14
