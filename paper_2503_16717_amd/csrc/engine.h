@@ -39,11 +39,26 @@ struct Engine {
     // total, for the byte accounting.
     const BatchReloc* br = nullptr;
     double rows_bytes = 0.0;
+    // Host count of arrivals on `counter` since it was zeroed (the context's, unless a call
+    // keeps its own).
+    unsigned* tickets;
+    // false: no profiler events (no host-side bookkeeping at all) for this engine's launches
+    bool profile = true;
 
     Engine(sko_ctx c_, int64_t n_, int W_, bool f32_, const sko_sketch& sk_)
-        : c(c_), st(c_->stream), n(n_), W(W_), f32(f32_), sk(sk_) {
+        : c(c_), st(c_->stream), n(n_), W(W_), f32(f32_), sk(sk_), tickets(&c_->tickets) {
         nstrips = (n + kPassThreads - 1) / kPassThreads;
         rows_bytes = (double)n;
+    }
+
+    // Profiler bracket of one launch; the kernel-kind name is built only while profiling.
+    template <typename NameFn>
+    int pbegin(NameFn&& name, double bytes) {
+        if (!profile || !c->prof.on) return -1;
+        return c->prof.begin(name(), bytes, st);
+    }
+    void pend(int ev) {
+        if (ev >= 0) c->prof.end(ev, st);
     }
 
     // Workgroups of a pass launch: the autotuned count for the variant and this row-count
@@ -102,9 +117,9 @@ struct Engine {
                 b.theta = sk.theta + (int64_t)r0 * sk.ld_theta;
                 b.ldtheta = sk.ld_theta;
             }
-            const int ev = c->prof.begin(pass_name(key), pass_bytes(key, b), st);
+            const int ev = pbegin([&] { return pass_name(key); }, pass_bytes(key, b));
             SKO_HIP(launch_pass(key, b, G, st, br));
-            c->prof.end(ev, st);
+            pend(ev);
         }
         ReduceArgs ra{};
         ra.partials = partials;
@@ -113,15 +128,15 @@ struct Engine {
         ra.count = rows_total * W;
         ra.scale = scale;
         ra.counter = counter;
-        ra.ticket0 = take_tickets(c->tickets, ra.count, br);
+        ra.ticket0 = take_tickets(*tickets, ra.count, br);
         ra.rows = ra.count;
         ra.ldo = ra.count;
         ra.small = small;
         ra.small.status = status;
         ra.unit_rows = kPassThreads;  // a strip is at least this many rows
-        const int ev = c->prof.begin(reduce_name(small.op), 8.0 * G * ra.count, st);
+        const int ev = pbegin([&] { return std::string(reduce_name(small.op)); }, 8.0 * G * ra.count);
         SKO_HIP(launch_reduce(ra, st, br));
-        c->prof.end(ev, st);
+        pend(ev);
         return SKO_OK;
     }
 
@@ -130,11 +145,11 @@ struct Engine {
     sko_status gemm_reduction(const void* A, int64_t lda, int ma, const void* B, int64_t ldb, int nbc,
                               SmallArgs small, int64_t ldo) {
         const int G = gemm_grid(A == B && lda == ldb && ma == nbc);
-        const int ev = c->prof.begin(std::string("wide_gemm_tn ") + (A == B ? "gram" : "proj") + " f" +
-                                         (f32 ? "32" : "64"),
-                                     rows_bytes * (A == B ? ma : ma + nbc) * (f32 ? 4.0 : 8.0), st);
+        const int ev = pbegin(
+            [&] { return std::string("wide_gemm_tn ") + (A == B ? "gram" : "proj") + " f" + (f32 ? "32" : "64"); },
+            rows_bytes * (A == B ? ma : ma + nbc) * (f32 ? 4.0 : 8.0));
         SKO_HIP(launch_skinny_gemm_tn(n, A, lda, ma, B, ldb, nbc, f32, partials, G, st, br));
-        c->prof.end(ev, st);
+        pend(ev);
         ReduceArgs ra{};
         ra.partials = partials;
         ra.stride = (int64_t)ma * nbc;
@@ -142,34 +157,36 @@ struct Engine {
         ra.count = ma * nbc;
         ra.scale = 1.0;
         ra.counter = counter;
-        ra.ticket0 = take_tickets(c->tickets, ra.count, br);
+        ra.ticket0 = take_tickets(*tickets, ra.count, br);
         ra.rows = ma;
         ra.ldo = ldo;
         ra.small = small;
         ra.small.status = status;
         ra.unit_rows = kGemmUnitRows;
-        const int ev2 = c->prof.begin(reduce_name(small.op), 8.0 * G * ra.count, st);
+        const int ev2 = pbegin([&] { return std::string(reduce_name(small.op)); }, 8.0 * G * ra.count);
         SKO_HIP(launch_reduce(ra, st, br));
-        c->prof.end(ev2, st);
+        pend(ev2);
         return SKO_OK;
     }
 
     // Rpk: the triangular factor packed by the Cholesky step that produced it (SmallArgs::Rpk)
     sko_status rowop(int Wd, const void* Y, int64_t ldy, const void* Qu, int64_t ldqu, int pu, const double* Cu,
                      const double* Rpk, void* X, int64_t ldx) {
-        const int ev = c->prof.begin(std::string("wide_rowop f") + (f32 ? "32" : "64") + (pu > 0 ? " upd" : "") +
-                                         (Rpk ? " trsm" : ""),
-                                     rows_bytes * (2 * Wd + pu) * (f32 ? 4.0 : 8.0), st);
+        const int ev = pbegin(
+            [&] {
+                return std::string("wide_rowop f") + (f32 ? "32" : "64") + (pu > 0 ? " upd" : "") + (Rpk ? " trsm" : "");
+            },
+            rows_bytes * (2 * Wd + pu) * (f32 ? 4.0 : 8.0));
         SKO_HIP(launch_wide_rowop(n, Wd, f32, Y, ldy, Qu, ldqu, pu, Cu, Rpk, X, ldx, st, br));
-        c->prof.end(ev, st);
+        pend(ev);
         return SKO_OK;
     }
 
     sko_status plain(PassKey key, PassArgs a) {
         a.n = n;
-        const int ev = c->prof.begin(pass_name(key), pass_bytes(key, a), st);
+        const int ev = pbegin([&] { return pass_name(key); }, pass_bytes(key, a));
         SKO_HIP(launch_pass(key, a, grid_for({key}), st, br));
-        c->prof.end(ev, st);
+        pend(ev);
         return SKO_OK;
     }
 

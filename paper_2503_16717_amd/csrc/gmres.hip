@@ -489,7 +489,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     pt.on = o->phase_timing != 0;
     g.pt = &pt;
     SKO_HIP(hipEventRecord(ev_total.a, g.st));
-    SKO_HIP(hipMemsetAsync(g.status, 0, 256, g.st));
+    SKO_HIP(launch_zero(g.status, 256, g.st));
     c->tickets = 0;
 
     // ---- CSR structure check before any kernel indexes through it
@@ -750,7 +750,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     pt.on = o->phase_timing != 0;
     g.pt = &pt;
     SKO_HIP(hipEventRecord(ev_total.a, g.st));
-    SKO_HIP(hipMemset2DAsync(small0 + st_off, L.bytes, 0, 256, nsys, g.st));
+    SKO_HIP(launch_zero_2d(small0 + st_off, L.bytes, 256, nsys, g.st));
 
     // strided reads of one double / one int of every system's small block
     auto read_dbl = [&](const double* tmpl) -> sko_status {
@@ -893,7 +893,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
         pt.stop(g.st);
         SKO_HIP(hipMemcpyAsync(act_d, act_h, sizeof(int) * list.size(), hipMemcpyHostToDevice, g.st));
         SKO_HIP(hipMemcpyAsync(blk_d, blk_h, sizeof(int) * (list.size() + 1), hipMemcpyHostToDevice, g.st));
-        SKO_HIP(hipMemset2DAsync(small0 + st_off + 16 * sizeof(int), L.bytes, 0, sizeof(unsigned), nsys, g.st));
+        SKO_HIP(launch_zero_2d(small0 + st_off + 16 * sizeof(int), L.bytes, sizeof(unsigned), nsys, g.st));
         SKO_HIP(hipStreamSynchronize(g.st));
         c->tickets = 0;
         return SKO_OK;

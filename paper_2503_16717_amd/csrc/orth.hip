@@ -271,9 +271,9 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     e.status = ar.at<int>(L.status);
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
     double* Rfull = ar.at<double>(L.rfull);
-    SKO_HIP(hipMemsetAsync(e.status, 0, 256, c->stream));
+    SKO_HIP(launch_zero(e.status, 256, c->stream));
     c->tickets = 0;
-    SKO_HIP(hipMemsetAsync(Rfull, 0, sizeof(double) * (size_t)N * N, c->stream));
+    SKO_HIP(launch_zero(Rfull, sizeof(double) * (size_t)N * N, c->stream));
     BlockBufs bb = carve(c, L, N - w, k, w);
     for (int j = 0; j < nb; ++j) {
         const int p = j * w;
@@ -321,7 +321,7 @@ sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const voi
     e.status = ar.at<int>(L.status);
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
     double* Rcol = ar.at<double>(L.rfull);  // (p + w) x w, ld p + w
-    SKO_HIP(hipMemsetAsync(e.status, 0, 256, c->stream));
+    SKO_HIP(launch_zero(e.status, 256, c->stream));
     c->tickets = 0;
     BlockBufs bb = carve(c, L, p, k, w);
     s = one_stage_block(e, bb, o->intra, p, Q, ldq, V, ldv, Qo, ldqo, Rcol, N, 0);
@@ -356,7 +356,7 @@ sko_status sketch_apply_impl(sko_ctx c, int64_t n, int32_t w, const void* X, int
     e.gmax = L.gmax;
     e.status = ar.at<int>(L.status);
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
-    SKO_HIP(hipMemsetAsync(e.status, 0, 256, c->stream));
+    SKO_HIP(launch_zero(e.status, 256, c->stream));
     c->tickets = 0;
     BlockBufs bb = carve(c, L, 0, k, w);
     const bool sparse = sk->kind == SKO_SKETCH_SPARSE_SIGN;
@@ -435,9 +435,9 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     double* Rt = ar.at<double>(o_Rt);
     double* Rpk = ar.at<double>(o_Rpk);  // packed copy of Rh, then of Rt, for the row solves
     double* Rfull = ar.at<double>(o_Rf);
-    SKO_HIP(hipMemsetAsync(e.status, 0, 256, c->stream));
+    SKO_HIP(launch_zero(e.status, 256, c->stream));
     c->tickets = 0;
-    SKO_HIP(hipMemsetAsync(Rfull, 0, sizeof(double) * (size_t)N * N, c->stream));
+    SKO_HIP(launch_zero(Rfull, sizeof(double) * (size_t)N * N, c->stream));
 
     const int red_sk = o->sketch.kind == SKO_SKETCH_SPARSE_SIGN ? RED_SKETCH_SPARSE : RED_SKETCH_DENSE;
     const double sk_scale =
@@ -447,7 +447,7 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     for (int big = 0; big < nb / ppb; ++big) {
         const int p_old = big * Wb;
         void* Qb = offset_elems(Q, (int64_t)p_old * ldq, f32);
-        SKO_HIP(hipMemsetAsync(Rbar, 0, sizeof(double) * (size_t)Wb * Wb, c->stream));
+        SKO_HIP(launch_zero(Rbar, sizeof(double) * (size_t)Wb * Wb, c->stream));
         // ---- first stage: pre-process panel by panel (Fig. 5 Lines 10, 12; Fig. 8)
         for (int i = 0; i < ppb; ++i) {
             const int col = p_old + i * w;

@@ -1,5 +1,9 @@
 // Dispatch and launch of the row-strip pass kernels (kernel template in pass_impl.h,
 // instantiated per panel width in pass_wNN.hip).
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "pass_impl.h"
 
 namespace sko {
@@ -38,11 +42,21 @@ int pass_strip_rows(const PassKey& key) { return select_kernel(key).threads; }
 
 const void* pass_kernel_id(const PassKey& key) { return reinterpret_cast<const void*>(select_kernel(key).fn); }
 
+// Resident workgroups of a pass kernel, queried once per (kernel, device): the occupancy
+// query costs more than a launch.
 int pass_grid_cap(const PassKey& key) {
     PassSel s = select_kernel(key);
     if (!s.fn) return 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
+    const std::pair<const void*, int> id{reinterpret_cast<const void*>(s.fn), dev};
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        const auto it = cache.find(id);
+        if (it != cache.end()) return it->second;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     int per_cu = 0;
@@ -50,6 +64,8 @@ int pass_grid_cap(const PassKey& key) {
         hipSuccess)
         return 0;
     if (per_cu < 1) per_cu = 1;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[id] = per_cu * cus;
     return per_cu * cus;
 }
 

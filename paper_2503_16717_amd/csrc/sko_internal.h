@@ -187,6 +187,14 @@ hipError_t launch_wide_rowop(int64_t n, int W, bool f32, const void* Y, int64_t 
                              const double* Rpk, void* X, int64_t ldx, hipStream_t stream,
                              const BatchReloc* br = nullptr);
 
+// Zero `rows` runs of `width` bytes, consecutive runs `pitch` bytes apart (pointer, pitch
+// and width multiples of 4 bytes).  A kernel rather than hipMemsetAsync, so the work is an
+// ordinary kernel node wherever a caller captures the stream into a graph.
+hipError_t launch_zero_2d(void* p, size_t pitch, size_t width, size_t rows, hipStream_t stream);
+inline hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
+    return launch_zero_2d(p, bytes, bytes, 1, stream);
+}
+
 // Small matrix helpers on the device (single workgroup).
 hipError_t launch_small_matmul_upper(int w, const double* A, const double* B, double* C,
                                      hipStream_t stream);

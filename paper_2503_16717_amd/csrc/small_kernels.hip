@@ -516,6 +516,14 @@ __global__ void __launch_bounds__(RT) small_step_kernel_batched(const SmallArgs 
     small_step(m);
 }
 
+__global__ void zero_words_kernel(uint32_t* base, int64_t pitch_words, int64_t width_words, int64_t total) {
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step) {
+        const int64_t r = i / width_words;
+        base[r * pitch_words + (i - r * width_words)] = 0u;
+    }
+}
+
 __global__ void matmul_upper_kernel(int w, const double* A, const double* B, double* C) {
     for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
         const int a = idx % w, c = idx / w;
@@ -574,6 +582,17 @@ unsigned take_tickets(unsigned& tickets, int count, const BatchReloc* br) {
     const unsigned t0 = tickets;
     if (!br) tickets += (unsigned)reduce_grid(count);
     return t0;
+}
+
+hipError_t launch_zero_2d(void* p, size_t pitch, size_t width, size_t rows, hipStream_t stream) {
+    if (rows == 0 || width == 0) return hipSuccess;
+    if (!p || (reinterpret_cast<uintptr_t>(p) & 3) || (pitch & 3) || (width & 3) || width > pitch)
+        return hipErrorInvalidValue;
+    const int64_t ww = (int64_t)(width / 4), total = ww * (int64_t)rows;
+    const int64_t grid = std::min<int64_t>((total + 255) / 256, 1024);
+    hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)grid), dim3(256), 0, stream, static_cast<uint32_t*>(p),
+                       (int64_t)(pitch / 4), ww, total);
+    return hipGetLastError();
 }
 
 hipError_t launch_small_matmul_upper(int w, const double* A, const double* B, double* C, hipStream_t stream) {
