@@ -41,7 +41,8 @@ typedef enum {
     SKO_ENOMEM = 3,        /* device workspace could not be allocated */
     SKO_EBREAKDOWN = 4,    /* non-positive / non-finite Cholesky pivot or zero Householder diagonal */
     SKO_ENOCONV = 5,       /* GMRES reached maxiter without meeting the tolerance */
-    SKO_EUNSUPPORTED = 6   /* valid request outside what this build implements */
+    SKO_EUNSUPPORTED = 6,  /* valid request outside what this build implements */
+    SKO_ESCRATCH = 7       /* sko_orth_block_noalloc: the request needs more than the fixed scratch */
 } sko_status;
 
 typedef enum { SKO_F64 = 0, SKO_MIXED_F32 = 1 } sko_precision;
@@ -171,6 +172,30 @@ sko_status sko_orth_block(sko_ctx ctx, int64_t n, int32_t p, int32_t w,
                           const void* Q, int64_t ldq, const void* V, int64_t ldv,
                           void* Q_out, int64_t ldqo, double* R_proj, double* R_diag,
                           const sko_orth_opts* opts, int32_t* breakdown_col);
+
+/*
+ * sko_orth_block without allocating: for callers that cannot allocate device or pinned
+ * memory while they run (work recorded for a graph replay, tight serving loops, harnesses
+ * that forbid allocation).  Arguments, results and errors are those of sko_orth_block; the
+ * kernels and the order of every partial sum are the same, so on the same context the
+ * outputs are the same.  The call allocates nothing: the reductions' partial sums, the
+ * small factors and the status words live in a fixed device scratch of
+ * SKO_NOALLOC_SCRATCH_BYTES (32 MiB) that the library holds on every device it runs on
+ * until the process ends (its device address is looked up by sko_create); R is copied
+ * straight into the caller's host arrays, and the context's kernel profiler does not see
+ * these launches.  Needed scratch: 8 * G * ceil(max(p, k, w) * w / 32) * 32 bytes of
+ * partial sums, G = min(ceil(n / 256), 8 * compute units), plus about 8 * (2 p w + k w +
+ * (p + w)^2 + 5 w^2) bytes; a request above 32 MiB returns SKO_ESCRATCH (2^24 rows with
+ * w = 6, k = 64 and p <= 66 need 7 MB).
+ * Every call on a device shares that device's scratch, and the status words are cleared at
+ * the start of each call: calls that overlap on one device (from any context or thread)
+ * race and give wrong results.
+ */
+#define SKO_NOALLOC_SCRATCH_BYTES (32u << 20)
+sko_status sko_orth_block_noalloc(sko_ctx ctx, int64_t n, int32_t p, int32_t w,
+                                  const void* Q, int64_t ldq, const void* V, int64_t ldv,
+                                  void* Q_out, int64_t ldqo, double* R_proj, double* R_diag,
+                                  const sko_orth_opts* opts, int32_t* breakdown_col);
 
 /*
  * Orthogonalise all nb blocks of width w of V (n x nb*w) in order: one-stage BCGS2

@@ -14,13 +14,14 @@ import numpy as np
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsko.so")
 
-SKO_OK, SKO_EINVAL, SKO_EDEVICE, SKO_ENOMEM, SKO_EBREAKDOWN, SKO_ENOCONV, SKO_EUNSUPPORTED = range(7)
+SKO_OK, SKO_EINVAL, SKO_EDEVICE, SKO_ENOMEM, SKO_EBREAKDOWN, SKO_ENOCONV, SKO_EUNSUPPORTED, SKO_ESCRATCH = range(8)
+SKO_NOALLOC_SCRATCH_BYTES = 32 << 20
 SKO_F64, SKO_MIXED_F32 = 0, 1
 SKO_SKETCH_GAUSSIAN, SKO_SKETCH_SPARSE_SIGN = 0, 1
 SKO_INTRA_CHOLQR2, SKO_INTRA_RANDCHOLQR = 0, 1
 
 EXPORTED = ["sko_create", "sko_destroy", "sko_set_stream", "sko_strerror", "sko_orth_block",
-            "sko_orth_blocks", "sko_sketch_apply", "sko_gmres", "sko_gmres_batched", "sko_autotune_orth",
+            "sko_orth_block_noalloc", "sko_orth_blocks", "sko_sketch_apply", "sko_gmres", "sko_gmres_batched", "sko_autotune_orth",
             "sko_profile_enable", "sko_profile_read"]
 
 
@@ -70,6 +71,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     lib.sko_strerror.restype = C.c_char_p
     lib.sko_orth_block.argtypes = [vp, i64, i32, i32, vp, i64, vp, i64, vp, i64, dp, dp,
                                    C.POINTER(sko_orth_opts), C.POINTER(i32)]
+    lib.sko_orth_block_noalloc.argtypes = lib.sko_orth_block.argtypes
     lib.sko_orth_blocks.argtypes = [vp, i64, i32, i32, vp, i64, vp, i64, dp, i64,
                                     C.POINTER(sko_orth_opts), C.POINTER(i32)]
     lib.sko_sketch_apply.argtypes = [vp, i64, i32, vp, i64, i32, C.POINTER(sko_sketch), dp, i64]
@@ -226,6 +228,14 @@ class Context:
                                  C.byref(opts), C.byref(col))
         return st, col.value
 
+    def sko_orth_block_noalloc(self, n, p, w, Q_ptr, ldq, V_ptr, ldv, Qo_ptr, ldqo, Rp, Rd, opts):
+        col = C.c_int32(0)
+        rpp = Rp.ctypes.data_as(C.POINTER(C.c_double)) if Rp is not None else None
+        rdp = Rd.ctypes.data_as(C.POINTER(C.c_double)) if Rd is not None else None
+        st = _lib.sko_orth_block_noalloc(self.h, n, p, w, Q_ptr, ldq, V_ptr, ldv, Qo_ptr, ldqo, rpp, rdp,
+                                         C.byref(opts), C.byref(col))
+        return st, col.value
+
     def sko_gmres(self, A: sko_csr, b_ptr, x_ptr, opts: sko_gmres_opts):
         info = sko_gmres_info()
         st = _lib.sko_gmres(self.h, C.byref(A), b_ptr, x_ptr, C.byref(opts), C.byref(info))
@@ -283,13 +293,17 @@ class Context:
             raise SkoError(st, "sko_orth_blocks", col)
         return Q, Rh, st, col
 
-    def orth_block(self, Qprev, V, Qout=None, raise_on_error: bool = True, **opt_kw):
-        """One BCGS2 block step.  Returns (Qout, R_proj, R_diag, status, col)."""
+    def orth_block(self, Qprev, V, Qout=None, raise_on_error: bool = True, noalloc: bool = False, **opt_kw):
+        """One BCGS2 block step (noalloc: through sko_orth_block_noalloc; Qout must then be
+        given, since the binding would otherwise allocate it).  Returns (Qout, R_proj, R_diag,
+        status, col)."""
         import torch
         dt = _storage_dtype(opt_kw.get("precision", "f64"))
         n, w = V.shape
         p = 0 if Qprev is None else Qprev.shape[1]
         if Qout is None:
+            if noalloc:
+                raise ValueError("orth_block(noalloc=True) needs Qout")
             Qout = torch.empty((w, n), dtype=dt, device=V.device).t()
         vp, ldv = _colmajor(V, "V", dt, self.device)
         op, ldo = _colmajor(Qout, "Qout", dt, self.device)
@@ -300,9 +314,10 @@ class Context:
         Rp = np.zeros((p, w), order="F") if p > 0 else None
         Rd = np.zeros((w, w), order="F")
         opts = orth_opts(**opt_kw)
-        st, col = self.sko_orth_block(n, p, w, qp, ldq, vp, ldv, op, ldo, Rp, Rd, opts)
+        call = self.sko_orth_block_noalloc if noalloc else self.sko_orth_block
+        st, col = call(n, p, w, qp, ldq, vp, ldv, op, ldo, Rp, Rd, opts)
         if raise_on_error and st not in (SKO_OK, SKO_EBREAKDOWN):
-            raise SkoError(st, "sko_orth_block", col)
+            raise SkoError(st, "sko_orth_block_noalloc" if noalloc else "sko_orth_block", col)
         return Qout, Rp, Rd, st, col
 
     def sko_sketch_apply(self, n, w, X_ptr, ldx, precision: int, sketch: sko_sketch, Y: np.ndarray, ldy):

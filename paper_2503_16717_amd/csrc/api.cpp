@@ -30,6 +30,13 @@ sko_status sko_create(int device, void* hip_stream, sko_ctx* out) {
         delete c;
         return SKO_ENOMEM;
     }
+    // device address of this device's fixed scratch (sko_orth_block_noalloc), once per device
+    const sko_status ns = sko::noalloc_init(device);
+    if (ns != SKO_OK) {
+        (void)hipHostFree(c->status_host);
+        delete c;
+        return ns;
+    }
     *out = c;
     return SKO_OK;
 }
@@ -61,6 +68,7 @@ const char* sko_strerror(sko_status s) {
         case SKO_EBREAKDOWN: return "breakdown: non-positive Cholesky pivot or zero Householder diagonal";
         case SKO_ENOCONV: return "GMRES did not converge within maxiter";
         case SKO_EUNSUPPORTED: return "unsupported configuration";
+        case SKO_ESCRATCH: return "request needs more device memory than the fixed no-allocation scratch holds";
     }
     return "unknown status";
 }
@@ -71,6 +79,15 @@ sko_status sko_orth_block(sko_ctx c, int64_t n, int32_t p, int32_t w, const void
     if (!c) return SKO_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;
     return sko::orth_block_impl(c, n, p, w, Q, ldq, V, ldv, Q_out, ldqo, R_proj, R_diag, opts, breakdown_col);
+}
+
+sko_status sko_orth_block_noalloc(sko_ctx c, int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq,
+                                  const void* V, int64_t ldv, void* Q_out, int64_t ldqo, double* R_proj,
+                                  double* R_diag, const sko_orth_opts* opts, int32_t* breakdown_col) {
+    if (!c) return SKO_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return SKO_EDEVICE;
+    return sko::orth_block_noalloc_impl(c, n, p, w, Q, ldq, V, ldv, Q_out, ldqo, R_proj, R_diag, opts,
+                                        breakdown_col);
 }
 
 sko_status sko_orth_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const void* V, int64_t ldv, void* Q,

@@ -185,10 +185,13 @@ struct sko_ctx_s {
 
 namespace sko {
 
-// Bump allocator over the context workspace (256-byte aligned slices).
+// Bump allocator over the context workspace, or over a fixed buffer (256-byte aligned
+// slices).  Offsets are resolved against the context's workspace at use, so an arena may
+// be laid out before the workspace has grown.
 class Arena {
    public:
     explicit Arena(sko_ctx c) : c_(c) {}
+    Arena(sko_ctx c, void* fixed) : c_(c), fixed_(fixed) {}
     size_t reserve(size_t bytes) {
         size_t off = (used_ + 255) & ~size_t(255);
         used_ = off + bytes;
@@ -197,11 +200,12 @@ class Arena {
     size_t used() const { return used_; }
     template <typename T>
     T* at(size_t off) const {
-        return reinterpret_cast<T*>(static_cast<char*>(c_->ws) + off);
+        return reinterpret_cast<T*>(static_cast<char*>(fixed_ ? fixed_ : c_->ws) + off);
     }
 
    private:
     sko_ctx c_;
+    void* fixed_ = nullptr;
     size_t used_ = 0;
 };
 
@@ -251,6 +255,15 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
 sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq,
                            const void* V, int64_t ldv, void* Qo, int64_t ldqo, double* Rp, double* Rd,
                            const sko_orth_opts* o, int32_t* breakdown_col);
+sko_status orth_block_noalloc_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq,
+                                   const void* V, int64_t ldv, void* Qo, int64_t ldqo, double* Rp, double* Rd,
+                                   const sko_orth_opts* o, int32_t* breakdown_col);
+// Fixed no-allocation scratch of a device (noalloc.hip): noalloc_init once per device with
+// that device current, at context creation; noalloc_scratch returns the device address
+// (null before a successful noalloc_init).
+constexpr size_t kNoallocScratchBytes = size_t(32) << 20;
+sko_status noalloc_init(int device);
+void* noalloc_scratch(int device);
 sko_status sketch_apply_impl(sko_ctx c, int64_t n, int32_t w, const void* X, int64_t ldx, int32_t precision,
                              const sko_sketch* sk, double* Y, int64_t ldy);
 sko_status autotune_orth_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const sko_orth_opts* o);

@@ -211,8 +211,7 @@ OneStageLayout layout_one_stage(sko_ctx c, int64_t n, int W, int pmax, int k, in
     return L;
 }
 
-BlockBufs carve(sko_ctx c, const OneStageLayout& L, int pmax, int k, int W) {
-    Arena ar(c);
+BlockBufs carve(const Arena& ar, const OneStageLayout& L, int pmax, int k, int W) {
     double* base = ar.at<double>(L.small);
     const int64_t cw = std::max<int64_t>(1, (int64_t)pmax * W);
     BlockBufs b{};
@@ -274,7 +273,7 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     SKO_HIP(launch_zero(e.status, 256, c->stream));
     c->tickets = 0;
     SKO_HIP(launch_zero(Rfull, sizeof(double) * (size_t)N * N, c->stream));
-    BlockBufs bb = carve(c, L, N - w, k, w);
+    BlockBufs bb = carve(ar, L, N - w, k, w);
     for (int j = 0; j < nb; ++j) {
         const int p = j * w;
         const void* Vj = offset_elems(V, (int64_t)p * ldv, f32);
@@ -294,10 +293,10 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     return s;
 }
 
-sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq, const void* V,
-                           int64_t ldv, void* Qo, int64_t ldqo, double* Rp, double* Rd, const sko_orth_opts* o,
-                           int32_t* breakdown_col) {
-    if (breakdown_col) *breakdown_col = 0;
+namespace {
+
+sko_status orth_block_check(int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq, const void* V, int64_t ldv,
+                            const void* Qo, int64_t ldqo, const sko_orth_opts* o) {
     if (!o || !V || !Qo || n < 1 || p < 0 || w < 1 || w > kMaxPassW || ldv < n || ldqo < n) return SKO_EINVAL;
     if (p > 0 && (!Q || ldq < n)) return SKO_EINVAL;
     if (o->two_stage) return SKO_EINVAL;
@@ -307,14 +306,16 @@ sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const voi
     if (rand && (!sketch_ok(o->sketch, n) || o->sketch.k < w)) return SKO_EINVAL;
     if ((int64_t)p * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
     if (w > pass_rows_per_launch(w, RED_GRAM)) return SKO_EUNSUPPORTED;
-    const bool f32 = o->precision == SKO_MIXED_F32;
+    return SKO_OK;
+}
+
+// The block step on the workspace of arena `ar` laid out as L; leaves the assembled
+// [R_proj; R_diag] ((p + w) x w, leading dimension p + w) at *Rcol_out on the device.
+sko_status orth_block_run(sko_ctx c, const Arena& ar, const OneStageLayout& L, Engine& e, int64_t n, int32_t p,
+                          int32_t w, const void* Q, int64_t ldq, const void* V, int64_t ldv, void* Qo, int64_t ldqo,
+                          const sko_orth_opts* o, double** Rcol_out) {
+    const bool rand = o->intra == SKO_INTRA_RANDCHOLQR;
     const int k = rand ? o->sketch.k : w;
-    const int N = p + w;
-    OneStageLayout L = layout_one_stage(c, n, w, p, k, N);
-    sko_status s = ensure_workspace(c, L.total);
-    if (s) return s;
-    Arena ar(c);
-    Engine e(c, n, w, f32, o->sketch);
     e.partials = ar.at<double>(L.partials);
     e.part_stride = L.part_stride;
     e.gmax = L.gmax;
@@ -322,10 +323,29 @@ sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const voi
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
     double* Rcol = ar.at<double>(L.rfull);  // (p + w) x w, ld p + w
     SKO_HIP(launch_zero(e.status, 256, c->stream));
-    c->tickets = 0;
-    BlockBufs bb = carve(c, L, p, k, w);
-    s = one_stage_block(e, bb, o->intra, p, Q, ldq, V, ldv, Qo, ldqo, Rcol, N, 0);
+    *e.tickets = 0;
+    BlockBufs bb = carve(ar, L, p, k, w);
+    *Rcol_out = Rcol;
+    return one_stage_block(e, bb, o->intra, p, Q, ldq, V, ldv, Qo, ldqo, Rcol, p + w, 0);
+}
+
+}  // namespace
+
+sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq, const void* V,
+                           int64_t ldv, void* Qo, int64_t ldqo, double* Rp, double* Rd, const sko_orth_opts* o,
+                           int32_t* breakdown_col) {
+    if (breakdown_col) *breakdown_col = 0;
+    sko_status s = orth_block_check(n, p, w, Q, ldq, V, ldv, Qo, ldqo, o);
     if (s) return s;
+    const bool f32 = o->precision == SKO_MIXED_F32;
+    const int k = o->intra == SKO_INTRA_RANDCHOLQR ? o->sketch.k : w;
+    const int N = p + w;
+    OneStageLayout L = layout_one_stage(c, n, w, p, k, N);
+    if ((s = ensure_workspace(c, L.total))) return s;
+    Arena ar(c);
+    Engine e(c, n, w, f32, o->sketch);
+    double* Rcol = nullptr;
+    if ((s = orth_block_run(c, ar, L, e, n, p, w, Q, ldq, V, ldv, Qo, ldqo, o, &Rcol))) return s;
     if ((s = ensure_pinned(c, sizeof(double) * (size_t)N * w))) return s;
     double* Rh = static_cast<double*>(c->pinned);
     SKO_HIP(hipMemcpyAsync(Rh, Rcol, sizeof(double) * (size_t)N * w, hipMemcpyDeviceToHost, c->stream));
@@ -335,6 +355,42 @@ sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const voi
         if (Rd) std::memcpy(Rd + (int64_t)jc * w, Rh + (int64_t)jc * N + p, sizeof(double) * w);
     }
     return s;
+}
+
+// The same block step on the device's fixed scratch (noalloc.hip) instead of the context's
+// workspace: no device or pinned allocation, no profiler bookkeeping; R goes straight into
+// the caller's host arrays.
+sko_status orth_block_noalloc_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const void* Q, int64_t ldq,
+                                   const void* V, int64_t ldv, void* Qo, int64_t ldqo, double* Rp, double* Rd,
+                                   const sko_orth_opts* o, int32_t* breakdown_col) {
+    if (breakdown_col) *breakdown_col = 0;
+    sko_status s = orth_block_check(n, p, w, Q, ldq, V, ldv, Qo, ldqo, o);
+    if (s) return s;
+    void* scratch = noalloc_scratch(c->device);
+    if (!scratch) return SKO_EDEVICE;
+    const bool f32 = o->precision == SKO_MIXED_F32;
+    const int k = o->intra == SKO_INTRA_RANDCHOLQR ? o->sketch.k : w;
+    const int N = p + w;
+    OneStageLayout L = layout_one_stage(c, n, w, p, k, N);
+    if (L.total > kNoallocScratchBytes) return SKO_ESCRATCH;
+    Arena ar(c, scratch);
+    Engine e(c, n, w, f32, o->sketch);
+    unsigned tickets = 0;
+    e.tickets = &tickets;
+    e.profile = false;
+    double* Rcol = nullptr;
+    if ((s = orth_block_run(c, ar, L, e, n, p, w, Q, ldq, V, ldv, Qo, ldqo, o, &Rcol))) return s;
+    if (Rp && p > 0)
+        SKO_HIP(hipMemcpy2DAsync(Rp, sizeof(double) * p, Rcol, sizeof(double) * N, sizeof(double) * p, w,
+                                 hipMemcpyDeviceToHost, c->stream));
+    if (Rd)
+        SKO_HIP(hipMemcpy2DAsync(Rd, sizeof(double) * w, Rcol + p, sizeof(double) * N, sizeof(double) * w, w,
+                                 hipMemcpyDeviceToHost, c->stream));
+    SKO_HIP(hipMemcpyAsync(c->status_host, e.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    SKO_HIP(hipStreamSynchronize(c->stream));
+    const int col = *c->status_host;
+    if (breakdown_col) *breakdown_col = col;
+    return col ? SKO_EBREAKDOWN : SKO_OK;
 }
 
 // Y = Theta^T X (Section 3), the reduction of the update + sketch pass on its own: the same
@@ -358,7 +414,7 @@ sko_status sketch_apply_impl(sko_ctx c, int64_t n, int32_t w, const void* X, int
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
     SKO_HIP(launch_zero(e.status, 256, c->stream));
     c->tickets = 0;
-    BlockBufs bb = carve(c, L, 0, k, w);
+    BlockBufs bb = carve(ar, L, 0, k, w);
     const bool sparse = sk->kind == SKO_SKETCH_SPARSE_SIGN;
     PassArgs a{};
     a.Y = X;
