@@ -46,8 +46,28 @@ def alg_bytes_one_stage(n: int, nb: int, w: int, eb: int = 8) -> float:
     return float(cols) * n * eb
 
 
+def alg_bytes_two_stage_method(n: int, nb: int, w: int, ppb: int, eb: int = 8) -> float:
+    """Tall traffic the two-stage method needs (each operand once per pass, the big-panel
+    close fused like the one-stage passes): per panel the projection and update + sketch
+    against Q_old (p + w, p + 2w; a sketch of w without previous big panels) and the
+    forward substitution ((i + 2) w for panel i); per big panel with previous columns the
+    close Gram (W), solve + write + projection (2W + p), update + write + Gram (2W + p) and
+    solve + write (2W); the first big panel's two CholQR passes pairs (6W).  193.3 GB at
+    n = 2^24, 12 blocks of 6, s_hat = 30."""
+    Wb = ppb * w
+    cols = 0
+    for big in range(nb // ppb):
+        p = big * Wb
+        for i in range(ppb):
+            cols += (p + w) + (p + 2 * w) if p > 0 else w
+            cols += (i + 2) * w
+        cols += (Wb + (2 * Wb + p) + (2 * Wb + p) + 2 * Wb) if p > 0 else 6 * Wb
+    return float(cols) * n * eb
+
+
 def alg_bytes_two_stage(n: int, nb: int, w: int, ppb: int, eb: int = 8) -> float:
-    """Pass schedule of the two-stage scheme (each tall operand once per pass)."""
+    """Pass schedule the library executes for the two-stage scheme (each tall operand once
+    per pass; the big-panel close runs unfused)."""
     Wb = ppb * w
     cols = 0
     for big in range(nb // ppb):
@@ -313,7 +333,9 @@ def measured_traffic(kernel: str):
 
 
 def cpu_baseline(n_sample: int):
-    """The FP64 oracle, untuned, on the first n_sample rows' worth of the same recipe."""
+    """The FP64 oracle, untuned, on the first n_sample rows' worth of the same recipe, with the
+    host's BLAS thread pool and with one thread."""
+    import numpy as np
     from oracle import orth
     from oracle.sketch import Sketch
     from paper_2503_16717_amd import workloads as wl
@@ -323,14 +345,30 @@ def cpu_baseline(n_sample: int):
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
+    sk = Sketch.sparse_sign(SK_K, SK_ZETA, SK_SEED)
     t0 = time.perf_counter()
-    r = orth.orth_blocks_one_stage(V, W, "randcholqr", Sketch.sparse_sign(SK_K, SK_ZETA, SK_SEED))
+    r = orth.orth_blocks_one_stage(V, W, "randcholqr", sk)
     dt = time.perf_counter() - t0
     assert r.info == 0
     gbs = alg_bytes_one_stage(n_sample, NB, W) / dt / 1e9
-    return {"value": round(gbs, 4), "unit": "GB/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"one-stage RandCholQR-BCGS2, {n_sample} rows (1/{N_ROWS // n_sample} of n) x 12 blocks "
-                      f"x 6 columns, same generator, {dt:.1f} s"}
+    out = {"value": round(gbs, 4), "unit": "GB/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"one-stage RandCholQR-BCGS2, {n_sample} rows (1/{N_ROWS // n_sample} of n) x 12 blocks "
+                     f"x 6 columns, same generator, {dt:.1f} s"}
+    # the same oracle on one host thread (BLAS pool limited to 1), on an eighth of that sample
+    try:
+        from threadpoolctl import threadpool_limits
+        n1 = max(4096, n_sample // 8)
+        V1 = np.asfortranarray(V[:n1])
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            r1 = orth.orth_blocks_one_stage(V1, W, "randcholqr", sk)
+            dt1 = time.perf_counter() - t0
+        assert r1.info == 0
+        out["one_thread"] = {"value": round(alg_bytes_one_stage(n1, NB, W) / dt1 / 1e9, 4), "unit": "GB/s",
+                             "cores": 1, "sample": f"first {n1} rows of the same sample, {dt1:.1f} s"}
+    except ImportError:
+        pass
+    return out
 
 
 def main() -> int:
@@ -479,9 +517,12 @@ def main() -> int:
         torch.cuda.synchronize()
         ctx.sko_profile_enable(False)
         stats2 = ctx.sko_profile_read()
-        ab2 = alg_bytes_two_stage(n, NB, W, 6)
+        ab2 = alg_bytes_two_stage_method(n, NB, W, 6)
+        ex2 = alg_bytes_two_stage(n, NB, W, 6)
         extra["two_stage"] = {"ms_per_step": round(ms2, 4), "GBps": round(ab2 / (ms2 * 1e-3) / 1e9, 2),
-                              "alg_bytes_per_step": ab2, "s_hat": 30, "big_panel_width": 36,
+                              "pct_hbm_peak": round(100 * ab2 / (ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+                              "alg_bytes_per_step": ab2, "executed_schedule_bytes_per_step": ex2,
+                              "s_hat": 30, "big_panel_width": 36,
                               "kernels_top": [{"name": q["name"], "ms_per_step": round(q["total_ms"] / args.steps, 4),
                                                "launches_per_step": q["launches"] / args.steps,
                                                "GBps": round(q["bytes"] / (q["total_ms"] * 1e-3) / 1e9, 1)

@@ -199,7 +199,8 @@ sko_status sko_orth_block_noalloc(sko_ctx ctx, int64_t n, int32_t p, int32_t w,
 
 /*
  * Orthogonalise all nb blocks of width w of V (n x nb*w) in order: one-stage BCGS2
- * per block, or two-stage over big panels of panels_per_big blocks.  Result: Q
+ * per block (Fig. 2c), or two-stage over big panels of panels_per_big blocks (Fig. 6,
+ * the flat form of Fig. 5, with the RandBCGS2 pre-processing of Fig. 8).  Result: Q
  * (n x nb*w, may alias V) and the HOST upper-triangular R (N x N, N = nb*w, leading
  * dimension ldr >= N; may be NULL) with V = Q R.  w <= 16; two-stage big panels are at
  * most 64 columns wide.  On SKO_EBREAKDOWN *breakdown_col is the 1-based column.
