@@ -5,6 +5,10 @@ Theta^T X; the Gaussian choice is Theta = G / sqrt(k) with G standard normal.
 Section 5.2 (Count sketch): one +-1 per row of Theta, applied as a sparse
 product.  The sparse-sign sketch here generalises that to zeta nonzeros per row
 of Theta, each +-1/sqrt(zeta); zeta = 1 is the paper's Count sketch.
+Section 5.2 (Count-Gaussian sketch): a Count sketch to O(s^2) rows followed by
+a Gaussian sketch to O(s) rows, Theta = Theta_c Theta_g, applied as
+Theta_g^T (Theta_c^T X) (Theta_c: kc columns, Theta_g: kc x k Gaussian with
+N(0, 1/k) entries, drawn by the input generator).
 
 Nonzero placement (the reading used for the unspecified hash, shared with the
 GPU side only as this written definition):
@@ -89,12 +93,15 @@ def sparse_sign_dense(n: int, k: int, zeta: int, seed: int) -> np.ndarray:
 
 
 class Sketch:
-    """Description of Theta: ``kind`` is 'gaussian' (explicit n x k array) or 'sparse_sign'."""
+    """Description of Theta: ``kind`` is 'gaussian' (explicit n x k array), 'sparse_sign',
+    or 'count_gauss' (sparse-sign Theta_c with kc columns times the kc x k array theta)."""
 
-    def __init__(self, kind: str, k: int, zeta: int = 1, seed: int = 0, theta: np.ndarray | None = None):
-        if kind not in ("gaussian", "sparse_sign", "dense"):
+    def __init__(self, kind: str, k: int, zeta: int = 1, seed: int = 0, theta: np.ndarray | None = None,
+                 kc: int = 0):
+        if kind not in ("gaussian", "sparse_sign", "dense", "count_gauss"):
             raise ValueError(kind)
         self.kind, self.k, self.zeta, self.seed, self.theta = kind, int(k), int(zeta), int(seed), theta
+        self.kc = int(kc)
 
     @staticmethod
     def gaussian(theta: np.ndarray) -> "Sketch":
@@ -103,6 +110,15 @@ class Sketch:
     @staticmethod
     def sparse_sign(k: int, zeta: int, seed: int) -> "Sketch":
         return Sketch("sparse_sign", k, zeta, seed)
+
+    @staticmethod
+    def count_gauss(kc: int, zeta: int, seed: int, theta_g: np.ndarray) -> "Sketch":
+        """Count-Gaussian composite (Section 5.2): sparse-sign (kc rows, zeta nonzeros per row
+        of Theta_c, stream ``seed``) followed by the Gaussian factor theta_g (kc x k)."""
+        theta_g = np.asarray(theta_g, dtype=np.float64)
+        if theta_g.shape[0] != kc:
+            raise ValueError("the Gaussian factor must have kc rows")
+        return Sketch("count_gauss", theta_g.shape[1], zeta, seed, theta=theta_g, kc=kc)
 
     @staticmethod
     def dense(theta: np.ndarray) -> "Sketch":
@@ -123,11 +139,19 @@ def apply_sketch(sk: Sketch, X: np.ndarray) -> np.ndarray:
         if sk.theta.shape[0] != n:
             raise ValueError("theta has the wrong number of rows")
         return sk.theta.T @ X
-    slots, signs = sparse_sign_pattern(np.arange(n), sk.k, sk.zeta, sk.seed)
-    scale = 1.0 / math.sqrt(sk.zeta)
-    Y = np.zeros((sk.k, w))
-    for t in range(sk.zeta):
+    if sk.kind == "count_gauss":
+        # the Count part first, then the Gaussian factor on its kc x w result
+        return sk.theta.T @ _apply_sparse_sign(sk.kc, sk.zeta, sk.seed, X)
+    return _apply_sparse_sign(sk.k, sk.zeta, sk.seed, X)
+
+
+def _apply_sparse_sign(k: int, zeta: int, seed: int, X: np.ndarray) -> np.ndarray:
+    n, w = X.shape
+    slots, signs = sparse_sign_pattern(np.arange(n), k, zeta, seed)
+    scale = 1.0 / math.sqrt(zeta)
+    Y = np.zeros((k, w))
+    for t in range(zeta):
         coef = signs[:, t] * scale
         for c in range(w):
-            Y[:, c] += np.bincount(slots[:, t], weights=coef * X[:, c], minlength=sk.k)
+            Y[:, c] += np.bincount(slots[:, t], weights=coef * X[:, c], minlength=k)
     return Y

@@ -74,6 +74,28 @@ def test_gaussian_sketch_scheme():
     assert metrics.orth_error(Q)[0] <= 1e-14
 
 
+@pytest.mark.parametrize("two_stage", [False, True])
+def test_count_gauss_sketch_schemes(two_stage):
+    """Count-Gaussian sketch (Section 5.2) in RandCholQR and in the two-stage pre-processing:
+    the same unique R and O(eps) orthogonality at kappa = 1e12.  Sizes as in the paper's
+    setup: Count to 2 s^2 rows per panel, Gaussian to 2 (s + 1); two-stage, 2 s_hat^2 capped
+    at a 128-row Count part (one nonzero per row) and Gaussian to 2 (s_hat + 1)."""
+    n, nb, w, e = 3000, 6, 6, 12
+    V = wl.glued_blocks(n, nb, w, e)
+    if two_stage:
+        kc, k = 128, 2 * 18 + 2
+        sk = Sketch.count_gauss(kc, 1, 3, wl.gaussian_theta(kc, k, 1))
+        Q, R, info = orth.orth_blocks_two_stage(V, w, 3, sk)
+    else:
+        kc, k = 2 * 25, 2 * 6
+        sk = Sketch.count_gauss(kc, 1, 3, wl.gaussian_theta(kc, k, 1))
+        Q, R, info = orth.orth_blocks_one_stage(V, w, "randcholqr", sk)
+    assert info == 0
+    assert metrics.rel_diff(R, lapack_R(V)) <= r_tol(e)
+    assert metrics.orth_error(Q)[0] <= 1e-14
+    assert metrics.backward_error(V, Q, R) <= 1e-15
+
+
 def test_cholqr2_regimes_fig9():
     """Fig. 9 caption: CholQR breaks down (non-positive pivot) for kappa(V) >= 1e8; below
     eps^-1/2 CholQR2 keeps O(eps) orthogonality.  Tests stay far from the threshold."""

@@ -74,7 +74,30 @@ def test_apply_equals_dense_product(kind):
     assert np.max(np.abs(Y - Yb)) <= 1e-13 * np.max(np.abs(Yb))
 
 
-@pytest.mark.parametrize("kind,k,zeta", [("sparse_sign", 64, 8), ("gaussian", 24, 0), ("sparse_sign", 48, 8)])
+def test_count_gauss_is_the_composite_product():
+    """Section 5.2: the Count-Gaussian sketch is Theta = Theta_c Theta_g (n x kc times kc x k),
+    applied as Theta_g^T (Theta_c^T X).  Brute force from the materialised n x k product; kc != k
+    and w != k, so a transposed or swapped factor cannot even be multiplied."""
+    n, kc, k, w = 500, 50, 12, 6
+    X = np.random.default_rng(1).standard_normal((n, w))
+    tg = np.random.default_rng(2).standard_normal((kc, k)) / math.sqrt(k)
+    sk = osk.Sketch.count_gauss(kc, 1, 9, tg)
+    theta = osk.sparse_sign_dense(n, kc, 1, 9) @ tg
+    Y = sk.apply(X)
+    Yb = np.array([[math.fsum(theta[:, h] * X[:, c]) for c in range(w)] for h in range(k)])
+    assert Y.shape == (k, w)
+    assert np.max(np.abs(Y - Yb)) <= 1e-13 * np.max(np.abs(Yb))
+
+
+def test_count_gauss_with_identity_factor_is_the_count_sketch():
+    n, kc, w = 2000, 48, 5
+    X = np.random.default_rng(3).standard_normal((n, w))
+    Y = osk.Sketch.count_gauss(kc, 8, 4, np.eye(kc)).apply(X)
+    assert np.array_equal(Y, osk.Sketch.sparse_sign(kc, 8, 4).apply(X))
+
+
+@pytest.mark.parametrize("kind,k,zeta", [("sparse_sign", 64, 8), ("gaussian", 24, 0), ("sparse_sign", 48, 8),
+                                         ("count_gauss", 24, 1)])
 def test_subspace_embedding(kind, k, zeta):
     """Def. 3.1 / Cor. 3.2-3.3: for orthonormal Q the singular values of Theta^T Q lie in
     [sqrt(1-mu), sqrt(1+mu)].  Section 3 sizes the sketch as k ~ d / mu^2 (a rule of thumb,
@@ -87,9 +110,15 @@ def test_subspace_embedding(kind, k, zeta):
         Q, _ = np.linalg.qr(np.random.default_rng(100 + seed).standard_normal((n, d)))
         if kind == "gaussian":
             sk = osk.Sketch.gaussian(np.random.default_rng(seed).standard_normal((n, k)) / math.sqrt(k))
+        elif kind == "count_gauss":
+            # Section 5.2 sizes: Count to O(d^2) rows (2 d^2 = 72), then Gaussian to O(d) rows
+            tg = np.random.default_rng(seed).standard_normal((2 * d * d, k)) / math.sqrt(k)
+            sk = osk.Sketch.count_gauss(2 * d * d, 1, seed, tg)
         else:
             sk = osk.Sketch.sparse_sign(k, zeta, seed)
         sv = np.linalg.svd(sk.apply(Q), compute_uv=False)
         mus.append(max(1.0 - sv[-1] ** 2, sv[0] ** 2 - 1.0))
         assert 1.0 - sv[-1] ** 2 < 1.0 and sv[0] / sv[-1] < 5.0
-    assert np.median(mus) < 0.85
+    # two embeddings compose: (1 +- mu_c)(1 +- mu_g), so the composite's typical distortion is
+    # allowed the sum of the parts' (about 0.4 for the Count part at 72 rows)
+    assert np.median(mus) < (1.0 if kind == "count_gauss" else 0.85)
