@@ -46,7 +46,7 @@ typedef enum {
 } sko_status;
 
 typedef enum { SKO_F64 = 0, SKO_MIXED_F32 = 1 } sko_precision;
-typedef enum { SKO_SKETCH_GAUSSIAN = 0, SKO_SKETCH_SPARSE_SIGN = 1 } sko_sketch_kind;
+typedef enum { SKO_SKETCH_GAUSSIAN = 0, SKO_SKETCH_SPARSE_SIGN = 1, SKO_SKETCH_COUNT_GAUSS = 2 } sko_sketch_kind;
 typedef enum { SKO_INTRA_CHOLQR2 = 0, SKO_INTRA_RANDCHOLQR = 1 } sko_intra;
 
 /*
@@ -60,14 +60,20 @@ typedef enum { SKO_INTRA_CHOLQR2 = 0, SKO_INTRA_RANDCHOLQR = 1 } sko_intra;
  *    sits in slot block [tB, (t+1)B); its byte b is bits [8t, 8t+8) of the 64-bit
  *    output number i+1 of a SplitMix64 stream started at state `seed` (Steele, Lea,
  *    Flood 2014); sign = -1 iff (b & 1), slot = tB + ((b >> 1) * B >> 7).
+ *  SKO_SKETCH_COUNT_GAUSS: the Count-Gaussian composite of Section 5.2, Theta =
+ *    Theta_c Theta_g: a sparse-sign sketch Theta_c with k_count rows (zeta, seed and
+ *    placement as above; zeta = 1 is the Count sketch), applied by the tall passes, then the
+ *    caller's Gaussian factor Theta_g (DEVICE, k_count x k column-major, leading dimension
+ *    ld_theta >= k_count; the caller draws it, N(0, 1/k)) applied to the reduced k_count x w
+ *    sketch.  Requires k <= k_count <= 256 and the sparse-sign conditions on k_count.
  */
 typedef struct {
     int32_t kind;          /* sko_sketch_kind */
     int32_t k;             /* sketch rows, 1..256 */
-    int32_t zeta;          /* nonzeros per row of Theta (sparse-sign) */
-    int32_t reserved_;
+    int32_t zeta;          /* nonzeros per row of Theta (sparse-sign), of Theta_c (Count-Gauss) */
+    int32_t k_count;       /* Count-Gauss: rows of the sparse-sign part; ignored otherwise */
     uint64_t seed;         /* sparse-sign stream seed */
-    const double* theta;   /* Gaussian: device n x k, column-major */
+    const double* theta;   /* Gaussian: device n x k; Count-Gauss: device k_count x k; column-major */
     int64_t ld_theta;
 } sko_sketch;
 

@@ -17,7 +17,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsko.so"
 SKO_OK, SKO_EINVAL, SKO_EDEVICE, SKO_ENOMEM, SKO_EBREAKDOWN, SKO_ENOCONV, SKO_EUNSUPPORTED, SKO_ESCRATCH = range(8)
 SKO_NOALLOC_SCRATCH_BYTES = 32 << 20
 SKO_F64, SKO_MIXED_F32 = 0, 1
-SKO_SKETCH_GAUSSIAN, SKO_SKETCH_SPARSE_SIGN = 0, 1
+SKO_SKETCH_GAUSSIAN, SKO_SKETCH_SPARSE_SIGN, SKO_SKETCH_COUNT_GAUSS = 0, 1, 2
 SKO_INTRA_CHOLQR2, SKO_INTRA_RANDCHOLQR = 0, 1
 
 EXPORTED = ["sko_create", "sko_destroy", "sko_set_stream", "sko_strerror", "sko_orth_block",
@@ -26,7 +26,7 @@ EXPORTED = ["sko_create", "sko_destroy", "sko_set_stream", "sko_strerror", "sko_
 
 
 class sko_sketch(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("k", C.c_int32), ("zeta", C.c_int32), ("reserved_", C.c_int32),
+    _fields_ = [("kind", C.c_int32), ("k", C.c_int32), ("zeta", C.c_int32), ("k_count", C.c_int32),
                 ("seed", C.c_uint64), ("theta", C.c_void_p), ("ld_theta", C.c_int64)]
 
 
@@ -144,7 +144,10 @@ def _colmajor(t, name, dtype=None, device_index=None):
 
 
 def make_sketch(kind: str = "sparse_sign", k: int = 64, zeta: int = 8, seed: int = 0, theta=None) -> sko_sketch:
-    """theta: column-major (n x k) float64 device tensor for the Gaussian sketch."""
+    """theta: column-major float64 device tensor, (n x k) for the Gaussian sketch, (k_count x k)
+    (the Gaussian factor) for the Count-Gauss composite, whose Count part has k_count =
+    theta.shape[0] rows, zeta nonzeros per row and stream seed `seed` (k is then theta.shape[1]).
+    The caller keeps theta alive while the sketch is in use."""
     sk = sko_sketch()
     if kind == "sparse_sign":
         sk.kind, sk.k, sk.zeta, sk.seed = SKO_SKETCH_SPARSE_SIGN, k, zeta, seed
@@ -152,6 +155,11 @@ def make_sketch(kind: str = "sparse_sign", k: int = 64, zeta: int = 8, seed: int
         import torch
         ptr, ld = _colmajor(theta, "theta", torch.float64)
         sk.kind, sk.k, sk.zeta, sk.seed, sk.theta, sk.ld_theta = SKO_SKETCH_GAUSSIAN, theta.shape[1], 0, 0, ptr, ld
+    elif kind == "count_gauss":
+        import torch
+        ptr, ld = _colmajor(theta, "theta", torch.float64)
+        sk.kind, sk.k, sk.k_count, sk.zeta, sk.seed = SKO_SKETCH_COUNT_GAUSS, theta.shape[1], theta.shape[0], zeta, seed
+        sk.theta, sk.ld_theta = ptr, ld
     else:
         raise ValueError(kind)
     return sk

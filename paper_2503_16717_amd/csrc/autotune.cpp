@@ -60,7 +60,8 @@ sko_status autotune_orth_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const
     const bool f32 = o->precision == SKO_MIXED_F32;
     const bool rand = o->two_stage || o->intra == SKO_INTRA_RANDCHOLQR;
     if (rand && !sketch_ok(o->sketch, n)) return SKO_EINVAL;
-    const int red_sk = o->sketch.kind == SKO_SKETCH_SPARSE_SIGN ? RED_SKETCH_SPARSE : RED_SKETCH_DENSE;
+    const SketchPlan sp = sketch_plan(o->sketch);
+    const int red_sk = sp.red;
     const int cus = std::max(1, c->cus);
     const int64_t nstrips = (n + kPassThreads - 1) / kPassThreads;
     if (nstrips < 4 * (int64_t)cus) return SKO_OK;  // too few strips for the grid to matter
@@ -69,13 +70,13 @@ sko_status autotune_orth_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const
     std::vector<Use> uses;
     if (!o->two_stage) {
         const int red_first = rand ? red_sk : RED_GRAM;
-        const int rows_first = rand ? o->sketch.k : w;
+        const int rows_first = rand ? sp.rows : w;
         for (int j = 0; j < nb; ++j) one_stage_uses(w, f32, red_first, rows_first, j * w, uses);
     } else {
         const int ppb = std::max(1, o->panels_per_big);
         for (int j = 0; j < nb; ++j) {
             const int big = j / ppb, i = j % ppb;
-            two_stage_uses(w, f32, red_sk, o->sketch.k, big * ppb * w, i * w, uses);
+            two_stage_uses(w, f32, red_sk, sp.rows, big * ppb * w, i * w, uses);
         }
     }
     std::map<const void*, std::vector<Use>> groups;
@@ -144,12 +145,12 @@ sko_status autotune_orth_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const
         a.ldx = n;
         a.Qp = Q;
         a.ldqp = n;
-        a.theta = o->sketch.theta;
+        a.theta = sp.red == RED_SKETCH_DENSE ? o->sketch.theta : nullptr;
         a.ldtheta = o->sketch.ld_theta;
         a.partials = partials;
         a.part_stride = part_stride;
         a.sk_seed = o->sketch.seed;
-        a.sk_k = o->sketch.k;
+        a.sk_k = sp.rows;
         a.sk_zeta = o->sketch.zeta;
         if (u.key.red != RED_NONE) {
             a.red_rows = std::min(u.rows, pass_rows_per_launch(w, u.key.red));

@@ -44,11 +44,13 @@ struct Engine {
     unsigned* tickets;
     // false: no profiler events (no host-side bookkeeping at all) for this engine's launches
     bool profile = true;
+    int sk_rows;  // sketch rows the passes produce (k_count for a Count-Gauss sketch)
 
     Engine(sko_ctx c_, int64_t n_, int W_, bool f32_, const sko_sketch& sk_)
         : c(c_), st(c_->stream), n(n_), W(W_), f32(f32_), sk(sk_), tickets(&c_->tickets) {
         nstrips = (n + kPassThreads - 1) / kPassThreads;
         rows_bytes = (double)n;
+        sk_rows = sketch_plan(sk).rows;
     }
 
     // Profiler bracket of one launch; the kernel-kind name is built only while profiling.
@@ -97,7 +99,7 @@ struct Engine {
         a.part_stride = part_stride;
         a.part_rows_total = rows_total;
         a.n = n;
-        a.sk_k = sk.k;
+        a.sk_k = sk_rows;
         a.sk_zeta = sk.zeta;
         a.sk_seed = sk.seed;
         for (int r0 = 0; r0 < rows_total; r0 += rpl) {

@@ -70,12 +70,13 @@ struct SmallLayout {
     size_t bb, gm, ts, st, bytes;
 };
 
-SmallLayout small_layout(int m, int W, int k, int Wb, bool two) {
+// kr: sketch rows the passes reduce; k: rows of the (final) sketch.
+SmallLayout small_layout(int m, int W, int kr, int k, int Wb, bool two) {
     auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
     const size_t mW = (size_t)m * W;
     SmallLayout L{};
     L.bb = 0;
-    L.gm = up(L.bb + sizeof(double) * (2 * mW + (size_t)std::max(k, W) * W + 5 * (size_t)W * W));
+    L.gm = up(L.bb + sizeof(double) * (2 * mW + (size_t)std::max(kr, W) * W + 5 * (size_t)W * W));
     L.ts = up(L.gm + sizeof(double) * (3 * (size_t)(m + 1) * m + 3 * (size_t)(m + 1) + 8 + (size_t)(m + 1) * W));
     L.st = up(L.ts + (two ? sizeof(double) * (mW + (size_t)k * Wb + (size_t)Wb * W + (size_t)W * W +
                                               3 * (size_t)Wb * Wb + (size_t)m * Wb + (size_t)Wb * (Wb + 1) / 2)
@@ -85,14 +86,14 @@ SmallLayout small_layout(int m, int W, int k, int Wb, bool two) {
 }
 
 // Point g's small buffers into the block at `base`.
-void carve_small(GmCtx& g, char* base, const SmallLayout& L, int k) {
+void carve_small(GmCtx& g, char* base, const SmallLayout& L, int kr, int k) {
     const int m = g.m, W = g.W;
     const int64_t mW = (int64_t)m * W;
     double* p = reinterpret_cast<double*>(base + L.bb);
     g.bb.C1 = p;
     g.bb.C2 = p + mW;
     g.bb.Ysk = g.bb.C2 + mW;
-    g.bb.G2 = g.bb.Ysk + (int64_t)std::max(k, W) * W;
+    g.bb.G2 = g.bb.Ysk + (int64_t)std::max(kr, W) * W;
     g.bb.G3 = g.bb.G2 + W * W;
     g.bb.R1 = g.bb.G3 + W * W;
     g.bb.R2 = g.bb.R1 + W * W;
@@ -243,8 +244,9 @@ sko_status cycle_one_stage(GmCtx& g, Engine& e, double bnorm, double tol, sko_gm
 sko_status two_stage_panel(GmCtx& g, Engine& e, int k0, int i) {
     sko_status s;
     const int S = g.s, W = g.W, ld = (int)g.m + 1;
-    const int red_sk = g.sk.kind == SKO_SKETCH_SPARSE_SIGN ? RED_SKETCH_SPARSE : RED_SKETCH_DENSE;
-    const double sk_scale = g.sk.kind == SKO_SKETCH_SPARSE_SIGN ? 1.0 / std::sqrt((double)g.sk.zeta) : 1.0;
+    const SketchPlan sp = sketch_plan(g.sk);
+    const int red_sk = sp.red;
+    const double sk_scale = sp.scale;
     void* Qb = col_ptr(g, k0);
     const int loc = i * S, kk = k0 + loc;
     // the panel V: in the basis itself, or (mixed precision) in the FP64 panel buffer
@@ -281,7 +283,8 @@ sko_status two_stage_panel(GmCtx& g, Engine& e, int k0, int i) {
     SmallArgs sm{};
     sm.op = OP_SKETCH_BCGS2;
     sm.w = W;
-    sm.k = g.sk.k;
+    sm.k = sp.k;
+    sketch_small(sm, sp);
     sm.col0 = kk;
     sm.out = g.bb.Ysk;
     sm.R = g.rho;
@@ -291,7 +294,7 @@ sko_status two_stage_panel(GmCtx& g, Engine& e, int k0, int i) {
     sm.Rbar = g.coef + k0;
     sm.ldrbar = ld;
     sm.rbar_col0 = 0;
-    if ((s = e.reduction(key, a, g.sk.k, V, g.ld, nullptr, 0, sm, sk_scale))) return s;
+    if ((s = e.reduction(key, a, sp.rows, V, g.ld, nullptr, 0, sm, sk_scale))) return s;
     PassArgs fa{};
     fa.Y = V;
     fa.ldy = g.ld;
@@ -435,9 +438,10 @@ sko_status check_opts(const sko_csr* A, const sko_gmres_opts* o, GmCtx& g) {
     return SKO_OK;
 }
 
-int sketch_rows(const GmCtx& g) {
+// Rows of the sketch (final = false: the rows the passes reduce, k_count for Count-Gauss).
+int sketch_rows(const GmCtx& g, bool final = true) {
     const bool need_sketch = g.two || g.intra == SKO_INTRA_RANDCHOLQR;
-    return need_sketch ? g.sk.k : g.W;
+    return need_sketch ? (final ? g.sk.k : sketch_plan(g.sk).rows) : g.W;
 }
 
 }  // namespace
@@ -454,7 +458,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     g.c = c;
     g.st = c->stream;
     const int eb = g.f32 ? 4 : 8;
-    const int k = sketch_rows(g);
+    const int k = sketch_rows(g), kr = sketch_rows(g, false);
 
     // ---- workspace
     Arena ar(c);
@@ -466,13 +470,13 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     const size_t o_dinv = g.jacobi ? ar.reserve(sizeof(double) * A->n) : 0;
     const int64_t nstrips = (A->n + kPassThreads - 1) / kPassThreads;
     const int gmax = (int)std::min<int64_t>(nstrips, (int64_t)std::max(1, c->cus) * 8);
-    const int64_t rows = std::max({(int64_t)m, (int64_t)k, (int64_t)g.W});
+    const int64_t rows = std::max({(int64_t)m, (int64_t)kr, (int64_t)g.W});
     const int64_t part_stride = ((rows * g.W + 31) / 32) * 32;
     g.grid_cap = std::max(1, c->cus) * 8;
     const size_t part_doubles = std::max({(size_t)part_stride * gmax, (size_t)64 * 64 * std::max(1, skinny_gemm_grid_cap()),
                                           (size_t)g.grid_cap});
     const size_t o_part = ar.reserve(sizeof(double) * part_doubles);
-    const SmallLayout L = small_layout(m, g.W, k, g.Wb, g.two);
+    const SmallLayout L = small_layout(m, g.W, kr, k, g.Wb, g.two);
     const size_t o_small = ar.reserve(L.bytes);
     sko_status s = ensure_workspace(c, ar.used());
     if (s) return s;
@@ -481,7 +485,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     g.Q = ar.at<void>(o_Q);
     g.P = panel64 ? ar.at<double>(o_P) : nullptr;
     g.dinv = g.jacobi ? ar.at<double>(o_dinv) : nullptr;
-    carve_small(g, ar.at<char>(o_small), L, k);
+    carve_small(g, ar.at<char>(o_small), L, kr, k);
 
     EventPair ev_total;
     SKO_HIP(ev_total.create());
@@ -654,7 +658,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     if (infos)
         for (int32_t i = 0; i < nsys; ++i) infos[i] = sko_gmres_info{};
     // lock step needs the two-stage scheme with the hashed sketch (no per-system Theta)
-    if (nsys == 1 || !o->two_stage || o->sketch.kind != SKO_SKETCH_SPARSE_SIGN)
+    if (nsys == 1 || !o->two_stage || o->sketch.kind == SKO_SKETCH_GAUSSIAN)
         return gmres_sequential(c, nsys, A, b, x, o, infos);
 
     GmCtx g{};
@@ -670,7 +674,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     g.c = c;
     g.st = c->stream;
     const int eb = g.f32 ? 4 : 8;
-    const int k = sketch_rows(g);
+    const int k = sketch_rows(g), kr = sketch_rows(g, false);
     const bool own_vals = g.jacobi || g.f32;
     int64_t max_n = 0;
     double nnz_sum = 0.0, n_sum = 0.0;
@@ -685,7 +689,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     const int cap = std::max(1, c->cus) * 8;
     const int64_t strips_max = (max_n + kPassThreads - 1) / kPassThreads;
     const int Gp = (int)std::max<int64_t>(1, std::min<int64_t>((strips_max + 7) / 8, cap));
-    const int64_t rows = std::max({(int64_t)m, (int64_t)k, (int64_t)g.W});
+    const int64_t rows = std::max({(int64_t)m, (int64_t)kr, (int64_t)g.W});
     const int64_t part_stride = ((rows * g.W + 31) / 32) * 32;
     const int64_t ns32 = (max_n + 31) / 32;
     const int Gg = (int)std::max<int64_t>(1, std::min<int64_t>((ns32 + 63) / 64, skinny_gemm_grid_cap()));
@@ -694,7 +698,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     const int Gr = (int)std::max<int64_t>(1, std::min<int64_t>((groups8 + 15) / 16, cap));
     const size_t part_doubles = std::max({(size_t)part_stride * Gp, (size_t)gemm_cells * Gg, (size_t)Gr});
     const size_t part_bytes = ((sizeof(double) * part_doubles + 255) / 256) * 256;
-    const SmallLayout L = small_layout(m, g.W, k, g.Wb, g.two);
+    const SmallLayout L = small_layout(m, g.W, kr, k, g.Wb, g.two);
 
     // ---- workspace: per-system basis / operator values / D^{-1}, then the equal-sized small
     // blocks, partial sums, the system table and the active list
@@ -737,7 +741,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     g.ld = ((A[0].n + 63) / 64) * 64;
     g.n = A[0].n;
     g.Q = ar.at<void>(o_Q[0]);
-    carve_small(g, small_of(0), L, k);
+    carve_small(g, small_of(0), L, kr, k);
     g.grid_cap = cap;
     g.avg_nnz = nnz_sum / std::max(1.0, n_sum);
     g.max_n = max_n;
@@ -807,7 +811,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
         }
         GmCtx gi = g;
         gi.n = A[i].n;
-        carve_small(gi, small_of(i), L, k);
+        carve_small(gi, small_of(i), L, kr, k);
         Engine e1(c, A[i].n, 1, false, g.sk);
         e1.partials = part_of(i);
         e1.part_stride = part_stride;

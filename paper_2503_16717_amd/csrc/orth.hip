@@ -37,11 +37,10 @@ sko_status one_stage_block(Engine& e, const BlockBufs& b, int intra, int p, cons
     const int W = e.W;
     const bool f32 = e.f32;
     const bool rand = intra == SKO_INTRA_RANDCHOLQR;
-    const int red_first = rand ? (e.sk.kind == SKO_SKETCH_SPARSE_SIGN ? RED_SKETCH_SPARSE : RED_SKETCH_DENSE)
-                               : RED_GRAM;
-    const int rows_first = rand ? e.sk.k : W;
-    const double sk_scale =
-        (rand && e.sk.kind == SKO_SKETCH_SPARSE_SIGN) ? 1.0 / std::sqrt((double)e.sk.zeta) : 1.0;
+    const SketchPlan sp = sketch_plan(e.sk);
+    const int red_first = rand ? sp.red : RED_GRAM;
+    const int rows_first = rand ? sp.rows : W;
+    const double sk_scale = rand ? sp.scale : 1.0;
     sko_status s;
 
     // P1: C1 = Q^T V
@@ -78,10 +77,11 @@ sko_status one_stage_block(Engine& e, const BlockBufs& b, int intra, int p, cons
         SmallArgs sm{};
         sm.op = rand ? OP_HH : OP_CHOL;
         sm.w = W;
-        sm.k = rows_first;
+        sm.k = rand ? sp.k : W;
         sm.col0 = col0;
         sm.out = b.Ysk;
         sm.R = b.R1;
+        if (rand) sketch_small(sm, sp);
         if ((s = e.reduction(key, a, rows_first, Vh, ldvh, nullptr, 0, sm, sk_scale))) return s;
     }
     // P3: G2 = (Vh R1^{-1})^T (Vh R1^{-1})
@@ -178,12 +178,34 @@ sko_status one_stage_block(Engine& e, const BlockBufs& b, int intra, int p, cons
 
 bool sketch_ok(const sko_sketch& sk, int64_t n) {
     if (sk.k < 1 || sk.k > 256) return false;
-    if (sk.kind == SKO_SKETCH_SPARSE_SIGN) {
-        if (sk.zeta < 1 || sk.zeta > 8 || sk.k % sk.zeta != 0 || sk.k / sk.zeta > 128) return false;
-        return true;
-    }
+    auto hashed_ok = [&](int rows) {
+        return sk.zeta >= 1 && sk.zeta <= 8 && rows % sk.zeta == 0 && rows / sk.zeta <= 128;
+    };
+    if (sk.kind == SKO_SKETCH_SPARSE_SIGN) return hashed_ok(sk.k);
     if (sk.kind == SKO_SKETCH_GAUSSIAN) return sk.theta != nullptr && sk.ld_theta >= n;
+    if (sk.kind == SKO_SKETCH_COUNT_GAUSS)
+        return sk.k_count >= sk.k && sk.k_count <= 256 && hashed_ok(sk.k_count) && sk.theta != nullptr &&
+               sk.ld_theta >= sk.k_count;
     return false;
+}
+
+SketchPlan sketch_plan(const sko_sketch& sk) {
+    SketchPlan p{};
+    p.k = sk.k;
+    p.rows = sk.k;
+    if (sk.kind == SKO_SKETCH_GAUSSIAN) {
+        p.red = RED_SKETCH_DENSE;
+        p.scale = 1.0;
+        return p;
+    }
+    p.red = RED_SKETCH_SPARSE;
+    p.scale = sk.zeta > 0 ? 1.0 / std::sqrt((double)sk.zeta) : 1.0;
+    if (sk.kind == SKO_SKETCH_COUNT_GAUSS) {
+        p.rows = sk.k_count;
+        p.theta_g = sk.theta;
+        p.ld_g = sk.ld_theta;
+    }
+    return p;
 }
 
 namespace {
@@ -258,7 +280,7 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     if ((int64_t)(N - w) * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
 
     const bool f32 = o->precision == SKO_MIXED_F32;
-    const int k = rand ? o->sketch.k : w;
+    const int k = rand ? sketch_plan(o->sketch).rows : w;
     OneStageLayout L = layout_one_stage(c, n, w, N - w, k, N);
     sko_status s = ensure_workspace(c, L.total);
     if (s) return s;
@@ -315,7 +337,7 @@ sko_status orth_block_run(sko_ctx c, const Arena& ar, const OneStageLayout& L, E
                           int32_t w, const void* Q, int64_t ldq, const void* V, int64_t ldv, void* Qo, int64_t ldqo,
                           const sko_orth_opts* o, double** Rcol_out) {
     const bool rand = o->intra == SKO_INTRA_RANDCHOLQR;
-    const int k = rand ? o->sketch.k : w;
+    const int k = rand ? sketch_plan(o->sketch).rows : w;
     e.partials = ar.at<double>(L.partials);
     e.part_stride = L.part_stride;
     e.gmax = L.gmax;
@@ -338,7 +360,7 @@ sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const voi
     sko_status s = orth_block_check(n, p, w, Q, ldq, V, ldv, Qo, ldqo, o);
     if (s) return s;
     const bool f32 = o->precision == SKO_MIXED_F32;
-    const int k = o->intra == SKO_INTRA_RANDCHOLQR ? o->sketch.k : w;
+    const int k = o->intra == SKO_INTRA_RANDCHOLQR ? sketch_plan(o->sketch).rows : w;
     const int N = p + w;
     OneStageLayout L = layout_one_stage(c, n, w, p, k, N);
     if ((s = ensure_workspace(c, L.total))) return s;
@@ -369,7 +391,7 @@ sko_status orth_block_noalloc_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, c
     void* scratch = noalloc_scratch(c->device);
     if (!scratch) return SKO_EDEVICE;
     const bool f32 = o->precision == SKO_MIXED_F32;
-    const int k = o->intra == SKO_INTRA_RANDCHOLQR ? o->sketch.k : w;
+    const int k = o->intra == SKO_INTRA_RANDCHOLQR ? sketch_plan(o->sketch).rows : w;
     const int N = p + w;
     OneStageLayout L = layout_one_stage(c, n, w, p, k, N);
     if (L.total > kNoallocScratchBytes) return SKO_ESCRATCH;
@@ -401,8 +423,10 @@ sko_status sketch_apply_impl(sko_ctx c, int64_t n, int32_t w, const void* X, int
     if (precision != SKO_F64 && precision != SKO_MIXED_F32) return SKO_EINVAL;
     if (!sketch_ok(*sk, n) || ldy < sk->k) return SKO_EINVAL;
     const bool f32 = precision == SKO_MIXED_F32;
+    const SketchPlan sp = sketch_plan(*sk);
     const int k = sk->k;
-    OneStageLayout L = layout_one_stage(c, n, w, 0, k, w);
+    // the C1 region (sized for pmax = k rows) receives a Count-Gauss product
+    OneStageLayout L = layout_one_stage(c, n, w, k, sp.rows, w);
     sko_status s = ensure_workspace(c, L.total);
     if (s) return s;
     Arena ar(c);
@@ -414,22 +438,22 @@ sko_status sketch_apply_impl(sko_ctx c, int64_t n, int32_t w, const void* X, int
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
     SKO_HIP(launch_zero(e.status, 256, c->stream));
     c->tickets = 0;
-    BlockBufs bb = carve(ar, L, 0, k, w);
-    const bool sparse = sk->kind == SKO_SKETCH_SPARSE_SIGN;
+    BlockBufs bb = carve(ar, L, k, sp.rows, w);
     PassArgs a{};
     a.Y = X;
     a.ldy = ldx;
     SmallArgs sm{};
     sm.op = OP_STORE;
     sm.w = w;
+    sm.k = k;
     sm.out = bb.Ysk;
-    const double scale = sparse ? 1.0 / std::sqrt((double)sk->zeta) : 1.0;
-    if ((s = e.reduction({w, f32, sparse ? RED_SKETCH_SPARSE : RED_SKETCH_DENSE, false, 0, false}, a, k, X, ldx,
-                         nullptr, 0, sm, scale)))
-        return s;
+    sm.R = bb.C1;
+    sketch_small(sm, sp);
+    if ((s = e.reduction({w, f32, sp.red, false, 0, false}, a, sp.rows, X, ldx, nullptr, 0, sm, sp.scale))) return s;
+    const double* Ydev = sp.theta_g ? bb.C1 : bb.Ysk;
     if ((s = ensure_pinned(c, sizeof(double) * (size_t)k * w))) return s;
     double* Yh = static_cast<double*>(c->pinned);
-    SKO_HIP(hipMemcpyAsync(Yh, bb.Ysk, sizeof(double) * (size_t)k * w, hipMemcpyDeviceToHost, c->stream));
+    SKO_HIP(hipMemcpyAsync(Yh, Ydev, sizeof(double) * (size_t)k * w, hipMemcpyDeviceToHost, c->stream));
     if ((s = finish(c, e.status, nullptr))) return s;
     for (int jc = 0; jc < w; ++jc) std::memcpy(Y + (int64_t)jc * ldy, Yh + (int64_t)jc * k, sizeof(double) * k);
     return SKO_OK;
@@ -444,7 +468,9 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     if (o->sketch.k < Wb) return SKO_EINVAL;  // the big panel must embed into the sketch space
     const bool f32 = o->precision == SKO_MIXED_F32;
     const int N = nb * w;
-    const int k = o->sketch.k;
+    const SketchPlan sp = sketch_plan(o->sketch);
+    const int k = sp.k;        // rows of the accumulated sketches
+    const int kr = sp.rows;    // rows the passes reduce
     const int pmax = N - Wb;  // largest previous-basis width
     if ((int64_t)(Wb - w) * w > kMaxUpdCoef || (int64_t)pmax * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
 
@@ -452,7 +478,7 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     Arena ar(c);
     const int64_t nstrips = (n + kPassThreads - 1) / kPassThreads;
     const int gmax = (int)std::min<int64_t>(nstrips, (int64_t)std::max(1, c->cus) * 8);
-    const int64_t rows = std::max({(int64_t)pmax, (int64_t)k, (int64_t)w});
+    const int64_t rows = std::max({(int64_t)pmax, (int64_t)kr, (int64_t)w});
     const int64_t part_stride = ((rows * w + 31) / 32) * 32;
     const size_t part_doubles =
         std::max<size_t>((size_t)part_stride * gmax, (size_t)64 * 64 * std::max(1, skinny_gemm_grid_cap()));
@@ -460,7 +486,7 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     const int64_t pw = std::max<int64_t>(1, (int64_t)pmax * Wb);
     const size_t o_C = ar.reserve(sizeof(double) * pw);
     const size_t o_C2 = ar.reserve(sizeof(double) * pw);
-    const size_t o_Y = ar.reserve(sizeof(double) * (size_t)k * w);
+    const size_t o_Y = ar.reserve(sizeof(double) * (size_t)kr * w);
     const size_t o_Yacc = ar.reserve(sizeof(double) * (size_t)k * Wb);
     const size_t o_r = ar.reserve(sizeof(double) * (size_t)Wb * w);
     const size_t o_rho = ar.reserve(sizeof(double) * (size_t)w * w);
@@ -495,9 +521,8 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     c->tickets = 0;
     SKO_HIP(launch_zero(Rfull, sizeof(double) * (size_t)N * N, c->stream));
 
-    const int red_sk = o->sketch.kind == SKO_SKETCH_SPARSE_SIGN ? RED_SKETCH_SPARSE : RED_SKETCH_DENSE;
-    const double sk_scale =
-        o->sketch.kind == SKO_SKETCH_SPARSE_SIGN ? 1.0 / std::sqrt((double)o->sketch.zeta) : 1.0;
+    const int red_sk = sp.red;
+    const double sk_scale = sp.scale;
     const bool reorth = o->reorth != 0;
 
     for (int big = 0; big < nb / ppb; ++big) {
@@ -553,7 +578,8 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
                 sm.Rbar = Rbar;
                 sm.ldrbar = Wb;
                 sm.rbar_col0 = i * w;
-                if ((s = e.reduction(key, a, k, Vh, ldvh, nullptr, 0, sm, sk_scale))) return s;
+                sketch_small(sm, sp);
+                if ((s = e.reduction(key, a, kr, Vh, ldvh, nullptr, 0, sm, sk_scale))) return s;
             }
             {   // Q_bar_i = (V_hat_i - Q_bar_prev r) rho^{-1}
                 PassArgs a{};

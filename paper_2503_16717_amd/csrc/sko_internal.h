@@ -132,6 +132,12 @@ struct SmallArgs {
     int p;
     double* Rout;        // destination of [Rproj; Rdiag] columns in a big R (ld ldr)
     int64_t ldr;
+    // Count-Gauss sketch (theta_g != null): the reduced values in `out` are the kc x w Count
+    // part; the step first forms theta_g^T out (k x w, theta_g kc x k with leading dimension
+    // ld_g) and works on that.  OP_STORE then writes the k x w product to R (ld k).
+    const double* theta_g;
+    int64_t ld_g;
+    int kc;
 };
 
 struct ReduceArgs {
@@ -158,6 +164,25 @@ struct ReduceArgs {
 };
 // Rows per workgroup index of the wide Gram / projection kernel (16-row groups, 4 waves).
 constexpr int kGemmUnitRows = 64;
+
+// How a sketch is applied: the tall passes reduce `rows` sketch rows of kind `red` (the
+// hashed sparse-sign Theta, or the stored Gaussian Theta), scaled by `scale`; a Count-Gauss
+// sketch then multiplies the reduced rows by its Gaussian factor in the small step.
+struct SketchPlan {
+    int red;
+    int rows;      // rows the passes produce: k, or k_count for Count-Gauss
+    int k;         // rows of the final sketch
+    double scale;
+    const double* theta_g;
+    int64_t ld_g;
+};
+SketchPlan sketch_plan(const sko_sketch& sk);
+// Hand the Count-Gauss factor (if any) to a small step.
+inline void sketch_small(SmallArgs& sm, const SketchPlan& sp) {
+    sm.theta_g = sp.theta_g;
+    sm.ld_g = sp.ld_g;
+    sm.kc = sp.theta_g ? sp.rows : 0;
+}
 
 // Number of workgroups launch_reduce uses for `count` reduced values.
 int reduce_grid(int count);

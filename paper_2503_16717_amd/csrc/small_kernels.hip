@@ -348,15 +348,38 @@ __device__ void assemble(const SmallArgs& s, double* rh) {
     __syncthreads();
 }
 
+// Count-Gauss sketch (Section 5.2): Z = theta_g^T Yc (k x w), Yc the reduced kc x w Count
+// part in s.out (written by other workgroups, read coherently into T in LDS).  Each entry
+// sums over the kc rows in ascending order.
+__device__ void count_gauss_product(const SmallArgs& s, double* Z, double* T) {
+    const int tid = threadIdx.x;
+    const int k = s.k, w = s.w, kc = s.kc;
+    fill_from<true>(s.out, kc * w, [&](int i, double v) { T[i] = v; });
+    __syncthreads();
+    for (int idx = tid; idx < k * w; idx += RT) {
+        const int i = idx % k, c = idx / k;
+        const double* g = s.theta_g + (int64_t)i * s.ld_g;
+        double v = 0.0;
+        for (int t = 0; t < kc; ++t) v += g[t] * T[t + c * kc];
+        Z[idx] = v;
+    }
+    __syncthreads();
+}
+
 // Sketch-space BCGS2 with Householder (Fig. 8a): y (k x w) against Yacc[:, 0:nacc].
 // Ys: LDS copy of Yacc[:, 0:nacc] with leading dimension k + 1 (so lanes reading different
 // columns at one row index fall in different banks); the dot products then never wait on
 // global memory.
-__device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* Ys, double* red, double* scal) {
+// T: LDS scratch for the Count part of a Count-Gauss sketch (kc x w).
+__device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* Ys, double* T, double* red,
+                             double* scal) {
     const int tid = threadIdx.x;
     const int k = s.k, w = s.w, na = s.nacc;
     const int ldy = k + 1;
-    fill_from<true>(s.out, k * w, [&](int i, double v) { Z[i] = v; });
+    if (s.theta_g)
+        count_gauss_product(s, Z, T);
+    else
+        fill_from<true>(s.out, k * w, [&](int i, double v) { Z[i] = v; });
     fill_from<false>(s.Yacc, k * na, [&](int i, double v) { Ys[i % k + (i / k) * ldy] = v; });
     __syncthreads();
     if (na > 0) {
@@ -436,10 +459,19 @@ __device__ __forceinline__ void small_step(const SmallArgs& s) {
     __shared__ double red[4 * 16];
     __shared__ double scal[128];
     const int tid = threadIdx.x;
-    if (s.op == OP_HH) {
+    if (s.op == OP_STORE) {
+        if (!s.theta_g) return;
+        double* Z = lds;
+        count_gauss_product(s, Z, lds + s.k * s.w);
+        for (int idx = tid; idx < s.k * s.w; idx += RT) s.R[idx] = Z[idx];
+    } else if (s.op == OP_HH) {
         double* A = lds;
-        fill_from<true>(s.out, s.k * s.w, [&](int i, double v) { A[i] = v; });
-        __syncthreads();
+        if (s.theta_g) {
+            count_gauss_product(s, A, lds + s.k * s.w);
+        } else {
+            fill_from<true>(s.out, s.k * s.w, [&](int i, double v) { A[i] = v; });
+            __syncthreads();
+        }
         householder(A, s.k, s.w, nullptr, s.R, s.w, s.status, s.col0, red, scal);
     } else if (s.op == OP_CHOL) {
         double* G = lds;
@@ -455,7 +487,7 @@ __device__ __forceinline__ void small_step(const SmallArgs& s) {
         double* Z = lds;
         double* E = lds + s.k * s.w;
         double* Ys = E + (s.k * s.w > s.nacc * s.w ? s.k * s.w : s.nacc * s.w);
-        sketch_bcgs2(s, Z, E, Ys, red, scal);
+        sketch_bcgs2(s, Z, E, Ys, Ys + (s.k + 1) * s.nacc, red, scal);
     }
 }
 
@@ -541,16 +573,22 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream, const BatchRel
     if (a.count <= 0 || a.G <= 0) return hipErrorInvalidValue;
     const SmallArgs& s = a.small;
     size_t lds = 0;
+    if (s.theta_g) {
+        if (s.op != OP_STORE && s.op != OP_HH && s.op != OP_SKETCH_BCGS2) return hipErrorInvalidValue;
+        if (s.kc < s.k || s.kc > RT || s.k < 1 || s.w > 16 || s.ld_g < s.kc) return hipErrorInvalidValue;
+        lds = sizeof(double) * (size_t)s.kc * s.w;  // the Count part, staged before the product
+        if (s.op == OP_STORE) lds += sizeof(double) * (size_t)s.k * s.w;
+    }
     if (s.op == OP_HH) {
         if (s.k > RT || s.w > 16 || s.k < s.w) return hipErrorInvalidValue;
-        lds = sizeof(double) * (size_t)s.k * s.w;
+        lds += sizeof(double) * (size_t)s.k * s.w;
     } else if (s.op == OP_CHOL) {
         if (s.w > 64) return hipErrorInvalidValue;
         lds = sizeof(double) * (size_t)s.w * s.w;
     } else if (s.op == OP_SKETCH_BCGS2) {
         if (s.k > RT || s.w > 16 || s.k < s.w) return hipErrorInvalidValue;
         const size_t e = (size_t)s.k * s.w > (size_t)s.nacc * s.w ? (size_t)s.k * s.w : (size_t)s.nacc * s.w;
-        lds = sizeof(double) * ((size_t)s.k * s.w + e + (size_t)(s.k + 1) * s.nacc);
+        lds += sizeof(double) * ((size_t)s.k * s.w + e + (size_t)(s.k + 1) * s.nacc);
     }
     // dynamic LDS beyond 64 KiB needs the kernels' limit raised once (gfx950: 160 KiB per CU)
     constexpr size_t kMaxLds = 150 * 1024;
@@ -568,7 +606,7 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream, const BatchRel
     if (br) {
         if (br->nact < 1) return hipErrorInvalidValue;
         hipLaunchKernelGGL(reduce_kernel_batched, dim3(grid, br->nact), dim3(RT), 0, stream, a, *br);
-        if (s.op != OP_STORE) {
+        if (s.op != OP_STORE || s.theta_g) {
             if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
             hipLaunchKernelGGL(small_step_kernel_batched, dim3(1, br->nact), dim3(RT), lds, stream, s, *br);
         }
