@@ -14,6 +14,16 @@ follows that description in the paper's order and notation:
   first intra-block step is the RandBCGS2 pre-processing (Fig. 8: each panel is
   sketched, orthogonalised in sketch space by BCGS2 with Householder, and the
   full vectors follow by forward substitution), then CholQR of the big panel.
+  The deterministic alternative pre-processing is BCGS-PIP (Fig. 7, Section 7.1):
+  one reduction gives P = Q_bar_prev^T V and G = V^T V, the Pythagorean rule gives
+  the Gram matrix of the projected panel as G - P^T P, R = chol(G - P^T P) and
+  Q_bar = (V - Q_bar_prev P) R^{-1}.
+* Recursive CholQR (Fig. 3, Section 5.1): when the Cholesky factorisation of the
+  Gram matrix meets a non-positive pivot at column k, the first k-1 columns are
+  finished with the partial factor, the remaining columns are projected against
+  them with the partial factor's off-diagonal block (no new dot products), and
+  CholQR is applied recursively to the projected remainder (whose Gram matrix is
+  computed afresh).
 
 Breakdown follows Section 5.1 / Fig. 9: a Cholesky pivot that is not positive, or
 an exactly zero diagonal of the Householder R, stops the computation; the
@@ -55,6 +65,57 @@ def cholqr2(X: np.ndarray):
     return Q, R2 @ R1, 0
 
 
+def cholqr_recursive(X: np.ndarray):
+    """Fig. 3: recursive CholQR.  (Q, R, info); info > 0 only when a column is numerically
+    dependent on the ones before it (a failing pivot at the first column of a recursion)."""
+    n, w = X.shape
+    G = X.T @ X
+    R, info = cholesky_upper(G)
+    if info == 0:
+        return trsm_right_upper(X, R), R, 0
+    if info == 1:
+        return None, R, 1
+    m1 = info - 1
+    R11, R12 = R[:m1, :m1], R[:m1, m1:]   # rows finished before the failing pivot
+    Q1 = trsm_right_upper(X[:, :m1], R11)
+    X2 = X[:, m1:] - Q1 @ R12
+    Q2, R22, info2 = cholqr_recursive(X2)
+    if info2:
+        return None, R, m1 + info2
+    Rfull = np.zeros((w, w))
+    Rfull[:m1, :m1] = R11
+    Rfull[:m1, m1:] = R12
+    Rfull[m1:, m1:] = R22
+    return np.hstack([Q1, Q2]), Rfull, 0
+
+
+def cholqr2_recursive(X: np.ndarray):
+    """CholQR2 with the recursive CholQR of Fig. 3 in both passes; R = R_2 R_1."""
+    Q1, R1, info = cholqr_recursive(X)
+    if info:
+        return None, R1, info
+    Q, R2, info = cholqr_recursive(Q1)
+    if info:
+        return None, R2, info
+    return Q, R2 @ R1, 0
+
+
+def bcgs_pip_step(Qbar_prev: np.ndarray, V: np.ndarray):
+    """One BCGS-PIP step (Fig. 7): V against the columns Qbar_prev with one reduction.
+
+    Returns (Qbar, P, R, info) with V = Qbar_prev P + Qbar R.  With no previous columns
+    P is empty and the step is CholQR (Section 7.1 footnote)."""
+    p = Qbar_prev.shape[1]
+    P = Qbar_prev.T @ V
+    G = V.T @ V
+    S = G - P.T @ P if p > 0 else G
+    R, info = cholesky_upper(S)
+    if info:
+        return None, P, R, info
+    X = V - Qbar_prev @ P if p > 0 else V
+    return trsm_right_upper(X, R), P, R, 0
+
+
 def randhh(X: np.ndarray, sk: Sketch):
     """Fig. 4a: v = Theta^T X; R = HH(v) (diag >= 0); Q_bar = X R^{-1}."""
     v = sk.apply(X)
@@ -78,6 +139,8 @@ def randcholqr(X: np.ndarray, sk: Sketch):
 def first_intra(X: np.ndarray, intra: str, sk: Sketch | None):
     if intra == "cholqr2":
         return cholqr2(X)
+    if intra == "cholqr2_recursive":
+        return cholqr2_recursive(X)
     if intra == "randcholqr":
         return randcholqr(X, sk)
     raise ValueError(intra)
@@ -106,7 +169,8 @@ def bcgs2_block(Qp: np.ndarray, V: np.ndarray, intra: str = "randcholqr", sk: Sk
     else:
         C2 = np.zeros((0, w))
         Vb = Qh
-    Qj, Rb, info = cholqr(Vb)
+    # with the recursive CholQR2 first intra step, the final CholQR is recursive too
+    Qj, Rb, info = (cholqr_recursive if intra == "cholqr2_recursive" else cholqr)(Vb)
     if info:
         return None, None, Rb, info
     return Qj, C1 + C2 @ Rh, Rb @ Rh, 0
@@ -155,8 +219,11 @@ def sketch_bcgs2_hh(Yacc: np.ndarray, y: np.ndarray):
     return q, r, rho, info
 
 
-def orth_blocks_two_stage(V: np.ndarray, w: int, panels_per_big: int, sk: Sketch, reorth: bool = True):
-    """Two-stage block orthogonalisation without MPK (Fig. 6) with RandBCGS2 pre-processing.
+def orth_blocks_two_stage(V: np.ndarray, w: int, panels_per_big: int, sk: Sketch | None, reorth: bool = True,
+                          preproc: str = "randbcgs2"):
+    """Two-stage block orthogonalisation without MPK (Fig. 6) with RandBCGS2 pre-processing
+    (or, preproc="pip", BCGS-PIP pre-processing of each panel against the big panel's
+    previous pre-processed panels, Fig. 7; no sketch).
 
     Big panels of ``panels_per_big`` blocks of width w.  For each big panel with
     previous basis Q_old (n x p_old):
@@ -179,7 +246,7 @@ def orth_blocks_two_stage(V: np.ndarray, w: int, panels_per_big: int, sk: Sketch
         p_old = big * Wb
         Qold = Q[:, :p_old]
         Qbar = np.zeros((n, Wb))
-        Yacc = np.zeros((sk.k, 0))
+        Yacc = np.zeros((sk.k if sk is not None else 0, 0))
         Rbar = np.zeros((Wb, Wb))
         C = np.zeros((p_old, Wb))
         for i in range(panels_per_big):
@@ -191,6 +258,14 @@ def orth_blocks_two_stage(V: np.ndarray, w: int, panels_per_big: int, sk: Sketch
                 C[:, i * w:(i + 1) * w] = Ci
             else:
                 Vh = Vi
+            if preproc == "pip":
+                Qbi, r, rho, info = bcgs_pip_step(Qbar[:, :i * w], Vh)
+                if info:
+                    return OrthResult(Q, R, p_old + i * w + info)
+                Qbar[:, i * w:(i + 1) * w] = Qbi
+                Rbar[:i * w, i * w:(i + 1) * w] = r
+                Rbar[i * w:(i + 1) * w, i * w:(i + 1) * w] = rho
+                continue
             y = sk.apply(Vh)
             q, r, rho, info = sketch_bcgs2_hh(Yacc, y)
             if info:
