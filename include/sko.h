@@ -47,7 +47,8 @@ typedef enum {
 
 typedef enum { SKO_F64 = 0, SKO_MIXED_F32 = 1 } sko_precision;
 typedef enum { SKO_SKETCH_GAUSSIAN = 0, SKO_SKETCH_SPARSE_SIGN = 1, SKO_SKETCH_COUNT_GAUSS = 2 } sko_sketch_kind;
-typedef enum { SKO_INTRA_CHOLQR2 = 0, SKO_INTRA_RANDCHOLQR = 1 } sko_intra;
+typedef enum { SKO_INTRA_CHOLQR2 = 0, SKO_INTRA_RANDCHOLQR = 1, SKO_INTRA_CHOLQR2_RECURSIVE = 2 } sko_intra;
+typedef enum { SKO_PREPROC_RANDBCGS2 = 0, SKO_PREPROC_PIP = 1 } sko_preproc;
 
 /*
  * Random sketch Theta (n x k), applied as Theta^T X (Section 3).
@@ -79,9 +80,22 @@ typedef struct {
 
 /*
  * Orthogonalisation options.
- *  intra            first intra-block step of one-stage BCGS2 (Section 5).
- *  two_stage        0: one-stage BCGS2 per block; 1: two-stage scheme (Fig. 6), whose
- *                   pre-processing is RandBCGS2 (Fig. 8) and always uses the sketch.
+ *  intra            first intra-block step of one-stage BCGS2 (Section 5):
+ *                   SKO_INTRA_CHOLQR2, SKO_INTRA_RANDCHOLQR, or SKO_INTRA_CHOLQR2_RECURSIVE:
+ *                   CholQR2 whose CholQRs (and the final CholQR of the block) use the
+ *                   recursive fallback of Fig. 3: on a non-positive pivot at column k the
+ *                   first k-1 columns are finished with the partial factor, the others are
+ *                   projected against them with its off-diagonal block and factorised
+ *                   recursively.  The host reads each Cholesky's status before going on
+ *                   (one synchronisation per CholQR), and the passes are not fused.
+ *                   Breakdown is reported only for a column that is numerically
+ *                   dependent on the ones before it.
+ *  two_stage        0: one-stage BCGS2 per block; 1: two-stage scheme (Fig. 6).
+ *  preproc          two-stage pre-processing: SKO_PREPROC_RANDBCGS2 (Fig. 8; uses the
+ *                   sketch) or SKO_PREPROC_PIP (BCGS with the Pythagorean inner product,
+ *                   Fig. 7, Section 7.1: one reduction gives P = Q_bar_prev^T V_hat and
+ *                   G = V_hat^T V_hat, R = chol(G - P^T P); no sketch; breaks down once a
+ *                   big panel's condition number passes about eps^(-1/2), Section 9).
  *  panels_per_big   two-stage: blocks per big panel (s_hat / s).
  *  reorth           two-stage: 1 runs the second BCGS + CholQR over each big panel
  *                   (Fig. 5 Line 19); 0 skips it (valid when one big panel spans the
@@ -94,7 +108,7 @@ typedef struct {
     int32_t panels_per_big;
     int32_t reorth;
     int32_t precision;
-    int32_t reserved_;
+    int32_t preproc;       /* sko_preproc (two-stage) */
     sko_sketch sketch;
 } sko_orth_opts;
 
@@ -260,7 +274,9 @@ sko_status sko_gmres_batched(sko_ctx ctx, int32_t nsys, const sko_csr* A,
  * small buffers, freed before returning), for 2..8 workgroups per compute unit, and keeps
  * the fastest count in ctx for that variant and row-count class (floor(log2(n / 256))).
  * Later launches of those variants on this context, by any entry point, use the choice;
- * all other launches keep the default (as many workgroups as are resident at once).
+ * all other launches keep the default (as many workgroups as are resident at once).  The
+ * deterministic comparators (two-stage with SKO_PREPROC_PIP, SKO_INTRA_CHOLQR2_RECURSIVE)
+ * are not tuned: the call returns SKO_OK without timing anything.
  * The arithmetic per row is unchanged; only the grouping of the per-workgroup partial
  * sums follows the grid, so results may change in the last bits once, when a choice
  * changes.  n below 1024 * (compute units) rows: nothing to tune, returns SKO_OK.

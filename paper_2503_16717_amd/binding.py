@@ -18,7 +18,8 @@ SKO_OK, SKO_EINVAL, SKO_EDEVICE, SKO_ENOMEM, SKO_EBREAKDOWN, SKO_ENOCONV, SKO_EU
 SKO_NOALLOC_SCRATCH_BYTES = 32 << 20
 SKO_F64, SKO_MIXED_F32 = 0, 1
 SKO_SKETCH_GAUSSIAN, SKO_SKETCH_SPARSE_SIGN, SKO_SKETCH_COUNT_GAUSS = 0, 1, 2
-SKO_INTRA_CHOLQR2, SKO_INTRA_RANDCHOLQR = 0, 1
+SKO_INTRA_CHOLQR2, SKO_INTRA_RANDCHOLQR, SKO_INTRA_CHOLQR2_RECURSIVE = 0, 1, 2
+SKO_PREPROC_RANDBCGS2, SKO_PREPROC_PIP = 0, 1
 
 EXPORTED = ["sko_create", "sko_destroy", "sko_set_stream", "sko_strerror", "sko_orth_block",
             "sko_orth_block_noalloc", "sko_orth_blocks", "sko_sketch_apply", "sko_gmres", "sko_gmres_batched", "sko_autotune_orth",
@@ -32,7 +33,7 @@ class sko_sketch(C.Structure):
 
 class sko_orth_opts(C.Structure):
     _fields_ = [("intra", C.c_int32), ("two_stage", C.c_int32), ("panels_per_big", C.c_int32),
-                ("reorth", C.c_int32), ("precision", C.c_int32), ("reserved_", C.c_int32),
+                ("reorth", C.c_int32), ("precision", C.c_int32), ("preproc", C.c_int32),
                 ("sketch", sko_sketch)]
 
 
@@ -103,7 +104,8 @@ def strerror(status: int) -> str:
 
 
 _PRECISIONS = {"f64": SKO_F64, "mixed": SKO_MIXED_F32}
-_INTRAS = {"randcholqr": SKO_INTRA_RANDCHOLQR, "cholqr2": SKO_INTRA_CHOLQR2}
+_INTRAS = {"randcholqr": SKO_INTRA_RANDCHOLQR, "cholqr2": SKO_INTRA_CHOLQR2,
+           "cholqr2_recursive": SKO_INTRA_CHOLQR2_RECURSIVE}
 
 
 def _precision_code(precision: str) -> int:
@@ -166,10 +168,14 @@ def make_sketch(kind: str = "sparse_sign", k: int = 64, zeta: int = 8, seed: int
 
 
 def orth_opts(intra="randcholqr", two_stage=False, panels_per_big=1, reorth=True, precision="f64",
-              sketch: sko_sketch | None = None) -> sko_orth_opts:
+              sketch: sko_sketch | None = None, preproc: str = "randbcgs2") -> sko_orth_opts:
     o = sko_orth_opts()
     o.intra = _intra_code(intra)
     o.two_stage = int(bool(two_stage))
+    codes = {"randbcgs2": SKO_PREPROC_RANDBCGS2, "pip": SKO_PREPROC_PIP}
+    if preproc not in codes:
+        raise ValueError(f"unknown pre-processing {preproc!r}")
+    o.preproc = codes[preproc]
     o.panels_per_big = int(panels_per_big)
     o.reorth = int(bool(reorth))
     o.precision = _precision_code(precision)

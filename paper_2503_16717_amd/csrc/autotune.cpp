@@ -58,6 +58,10 @@ sko_status autotune_orth_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const
     if (!o || n < 1 || nb < 1 || w < 1 || w > kMaxPassW) return SKO_EINVAL;
     if (o->precision != SKO_F64 && o->precision != SKO_MIXED_F32) return SKO_EINVAL;
     const bool f32 = o->precision == SKO_MIXED_F32;
+    // the deterministic comparators (BCGS-PIP pre-processing, recursive CholQR2) keep the
+    // default launch shapes
+    if ((o->two_stage && o->preproc == SKO_PREPROC_PIP) || (!o->two_stage && o->intra == SKO_INTRA_CHOLQR2_RECURSIVE))
+        return SKO_OK;
     const bool rand = o->two_stage || o->intra == SKO_INTRA_RANDCHOLQR;
     if (rand && !sketch_ok(o->sketch, n)) return SKO_EINVAL;
     const SketchPlan sp = sketch_plan(o->sketch);

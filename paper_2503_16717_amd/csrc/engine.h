@@ -243,6 +243,7 @@ struct Engine {
 
 struct BlockBufs {
     double *C1, *C2, *Ysk, *G2, *G3, *R1, *R2, *R3;
+    double *S1, *S2;  // w x w scratch of the recursive CholQR (compact partial factors)
 };
 
 // One-stage BCGS2 block (Fig. 2c): V (n x W) against Q (n x p) -> Qo (may alias V);

@@ -76,7 +76,7 @@ SmallLayout small_layout(int m, int W, int kr, int k, int Wb, bool two) {
     const size_t mW = (size_t)m * W;
     SmallLayout L{};
     L.bb = 0;
-    L.gm = up(L.bb + sizeof(double) * (2 * mW + (size_t)std::max(kr, W) * W + 5 * (size_t)W * W));
+    L.gm = up(L.bb + sizeof(double) * (2 * mW + (size_t)std::max(kr, W) * W + 7 * (size_t)W * W));
     L.ts = up(L.gm + sizeof(double) * (3 * (size_t)(m + 1) * m + 3 * (size_t)(m + 1) + 8 + (size_t)(m + 1) * W));
     L.st = up(L.ts + (two ? sizeof(double) * (mW + (size_t)k * Wb + (size_t)Wb * W + (size_t)W * W +
                                               3 * (size_t)Wb * Wb + (size_t)m * Wb + (size_t)Wb * (Wb + 1) / 2)
@@ -98,6 +98,8 @@ void carve_small(GmCtx& g, char* base, const SmallLayout& L, int kr, int k) {
     g.bb.R1 = g.bb.G3 + W * W;
     g.bb.R2 = g.bb.R1 + W * W;
     g.bb.R3 = g.bb.R2 + W * W;
+    g.bb.S1 = g.bb.R3 + W * W;
+    g.bb.S2 = g.bb.S1 + W * W;
     double* q = reinterpret_cast<double*>(base + L.gm);
     const int64_t big = (int64_t)(m + 1) * m;
     g.Tin = q;

@@ -31,9 +31,15 @@ namespace sko {
 
 // One-stage BCGS2 block: V (n x W) against Q (n x p) -> Qo; R columns assembled at
 // Rcol (device, rows 0..p+W-1, leading dimension ldr).
+sko_status one_stage_block_recursive(Engine& e, const BlockBufs& b, int p, const void* Q, int64_t ldq,
+                                     const void* V, int64_t ldv, void* Qo, int64_t ldqo, double* Rcol,
+                                     int64_t ldr, int col0);
+
 sko_status one_stage_block(Engine& e, const BlockBufs& b, int intra, int p, const void* Q, int64_t ldq,
                            const void* V, int64_t ldv, void* Qo, int64_t ldqo, double* Rcol, int64_t ldr,
                            int col0) {
+    if (intra == SKO_INTRA_CHOLQR2_RECURSIVE)
+        return one_stage_block_recursive(e, b, p, Q, ldq, V, ldv, Qo, ldqo, Rcol, ldr, col0);
     const int W = e.W;
     const bool f32 = e.f32;
     const bool rand = intra == SKO_INTRA_RANDCHOLQR;
@@ -176,6 +182,177 @@ sko_status one_stage_block(Engine& e, const BlockBufs& b, int intra, int p, cons
     return SKO_OK;
 }
 
+namespace {
+
+// The host reads a device status word (one synchronisation of the stream).
+sko_status read_status(Engine& e, const int* word, int* out) {
+    SKO_HIP(hipMemcpyAsync(e.c->status_host, word, sizeof(int), hipMemcpyDeviceToHost, e.st));
+    SKO_HIP(hipStreamSynchronize(e.st));
+    *out = *e.c->status_host;
+    return SKO_OK;
+}
+
+// Copy a rows x cols block of doubles between device matrices (column-major).
+hipError_t copy_block(double* dst, int64_t ldd, const double* src, int64_t lds, int rows, int cols, hipStream_t st) {
+    if (rows < 1 || cols < 1) return hipSuccess;
+    return hipMemcpy2DAsync(dst, sizeof(double) * ldd, src, sizeof(double) * lds, sizeof(double) * rows, cols,
+                            hipMemcpyDeviceToDevice, st);
+}
+
+// Recursive CholQR (Fig. 3) of the w columns at X, in place, R (w x w, ld w) on the device.
+// G, Rseg: w x w scratch; Rc, Cc: the compact partial factors; probe: a status word the
+// host reads after every Cholesky (the global status word gets a breakdown only for a
+// column that fails as the first of a recursion, i.e. is dependent on the ones before it).
+sko_status cholqr_recursive_dev(Engine& e, void* X, int64_t ldx, int w, double* R, int col0, double* G,
+                                double* Rseg, double* Rc, double* Cc, int* probe) {
+    const bool f32 = e.f32;
+    SKO_HIP(launch_zero(R, sizeof(double) * (size_t)w * w, e.st));
+    int c0 = 0;
+    while (c0 < w) {
+        const int ws = w - c0;
+        void* Xc = offset_elems(X, (int64_t)c0 * ldx, f32);
+        Engine es = e;
+        es.W = ws;
+        es.status = probe;
+        SKO_HIP(launch_zero(probe, sizeof(int), e.st));
+        PassArgs a{};
+        a.Y = Xc;
+        a.ldy = ldx;
+        SmallArgs sm{};
+        sm.op = OP_CHOL;
+        sm.w = ws;
+        sm.col0 = col0 + c0;
+        sm.out = G;
+        sm.R = Rseg;
+        sko_status s;
+        if ((s = es.reduction({ws, f32, RED_GRAM, false, 0, false}, a, ws, nullptr, 0, nullptr, 0, sm, 1.0))) return s;
+        int fail = 0;
+        if ((s = read_status(e, probe, &fail))) return s;
+        const int k = fail ? fail - (col0 + c0) : 0;  // 1-based within this segment
+        if (k == 0) {
+            PassArgs t{};
+            t.Y = Xc;
+            t.ldy = ldx;
+            t.R1 = Rseg;
+            t.X = Xc;
+            t.ldx = ldx;
+            if ((s = es.plain({ws, f32, RED_NONE, false, 1, true}, t))) return s;
+            SKO_HIP(copy_block(R + c0 + (int64_t)c0 * w, w, Rseg, ws, ws, ws, e.st));
+            return SKO_OK;
+        }
+        if (k == 1) {  // the segment's first column depends on the columns before it
+            const int col = col0 + c0 + 1;
+            SKO_HIP(hipMemcpyAsync(e.status, &col, sizeof(int), hipMemcpyHostToDevice, e.st));
+            SKO_HIP(hipStreamSynchronize(e.st));
+            return SKO_EBREAKDOWN;
+        }
+        const int m1 = k - 1;
+        // the first m1 rows of the partial factor: [R11 R12]
+        SKO_HIP(copy_block(Rc, m1, Rseg, ws, m1, m1, e.st));
+        SKO_HIP(copy_block(Cc, m1, Rseg + (int64_t)m1 * ws, ws, m1, ws - m1, e.st));
+        SKO_HIP(copy_block(R + c0 + (int64_t)c0 * w, w, Rseg, ws, m1, ws, e.st));
+        {   // Q1 = X1 R11^{-1}
+            Engine e1 = e;
+            e1.W = m1;
+            PassArgs t{};
+            t.Y = Xc;
+            t.ldy = ldx;
+            t.R1 = Rc;
+            t.X = Xc;
+            t.ldx = ldx;
+            if ((s = e1.plain({m1, f32, RED_NONE, false, 1, true}, t))) return s;
+        }
+        {   // X2 <- X2 - Q1 R12
+            Engine e2 = e;
+            e2.W = ws - m1;
+            void* X2 = offset_elems(Xc, (int64_t)m1 * ldx, f32);
+            PassArgs t{};
+            t.Y = X2;
+            t.ldy = ldx;
+            t.Qu = Xc;
+            t.ldqu = ldx;
+            t.pu = m1;
+            t.Cu = Cc;
+            t.X = X2;
+            t.ldx = ldx;
+            if ((s = e2.plain({ws - m1, f32, RED_NONE, true, 0, true}, t))) return s;
+        }
+        c0 += m1;
+    }
+    return SKO_OK;
+}
+
+}  // namespace
+
+// One-stage BCGS2 block with the recursive CholQR2 first intra step and a recursive final
+// CholQR (unfused passes; the host reads every Cholesky's status).
+sko_status one_stage_block_recursive(Engine& e, const BlockBufs& b, int p, const void* Q, int64_t ldq,
+                                     const void* V, int64_t ldv, void* Qo, int64_t ldqo, double* Rcol,
+                                     int64_t ldr, int col0) {
+    const int W = e.W;
+    const bool f32 = e.f32;
+    int* probe = e.status + 8;
+    sko_status s;
+    if (p > 0) {
+        PassArgs a{};
+        a.Y = V;
+        a.ldy = ldv;
+        SmallArgs sm{};
+        sm.op = OP_STORE;
+        sm.w = W;
+        sm.out = b.C1;
+        if ((s = e.reduction({W, f32, RED_PROJ, false, 0, false}, a, p, V, ldv, Q, ldq, sm, 1.0))) return s;
+        PassArgs u{};
+        u.Y = V;
+        u.ldy = ldv;
+        u.Qu = Q;
+        u.ldqu = ldq;
+        u.pu = p;
+        u.Cu = b.C1;
+        u.X = Qo;
+        u.ldx = ldqo;
+        if ((s = e.plain({W, f32, RED_NONE, true, 0, true}, u))) return s;
+    } else if (Qo != V || ldqo != ldv) {
+        const size_t eb = f32 ? 4 : 8;
+        SKO_HIP(hipMemcpy2DAsync(Qo, eb * ldqo, V, eb * ldv, eb * e.n, W, hipMemcpyDeviceToDevice, e.st));
+    }
+    if ((s = cholqr_recursive_dev(e, Qo, ldqo, W, b.R1, col0, b.G2, b.G3, b.S1, b.S2, probe))) return s;
+    if ((s = cholqr_recursive_dev(e, Qo, ldqo, W, b.R2, col0, b.G2, b.G3, b.S1, b.S2, probe))) return s;
+    if (p > 0) {
+        PassArgs a{};
+        a.Y = Qo;
+        a.ldy = ldqo;
+        SmallArgs sm{};
+        sm.op = OP_STORE;
+        sm.w = W;
+        sm.out = b.C2;
+        if ((s = e.reduction({W, f32, RED_PROJ, false, 0, false}, a, p, Qo, ldqo, Q, ldq, sm, 1.0))) return s;
+        PassArgs u{};
+        u.Y = Qo;
+        u.ldy = ldqo;
+        u.Qu = Q;
+        u.ldqu = ldq;
+        u.pu = p;
+        u.Cu = b.C2;
+        u.X = Qo;
+        u.ldx = ldqo;
+        if ((s = e.plain({W, f32, RED_NONE, true, 0, true}, u))) return s;
+    }
+    if ((s = cholqr_recursive_dev(e, Qo, ldqo, W, b.R3, col0, b.G2, b.G3, b.S1, b.S2, probe))) return s;
+    SmallArgs as{};
+    as.w = W;
+    as.R = b.R3;
+    as.Ra = b.R2;
+    as.Rb = b.R1;
+    as.C1 = p > 0 ? b.C1 : nullptr;
+    as.C2 = p > 0 ? b.C2 : nullptr;
+    as.p = p;
+    as.Rout = Rcol;
+    as.ldr = ldr;
+    SKO_HIP(launch_assemble(as, b.G2, e.st));
+    return SKO_OK;
+}
+
 bool sketch_ok(const sko_sketch& sk, int64_t n) {
     if (sk.k < 1 || sk.k > 256) return false;
     auto hashed_ok = [&](int rows) {
@@ -226,7 +403,7 @@ OneStageLayout layout_one_stage(sko_ctx c, int64_t n, int W, int pmax, int k, in
     L.part_stride = ((rows * W + 31) / 32) * 32;
     L.partials = ar.reserve(sizeof(double) * L.part_stride * L.gmax);
     const int64_t cw = std::max<int64_t>(1, (int64_t)pmax * W);
-    L.small = ar.reserve(sizeof(double) * (2 * cw + (int64_t)std::max(k, W) * W + 5 * W * W));
+    L.small = ar.reserve(sizeof(double) * (2 * cw + (int64_t)std::max(k, W) * W + 7 * W * W));
     L.rfull = ar.reserve(sizeof(double) * (int64_t)std::max(1, N) * std::max(1, N));
     L.status = ar.reserve(256);
     L.total = ar.used();
@@ -245,6 +422,8 @@ BlockBufs carve(const Arena& ar, const OneStageLayout& L, int pmax, int k, int W
     b.R1 = b.G3 + W * W;
     b.R2 = b.R1 + W * W;
     b.R3 = b.R2 + W * W;
+    b.S1 = b.R3 + W * W;
+    b.S2 = b.S1 + W * W;
     return b;
 }
 
@@ -271,8 +450,11 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     if (o->precision != SKO_F64 && o->precision != SKO_MIXED_F32) return SKO_EINVAL;
     const int N = nb * w;
     if (R && ldr < N) return SKO_EINVAL;
-    const bool rand = o->two_stage || o->intra == SKO_INTRA_RANDCHOLQR;
-    if (!o->two_stage && o->intra != SKO_INTRA_RANDCHOLQR && o->intra != SKO_INTRA_CHOLQR2) return SKO_EINVAL;
+    if (o->two_stage && o->preproc != SKO_PREPROC_RANDBCGS2 && o->preproc != SKO_PREPROC_PIP) return SKO_EINVAL;
+    const bool rand = o->two_stage ? o->preproc == SKO_PREPROC_RANDBCGS2 : o->intra == SKO_INTRA_RANDCHOLQR;
+    if (!o->two_stage && o->intra != SKO_INTRA_RANDCHOLQR && o->intra != SKO_INTRA_CHOLQR2 &&
+        o->intra != SKO_INTRA_CHOLQR2_RECURSIVE)
+        return SKO_EINVAL;
     if (rand && !sketch_ok(o->sketch, n)) return SKO_EINVAL;
     if (rand && o->sketch.k < w) return SKO_EINVAL;
     if (w > pass_rows_per_launch(w, RED_GRAM)) return SKO_EUNSUPPORTED;
@@ -301,6 +483,8 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
         const void* Vj = offset_elems(V, (int64_t)p * ldv, f32);
         void* Qj = offset_elems(Q, (int64_t)p * ldq, f32);
         s = one_stage_block(e, bb, o->intra, p, Q, ldq, Vj, ldv, Qj, ldq, Rfull + (int64_t)p * N, N, p);
+        // the recursive CholQR stops at a dependent column; its column is in the status word
+        if (s == SKO_EBREAKDOWN) return finish(c, e.status, breakdown_col);
         if (s) return s;
     }
     double* Rh = nullptr;
@@ -323,7 +507,8 @@ sko_status orth_block_check(int64_t n, int32_t p, int32_t w, const void* Q, int6
     if (p > 0 && (!Q || ldq < n)) return SKO_EINVAL;
     if (o->two_stage) return SKO_EINVAL;
     if (o->precision != SKO_F64 && o->precision != SKO_MIXED_F32) return SKO_EINVAL;
-    if (o->intra != SKO_INTRA_RANDCHOLQR && o->intra != SKO_INTRA_CHOLQR2) return SKO_EINVAL;
+    if (o->intra != SKO_INTRA_RANDCHOLQR && o->intra != SKO_INTRA_CHOLQR2 && o->intra != SKO_INTRA_CHOLQR2_RECURSIVE)
+        return SKO_EINVAL;
     const bool rand = o->intra == SKO_INTRA_RANDCHOLQR;
     if (rand && (!sketch_ok(o->sketch, n) || o->sketch.k < w)) return SKO_EINVAL;
     if ((int64_t)p * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
@@ -367,7 +552,9 @@ sko_status orth_block_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, const voi
     Arena ar(c);
     Engine e(c, n, w, f32, o->sketch);
     double* Rcol = nullptr;
-    if ((s = orth_block_run(c, ar, L, e, n, p, w, Q, ldq, V, ldv, Qo, ldqo, o, &Rcol))) return s;
+    s = orth_block_run(c, ar, L, e, n, p, w, Q, ldq, V, ldv, Qo, ldqo, o, &Rcol);
+    if (s == SKO_EBREAKDOWN) return finish(c, e.status, breakdown_col);
+    if (s) return s;
     if ((s = ensure_pinned(c, sizeof(double) * (size_t)N * w))) return s;
     double* Rh = static_cast<double*>(c->pinned);
     SKO_HIP(hipMemcpyAsync(Rh, Rcol, sizeof(double) * (size_t)N * w, hipMemcpyDeviceToHost, c->stream));
@@ -401,7 +588,14 @@ sko_status orth_block_noalloc_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, c
     e.tickets = &tickets;
     e.profile = false;
     double* Rcol = nullptr;
-    if ((s = orth_block_run(c, ar, L, e, n, p, w, Q, ldq, V, ldv, Qo, ldqo, o, &Rcol))) return s;
+    s = orth_block_run(c, ar, L, e, n, p, w, Q, ldq, V, ldv, Qo, ldqo, o, &Rcol);
+    if (s == SKO_EBREAKDOWN) {
+        SKO_HIP(hipMemcpyAsync(c->status_host, e.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        SKO_HIP(hipStreamSynchronize(c->stream));
+        if (breakdown_col) *breakdown_col = *c->status_host;
+        return s;
+    }
+    if (s) return s;
     if (Rp && p > 0)
         SKO_HIP(hipMemcpy2DAsync(Rp, sizeof(double) * p, Rcol, sizeof(double) * N, sizeof(double) * p, w,
                                  hipMemcpyDeviceToHost, c->stream));
@@ -465,12 +659,14 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     if (ppb < 1 || nb % ppb) return SKO_EINVAL;
     const int Wb = ppb * w;
     if (Wb > 64) return SKO_EUNSUPPORTED;
-    if (o->sketch.k < Wb) return SKO_EINVAL;  // the big panel must embed into the sketch space
+    const bool pip = o->preproc == SKO_PREPROC_PIP;
+    if (!pip && o->sketch.k < Wb) return SKO_EINVAL;  // the big panel must embed into the sketch space
     const bool f32 = o->precision == SKO_MIXED_F32;
     const int N = nb * w;
-    const SketchPlan sp = sketch_plan(o->sketch);
+    const SketchPlan sp = pip ? SketchPlan{RED_NONE, 0, 0, 1.0, nullptr, 0} : sketch_plan(o->sketch);
     const int k = sp.k;        // rows of the accumulated sketches
-    const int kr = sp.rows;    // rows the passes reduce
+    // rows the passes reduce (BCGS-PIP: the projection on the previous panels of the big panel)
+    const int kr = pip ? Wb - w : sp.rows;
     const int pmax = N - Wb;  // largest previous-basis width
     if ((int64_t)(Wb - w) * w > kMaxUpdCoef || (int64_t)pmax * w > kMaxUpdCoef) return SKO_EUNSUPPORTED;
 
@@ -486,7 +682,8 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     const int64_t pw = std::max<int64_t>(1, (int64_t)pmax * Wb);
     const size_t o_C = ar.reserve(sizeof(double) * pw);
     const size_t o_C2 = ar.reserve(sizeof(double) * pw);
-    const size_t o_Y = ar.reserve(sizeof(double) * (size_t)kr * w);
+    const size_t o_Y = ar.reserve(sizeof(double) * (size_t)std::max(kr, w) * w);
+    const size_t o_Gp = ar.reserve(sizeof(double) * (size_t)w * w);
     const size_t o_Yacc = ar.reserve(sizeof(double) * (size_t)k * Wb);
     const size_t o_r = ar.reserve(sizeof(double) * (size_t)Wb * w);
     const size_t o_rho = ar.reserve(sizeof(double) * (size_t)w * w);
@@ -508,6 +705,7 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     double* C = ar.at<double>(o_C);
     double* C2 = ar.at<double>(o_C2);
     double* Ysk = ar.at<double>(o_Y);
+    double* Gpip = ar.at<double>(o_Gp);
     double* Yacc = ar.at<double>(o_Yacc);
     double* rt = ar.at<double>(o_r);
     double* rho = ar.at<double>(o_rho);
@@ -548,7 +746,54 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
                 if ((s = e.reduction({w, f32, RED_PROJ, false, 0, false}, a, p_old, Vi, ldv, Q, ldq, sm, 1.0)))
                     return s;
             }
-            {
+            if (pip) {
+                // BCGS-PIP (Fig. 7): G = V_hat^T V_hat (fused with the update against Q_old), then
+                // P = Q_bar_prev^T V_hat, R = chol(G - P^T P); the first panel is CholQR.
+                SmallArgs sp_{};
+                sp_.op = OP_PIP;
+                sp_.w = w;
+                sp_.col0 = col;
+                sp_.R = rho;
+                sp_.r = rt;
+                sp_.gram = Gpip;
+                sp_.nacc = i * w;
+                sp_.Rbar = Rbar;
+                sp_.ldrbar = Wb;
+                sp_.rbar_col0 = i * w;
+                SmallArgs sg{};
+                sg.op = OP_STORE;
+                sg.w = w;
+                sg.out = Gpip;
+                PassArgs a{};
+                a.Y = Vi;
+                a.ldy = ldv;
+                PassKey key{w, f32, RED_GRAM, false, 0, false};
+                if (p_old > 0) {
+                    key.upd = true;
+                    key.write = true;
+                    a.Qu = Q;
+                    a.ldqu = ldq;
+                    a.pu = p_old;
+                    a.Cu = Ci;
+                    a.X = Qi;
+                    a.ldx = ldq;
+                    Vh = Qi;
+                    ldvh = ldq;
+                }
+                if (i == 0) {
+                    sp_.out = Ysk;
+                    if ((s = e.reduction(key, a, w, nullptr, 0, nullptr, 0, sp_, 1.0))) return s;
+                } else {
+                    if ((s = e.reduction(key, a, w, nullptr, 0, nullptr, 0, sg, 1.0))) return s;
+                    PassArgs pa{};
+                    pa.Y = Vh;
+                    pa.ldy = ldvh;
+                    sp_.out = Ysk;
+                    if ((s = e.reduction({w, f32, RED_PROJ, false, 0, false}, pa, i * w, Vh, ldvh, Qb, ldq, sp_,
+                                         1.0)))
+                        return s;
+                }
+            } else {
                 PassArgs a{};
                 a.Y = Vi;
                 a.ldy = ldv;

@@ -99,6 +99,7 @@ enum SmallOp : int {
     OP_HH = 1,           // Householder R of the k x w sketch (Fig. 4a Line 4), diag >= 0
     OP_CHOL = 2,         // upper Cholesky factor of the w x w Gram matrix (Fig. 2b)
     OP_SKETCH_BCGS2 = 3, // sketch-space BCGS2 with Householder (Fig. 8a)
+    OP_PIP = 4,          // BCGS-PIP step (Fig. 7): R = chol(G - P^T P)
 };
 
 struct SmallArgs {
@@ -116,7 +117,10 @@ struct SmallArgs {
     double* Yacc;        // k x cap, column-major (ld k): accumulated orthonormal sketches
     int nacc;            // columns of Yacc orthogonalised against (the first nacc)
     double* r;           // nacc x w coefficients (ld nacc), r1 + r2
-    // OP_SKETCH_BCGS2: optional copy of [r; rho] into columns rbar_col0.. of Rbar (ld ldrbar)
+    // OP_PIP: the reduced values are P (nacc x w) and `gram` holds G (w x w) from an earlier
+    // reduction; with nacc = 0 the reduced values are G itself.  R = chol(G - P^T P), r = P.
+    const double* gram;
+    // OP_SKETCH_BCGS2 / OP_PIP: optional copy of [r; R] into columns rbar_col0.. of Rbar (ld ldrbar)
     double* Rbar;
     int ldrbar;
     int rbar_col0;
@@ -219,6 +223,10 @@ hipError_t launch_zero_2d(void* p, size_t pitch, size_t width, size_t rows, hipS
 inline hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
     return launch_zero_2d(p, bytes, bytes, 1, stream);
 }
+
+// The R assembly of a BCGS2 block step on its own (the assembly fields of SmallArgs: Rhat =
+// Ra Rb into rh (w x w), Rdiag = R Rhat, Rproj = C1 + C2 Rhat into Rout); one workgroup.
+hipError_t launch_assemble(const SmallArgs& s, double* rh, hipStream_t stream);
 
 // Small matrix helpers on the device (single workgroup).
 hipError_t launch_small_matmul_upper(int w, const double* A, const double* B, double* C,

@@ -420,6 +420,42 @@ __device__ void sketch_bcgs2(const SmallArgs& s, double* Z, double* E, double* Y
     __syncthreads();
 }
 
+// BCGS-PIP step (Fig. 7): S = G - P^T P in LDS, R = chol(S) by one wave; r = P and, if
+// requested, [r; R] into Rbar.  P (nacc x w) is the reduction just finished (read
+// coherently); G was stored by an earlier launch (nacc > 0) or is the reduction itself.
+__device__ void pip_step(const SmallArgs& s, double* S, double* P, double* scal) {
+    const int tid = threadIdx.x;
+    const int w = s.w, na = s.nacc;
+    if (na == 0) {
+        fill_from<true>(s.out, w * w, [&](int i, double v) { S[i] = v; });
+    } else {
+        fill_from<true>(s.out, na * w, [&](int i, double v) { P[i] = v; });
+        fill_from<false>(s.gram, w * w, [&](int i, double v) { S[i] = v; });
+    }
+    __syncthreads();
+    if (na > 0) {
+        for (int idx = tid; idx < w * w; idx += RT) {
+            const int a = idx % w, c = idx / w;
+            double d = 0.0;
+            for (int t = 0; t < na; ++t) d += P[t + a * na] * P[t + c * na];
+            S[idx] -= d;
+        }
+        for (int idx = tid; idx < na * w; idx += RT) s.r[idx] = P[idx];
+    }
+    __syncthreads();
+    if (tid < 64) cholesky_wave(S, w, s.R, nullptr, s.status, s.col0, scal);
+    __syncthreads();
+    if (s.Rbar) {
+        __threadfence();
+        for (int idx = tid; idx < (na + w) * w; idx += RT) {
+            const int a = idx % (na + w), c = idx / (na + w);
+            const double v = a < na ? P[a + c * na] : load_coherent(s.R + (a - na) + c * w);
+            s.Rbar[a + (int64_t)(s.rbar_col0 + c) * s.ldrbar] = v;
+        }
+    }
+    __syncthreads();
+}
+
 // Sums this workgroup's EPW reduced values over the G partials and stores them (scaled)
 // into small.out.  Only threads of wave 0 store.
 __device__ __forceinline__ void reduce_partials(const ReduceArgs& a) {
@@ -483,6 +519,8 @@ __device__ __forceinline__ void small_step(const SmallArgs& s) {
             __threadfence();
             assemble(s, s.out);  // Rhat overwrites the consumed Gram matrix
         }
+    } else if (s.op == OP_PIP) {
+        pip_step(s, lds, lds + s.w * s.w, scal);
     } else if (s.op == OP_SKETCH_BCGS2) {
         double* Z = lds;
         double* E = lds + s.k * s.w;
@@ -545,8 +583,11 @@ __global__ void __launch_bounds__(RT) small_step_kernel_batched(const SmallArgs 
     m.C1 = batch_ptr(br, sys, d, t.C1);
     m.C2 = batch_ptr(br, sys, d, t.C2);
     m.Rout = batch_ptr(br, sys, d, t.Rout);
+    m.gram = batch_ptr(br, sys, d, t.gram);
     small_step(m);
 }
+
+__global__ void __launch_bounds__(RT) assemble_kernel(const SmallArgs s, double* rh) { assemble(s, rh); }
 
 __global__ void zero_words_kernel(uint32_t* base, int64_t pitch_words, int64_t width_words, int64_t total) {
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
@@ -585,6 +626,9 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream, const BatchRel
     } else if (s.op == OP_CHOL) {
         if (s.w > 64) return hipErrorInvalidValue;
         lds = sizeof(double) * (size_t)s.w * s.w;
+    } else if (s.op == OP_PIP) {
+        if (s.w > 64 || s.nacc < 0 || (s.nacc > 0 && (!s.gram || !s.r))) return hipErrorInvalidValue;
+        lds = sizeof(double) * ((size_t)s.w * s.w + (size_t)s.nacc * s.w);
     } else if (s.op == OP_SKETCH_BCGS2) {
         if (s.k > RT || s.w > 16 || s.k < s.w) return hipErrorInvalidValue;
         const size_t e = (size_t)s.k * s.w > (size_t)s.nacc * s.w ? (size_t)s.k * s.w : (size_t)s.nacc * s.w;
@@ -620,6 +664,12 @@ unsigned take_tickets(unsigned& tickets, int count, const BatchReloc* br) {
     const unsigned t0 = tickets;
     if (!br) tickets += (unsigned)reduce_grid(count);
     return t0;
+}
+
+hipError_t launch_assemble(const SmallArgs& s, double* rh, hipStream_t stream) {
+    if (s.w < 1 || s.w > 64 || !s.Ra || !s.Rb || !s.R || !s.Rout || !rh) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(assemble_kernel, dim3(1), dim3(RT), 0, stream, s, rh);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero_2d(void* p, size_t pitch, size_t width, size_t rows, hipStream_t stream) {
