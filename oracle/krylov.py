@@ -24,6 +24,15 @@ v_{sj+1}] including its start vector, which is the last basis vector so far):
   every big panel (two-stage, the Hessenberg matrix is only formed once the big
   panel is orthonormal, Section 6); at the end of a cycle, or once the implicit
   check passes, x is updated and the explicit residual decides.
+* Newton basis (Section 4 names it as the more stable alternative to the monomial
+  basis, after Bai, Hu and Reichel 1994): the first restart cycle runs with the
+  monomial basis; the eigenvalues of its square Hessenberg matrix (Ritz values),
+  in Leja order, give the shifts of every later cycle.  In real arithmetic step j
+  of the matrix-powers kernel is v_{j+1} = (A M^{-1} - a_j) v_j + b_j v_{j-1}: a
+  real shift theta gives (a_j, b_j) = (theta, 0); a complex pair alpha +- i beta
+  takes two steps, (alpha, 0) then (alpha, beta^2), so that v_{j+2} =
+  (A M^{-1} - theta)(A M^{-1} - conj(theta)) v_j.  The outputs are then
+  A M^{-1} v_j = v_{j+1} + a_j v_j - b_j v_{j-1}, which is what T_out stores.
 * Two-stage (Fig. 5): each panel's MPK starts from the last pre-processed
   vector; the panel is projected against the previous big panels (Line 10),
   sketched, orthogonalised in sketch space by BCGS2-HH against the accumulated
@@ -70,6 +79,74 @@ def mpk(A, dinv: np.ndarray | None, q: np.ndarray, s: int) -> np.ndarray:
     return V
 
 
+def mpk_newton(A, dinv: np.ndarray | None, q: np.ndarray, s: int, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Newton-basis matrix-powers kernel: v_0 = q, v_{j+1} = (A M^{-1} - a_j) v_j + b_j v_{j-1}."""
+    V = np.empty((q.size, s + 1))
+    V[:, 0] = q
+    for j in range(s):
+        x = V[:, j] if dinv is None else dinv * V[:, j]
+        v = spmv(A, x) - a[j] * V[:, j]
+        if b[j] != 0.0:
+            v = v + b[j] * V[:, j - 1]
+        V[:, j + 1] = v
+    return V
+
+
+def leja_order(points: np.ndarray) -> np.ndarray:
+    """Leja ordering of a set closed under conjugation.  Candidates are the points with
+    imaginary part >= 0, sorted by (real, imaginary part); the first is the one of largest
+    modulus, each next one maximises the product of distances to those chosen (sum of
+    logarithms; the first maximum in the sorted order wins).  A complex point is followed by
+    its conjugate."""
+    pts = np.asarray(points, dtype=np.complex128)
+    cand = sorted((complex(z) for z in pts if z.imag >= 0.0), key=lambda z: (z.real, z.imag))
+    order = []
+    while cand:
+        if not order:
+            best = max(range(len(cand)), key=lambda i: (abs(cand[i]), -i))
+        else:
+            def score(z):
+                tot = 0.0
+                for c in order:
+                    d = abs(z - c)
+                    if d == 0.0:
+                        return -math.inf
+                    tot += math.log(d)
+                return tot
+            scores = [score(z) for z in cand]
+            top = max(scores)
+            best = scores.index(top)
+        z = cand.pop(best)
+        order.append(z)
+        if z.imag > 0.0:
+            order.append(z.conjugate())
+    return np.array(order)
+
+
+def newton_coefficients(ritz: np.ndarray, s: int):
+    """Recurrence coefficients (a_j, b_j), j < s, from the first s Leja-ordered Ritz values; a
+    complex pair that would not fit in the last step enters by its real part."""
+    z = leja_order(ritz)
+    a = np.zeros(s)
+    b = np.zeros(s)
+    j = i = 0
+    while j < s and i < len(z):
+        t = z[i]
+        if t.imag > 0.0:
+            if j + 1 < s:
+                a[j], a[j + 1], b[j + 1] = t.real, t.real, t.imag ** 2
+                j += 2
+            else:
+                a[j] = t.real
+                j += 1
+            i += 2
+        else:
+            a[j] = t.real
+            j += 1
+            i += 1
+    return a, b
+
+
 def hessenberg_lsq(H: np.ndarray, g: np.ndarray):
     """min_y ||g - H y|| for (k+1) x k upper Hessenberg H by Givens rotations.
 
@@ -112,6 +189,8 @@ class GmresResult:
         self.explicit_history = []  # (iters, explicit relres) at every restart
         self.last_Q = None
         self.last_H = None
+        self.ritz = None            # Newton basis: Ritz values of the first cycle
+        self.newton = None          # Newton basis: recurrence coefficients (a, b)
 
 
 class _Coefs:
@@ -133,10 +212,17 @@ class _Coefs:
         self.g[:row] += t * sub[:row]
         self.g[row] = t * sub[row]
 
-    def store_block(self, kk: int, coef: np.ndarray, s: int):
-        """Inputs are coef[:, 0..s-1], outputs coef[:, 1..s] (coef is (m+1) x (s+1))."""
+    def store_block(self, kk: int, coef: np.ndarray, s: int, newton=None):
+        """Inputs are coef[:, 0..s-1], outputs coef[:, 1..s] (coef is (m+1) x (s+1)); with the
+        Newton recurrence (a, b) the output of step j is v_{j+1} + a_j v_j - b_j v_{j-1}."""
         self.Tin[:, kk:kk + s] = coef[:, :s]
         self.Tout[:, kk:kk + s] = coef[:, 1:]
+        if newton is not None:
+            a, b = newton
+            for j in range(s):
+                self.Tout[:, kk + j] += a[j] * coef[:, j]
+                if b[j] != 0.0:
+                    self.Tout[:, kk + j] -= b[j] * coef[:, j - 1]
 
     def lsq(self, k: int):
         H = trsm_right_upper(self.Tout[:k + 1, :k], self.Tin[:k, :k])
@@ -144,7 +230,11 @@ class _Coefs:
         return H, y, res
 
 
-def _cycle_one_stage(A, dinv, r, beta, bnorm, s, m, intra, sk, tol, res, maxiter):
+def _mpk(A, dinv, q, s, newton):
+    return mpk(A, dinv, q, s) if newton is None else mpk_newton(A, dinv, q, s, *newton)
+
+
+def _cycle_one_stage(A, dinv, r, beta, bnorm, s, m, intra, sk, tol, res, maxiter, newton=None):
     n = r.size
     Q = np.zeros((n, m + 1))
     Q[:, 0] = r / beta
@@ -153,7 +243,7 @@ def _cycle_one_stage(A, dinv, r, beta, bnorm, s, m, intra, sk, tol, res, maxiter
     y = np.zeros(0)
     H = None
     while k < m:
-        V = mpk(A, dinv, Q[:, k], s)
+        V = _mpk(A, dinv, Q[:, k], s, newton)
         Qj, Rp, Rd, info = bcgs2_block(Q[:, :k], V, intra, sk)
         if info:
             res.breakdown_col = k + info
@@ -166,7 +256,7 @@ def _cycle_one_stage(A, dinv, r, beta, bnorm, s, m, intra, sk, tol, res, maxiter
         coef = np.zeros((m + 1, s + 1))
         coef[:k, :] = Rp
         coef[k:k + s + 1, :] = Rd
-        co.store_block(k, coef, s)
+        co.store_block(k, coef, s, newton)
         k += s
         res.iters += s
         H, y, rimp = co.lsq(k)
@@ -177,7 +267,7 @@ def _cycle_one_stage(A, dinv, r, beta, bnorm, s, m, intra, sk, tol, res, maxiter
     return Q[:, :k] @ y, Q[:, :k + 1], H
 
 
-def _cycle_two_stage(A, dinv, r, beta, bnorm, s, shat, m, sk, tol, res, maxiter):
+def _cycle_two_stage(A, dinv, r, beta, bnorm, s, shat, m, sk, tol, res, maxiter, newton=None):
     n = r.size
     Q = np.zeros((n, m + 1))
     Q[:, 0] = r / beta
@@ -196,7 +286,7 @@ def _cycle_two_stage(A, dinv, r, beta, bnorm, s, shat, m, sk, tol, res, maxiter)
         for i in range(shat // s):
             loc = i * s
             kk = k0 + loc
-            V = mpk(A, dinv, Qbar[:, loc], s)
+            V = _mpk(A, dinv, Qbar[:, loc], s, newton)
             if k0 > 0:
                 C = Qold.T @ V
                 Vh = V - Qold @ C
@@ -216,7 +306,7 @@ def _cycle_two_stage(A, dinv, r, beta, bnorm, s, shat, m, sk, tol, res, maxiter)
             coef[k0:kk, :] = rr
             coef[kk:kk + s + 1, :] = rho
             co.replace_row(kk, coef[:, 0], kk)
-            co.store_block(kk, coef, s)
+            co.store_block(kk, coef, s, newton)
             res.iters += s
         Qh, Rh, info = cholqr(Qbar)
         if info:
@@ -257,8 +347,12 @@ def _cycle_two_stage(A, dinv, r, beta, bnorm, s, shat, m, sk, tol, res, maxiter)
 def sstep_gmres(A, b: np.ndarray, *, x0: np.ndarray | None = None, s: int = 5, m: int = 30,
                 shat: int | None = None, two_stage: bool = False, intra: str = "randcholqr",
                 sk: Sketch | None = None, jacobi: bool = False, tol: float = 1e-10,
-                maxiter: int = 50000, max_restarts: int | None = None) -> GmresResult:
-    """Restarted s-step GMRES (one- or two-stage); returns a GmresResult."""
+                maxiter: int = 50000, max_restarts: int | None = None,
+                basis: str = "monomial") -> GmresResult:
+    """Restarted s-step GMRES (one- or two-stage); returns a GmresResult.  basis="newton":
+    Newton basis from the second cycle on, shifts from the first cycle's Ritz values."""
+    if basis not in ("monomial", "newton"):
+        raise ValueError(basis)
     if m % s:
         raise ValueError("m must be a multiple of s")
     if two_stage:
@@ -280,12 +374,16 @@ def sstep_gmres(A, b: np.ndarray, *, x0: np.ndarray | None = None, s: int = 5, m
         if res.iters >= maxiter or (max_restarts is not None and res.restarts >= max_restarts):
             break
         if two_stage:
-            dx, Qc, H = _cycle_two_stage(A, dinv, r, beta, bnorm, s, shat, m, sk, tol, res, maxiter)
+            dx, Qc, H = _cycle_two_stage(A, dinv, r, beta, bnorm, s, shat, m, sk, tol, res, maxiter, res.newton)
         else:
-            dx, Qc, H = _cycle_one_stage(A, dinv, r, beta, bnorm, s, m, intra, sk, tol, res, maxiter)
+            dx, Qc, H = _cycle_one_stage(A, dinv, r, beta, bnorm, s, m, intra, sk, tol, res, maxiter, res.newton)
         res.last_Q, res.last_H = Qc, H
         if dx is None:
             break
+        if basis == "newton" and res.newton is None and H is not None:
+            k = H.shape[1]
+            res.ritz = np.linalg.eigvals(H[:k, :k])
+            res.newton = newton_coefficients(res.ritz, s)
         x += dx if dinv is None else dinv * dx
         res.restarts += 1
     res.x = x
