@@ -49,6 +49,7 @@ typedef enum { SKO_F64 = 0, SKO_MIXED_F32 = 1 } sko_precision;
 typedef enum { SKO_SKETCH_GAUSSIAN = 0, SKO_SKETCH_SPARSE_SIGN = 1, SKO_SKETCH_COUNT_GAUSS = 2 } sko_sketch_kind;
 typedef enum { SKO_INTRA_CHOLQR2 = 0, SKO_INTRA_RANDCHOLQR = 1, SKO_INTRA_CHOLQR2_RECURSIVE = 2 } sko_intra;
 typedef enum { SKO_PREPROC_RANDBCGS2 = 0, SKO_PREPROC_PIP = 1 } sko_preproc;
+typedef enum { SKO_BASIS_MONOMIAL = 0, SKO_BASIS_NEWTON = 1 } sko_basis;
 
 /*
  * Random sketch Theta (n x k), applied as Theta^T X (Section 3).
@@ -141,6 +142,14 @@ typedef struct {
  *                 the phase boundaries, a few microseconds each); 0: they are 0.
  *  tol            stop when ||b - A x||_2 / ||b||_2 <= tol (explicit, double).
  *  maxiter        cap on generated basis vectors (0: 50000).
+ *  basis          SKO_BASIS_MONOMIAL, or SKO_BASIS_NEWTON (Section 4; Bai, Hu and Reichel
+ *                 1994): the first restart cycle runs with the monomial basis; the
+ *                 eigenvalues of its square Hessenberg matrix (Ritz values, computed on the
+ *                 device by the double-shift QR iteration), in Leja order, give the shifts of
+ *                 every later cycle, whose matrix-powers steps are v_{j+1} = (A M^{-1} - a_j)
+ *                 v_j + b_j v_{j-1} (a real shift theta: (theta, 0); a complex pair alpha +- i
+ *                 beta: two steps (alpha, 0), (alpha, beta^2)).  Requires m <= 64; batches with
+ *                 it are solved system by system.
  */
 typedef struct {
     int32_t s, shat, m, two_stage;
@@ -151,6 +160,8 @@ typedef struct {
     sko_sketch sketch;
     double tol;
     int64_t maxiter;
+    int32_t basis;         /* sko_basis */
+    int32_t reserved_;
 } sko_gmres_opts;
 
 typedef struct {

@@ -20,6 +20,7 @@ SKO_F64, SKO_MIXED_F32 = 0, 1
 SKO_SKETCH_GAUSSIAN, SKO_SKETCH_SPARSE_SIGN, SKO_SKETCH_COUNT_GAUSS = 0, 1, 2
 SKO_INTRA_CHOLQR2, SKO_INTRA_RANDCHOLQR, SKO_INTRA_CHOLQR2_RECURSIVE = 0, 1, 2
 SKO_PREPROC_RANDBCGS2, SKO_PREPROC_PIP = 0, 1
+SKO_BASIS_MONOMIAL, SKO_BASIS_NEWTON = 0, 1
 
 EXPORTED = ["sko_create", "sko_destroy", "sko_set_stream", "sko_strerror", "sko_orth_block",
             "sko_orth_block_noalloc", "sko_orth_blocks", "sko_sketch_apply", "sko_gmres", "sko_gmres_batched", "sko_autotune_orth",
@@ -46,7 +47,7 @@ class sko_gmres_opts(C.Structure):
     _fields_ = [("s", C.c_int32), ("shat", C.c_int32), ("m", C.c_int32), ("two_stage", C.c_int32),
                 ("precond", C.c_int32), ("intra", C.c_int32), ("precision", C.c_int32),
                 ("phase_timing", C.c_int32), ("sketch", sko_sketch), ("tol", C.c_double),
-                ("maxiter", C.c_int64)]
+                ("maxiter", C.c_int64), ("basis", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class sko_gmres_info(C.Structure):
@@ -184,9 +185,14 @@ def orth_opts(intra="randcholqr", two_stage=False, panels_per_big=1, reorth=True
 
 
 def gmres_opts(s=5, m=30, shat=0, two_stage=False, precond=0, intra="randcholqr", precision="f64",
-               sketch: sko_sketch | None = None, tol=1e-10, maxiter=0, phase_timing=False) -> sko_gmres_opts:
+               sketch: sko_sketch | None = None, tol=1e-10, maxiter=0, phase_timing=False,
+               basis: str = "monomial") -> sko_gmres_opts:
     o = sko_gmres_opts()
     o.phase_timing = int(bool(phase_timing))
+    bases = {"monomial": SKO_BASIS_MONOMIAL, "newton": SKO_BASIS_NEWTON}
+    if basis not in bases:
+        raise ValueError(f"unknown basis {basis!r}")
+    o.basis = bases[basis]
     o.s, o.m, o.shat, o.two_stage = int(s), int(m), int(shat), int(bool(two_stage))
     o.precond = int(precond)
     o.intra = _intra_code(intra)

@@ -48,6 +48,10 @@ struct GmCtx {
     double *Tin, *Tout, *g, *gw, *H, *y, *res, *beta, *bnorm, *coef;
     double *Cpan, *Yacc, *rt, *rho, *Gb, *Rh, *Rt, *C2b;
     double* Rpk;  // packed copy of Rh, then of Rt, for the row solves
+    // Newton basis: recurrence coefficients a (s) then b (s) on the device, set from the first
+    // cycle's Ritz values (newton_on from then on)
+    double* newton = nullptr;
+    bool newton_on = false;
     BlockBufs bb;
     int* status;
     int grid_cap;
@@ -165,6 +169,9 @@ sko_status mpk(GmCtx& g, int from, int s) {
         if (g.br)
             SKO_HIP(launch_spmv_batched(g.f32, g.avg_nnz, g.max_n, col_ptr(g, from + i - 1), col_ptr(g, from + i),
                                         g.spmv_cap, g.st, *g.br));
+        else if (g.newton_on)  // step i - 1 of the Newton recurrence
+            SKO_HIP(launch_spmv(g.A, g.f32, col_ptr(g, from + i - 1), col_ptr(g, from + i), g.grid_cap, g.st,
+                                g.newton + (i - 1), g.newton + g.s + (i - 1), col_ptr(g, from + (i >= 2 ? i - 2 : 0))));
         else
             SKO_HIP(launch_spmv(g.A, g.f32, col_ptr(g, from + i - 1), col_ptr(g, from + i), g.grid_cap, g.st));
         g.c->prof.end(ev, g.st);
@@ -184,7 +191,12 @@ sko_status mpk_panel(GmCtx& g, int from, int s) {
     for (int i = 1; i <= s; ++i) {
         const int ev = g.c->prof.begin("spmv f32 values, f64 vectors",
                                        (double)g.A.nnz * 8.0 + (double)g.n * 20.0, g.st);
-        SKO_HIP(launch_spmv_panel(g.A, P + (int64_t)(i - 1) * g.ld, P + (int64_t)i * g.ld, g.grid_cap, g.st));
+        if (g.newton_on)
+            SKO_HIP(launch_spmv_panel(g.A, P + (int64_t)(i - 1) * g.ld, P + (int64_t)i * g.ld, g.grid_cap, g.st,
+                                      g.newton + (i - 1), g.newton + g.s + (i - 1),
+                                      P + (int64_t)(i >= 2 ? i - 2 : 0) * g.ld));
+        else
+            SKO_HIP(launch_spmv_panel(g.A, P + (int64_t)(i - 1) * g.ld, P + (int64_t)i * g.ld, g.grid_cap, g.st));
         g.c->prof.end(ev, g.st);
     }
     return SKO_OK;
@@ -202,6 +214,7 @@ sko_status gm_op(GmCtx& g, GmSmallArgs a) {
     a.res = g.res;
     a.beta = g.beta;
     a.coef = g.coef;
+    if (a.op == GM_BLOCK && g.newton_on) a.newton = g.newton;
     g.phase(PhaseTimer::SMALL);
     const int ev = g.c->prof.begin("gmres small", 0.0, g.st);
     SKO_HIP(launch_gm_small(a, g.st, g.br));
@@ -424,6 +437,8 @@ sko_status check_opts(const sko_csr* A, const sko_gmres_opts* o, GmCtx& g) {
     if (need_sketch && !sketch_ok(o->sketch, A->n)) return SKO_EINVAL;
     if (need_sketch && o->sketch.k < (two ? shat + 1 : S + 1)) return SKO_EINVAL;
     if (!(o->tol > 0.0)) return SKO_EINVAL;
+    if (o->basis != SKO_BASIS_MONOMIAL && o->basis != SKO_BASIS_NEWTON) return SKO_EINVAL;
+    if (o->basis == SKO_BASIS_NEWTON && m > 64) return SKO_EUNSUPPORTED;
     g.n = A->n;
     g.ld = ((A->n + 63) / 64) * 64;
     g.s = S;
@@ -480,10 +495,12 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     const size_t o_part = ar.reserve(sizeof(double) * part_doubles);
     const SmallLayout L = small_layout(m, g.W, kr, k, g.Wb, g.two);
     const size_t o_small = ar.reserve(L.bytes);
+    const size_t o_newton = ar.reserve(sizeof(double) * 2 * g.s);
     sko_status s = ensure_workspace(c, ar.used());
     if (s) return s;
     if ((s = ensure_pinned(c, 64))) return s;
     g.host = static_cast<double*>(c->pinned);
+    g.newton = ar.at<double>(o_newton);
     g.Q = ar.at<void>(o_Q);
     g.P = panel64 ? ar.at<double>(o_P) : nullptr;
     g.dinv = g.jacobi ? ar.at<double>(o_dinv) : nullptr;
@@ -602,6 +619,17 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
                 break;
             }
             if (s) return s;
+            if (o->basis == SKO_BASIS_NEWTON && !g.newton_on && kreached > 0) {
+                // shifts for the later cycles: Leja-ordered Ritz values of this cycle
+                GmSmallArgs ra{};
+                ra.m = g.m;
+                ra.s = g.s;
+                ra.Tin = g.Tin;
+                ra.Tout = g.Tout;
+                g.phase(PhaseTimer::SMALL);
+                SKO_HIP(launch_ritz(ra, kreached, g.newton, g.st));
+                g.newton_on = true;
+            }
             {
                 g.phase(PhaseTimer::SMALL);
                 const int ev2 = c->prof.begin("update x", (double)A->n * (kreached * eb + 16.0), g.st);
@@ -659,8 +687,9 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     if (nsys == 0) return SKO_OK;
     if (infos)
         for (int32_t i = 0; i < nsys; ++i) infos[i] = sko_gmres_info{};
-    // lock step needs the two-stage scheme with the hashed sketch (no per-system Theta)
-    if (nsys == 1 || !o->two_stage || o->sketch.kind == SKO_SKETCH_GAUSSIAN)
+    // lock step needs the two-stage scheme with the hashed sketch (no per-system Theta) and
+    // the monomial basis (Newton shifts are per system)
+    if (nsys == 1 || !o->two_stage || o->sketch.kind == SKO_SKETCH_GAUSSIAN || o->basis != SKO_BASIS_MONOMIAL)
         return gmres_sequential(c, nsys, A, b, x, o, infos);
 
     GmCtx g{};

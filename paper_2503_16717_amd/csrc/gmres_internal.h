@@ -21,10 +21,14 @@ struct CsrView {
     const void* val_op;    // MPK operator values (double or float)
 };
 
-hipError_t launch_spmv(const CsrView& A, bool f32, const void* x, void* y, int grid_cap, hipStream_t st);
+// y = A x, or with a Newton step (na != null) y = A x - (*na) x + (*nb) z (na, nb: device
+// scalars; z: the basis vector before x, read only where *nb != 0).
+hipError_t launch_spmv(const CsrView& A, bool f32, const void* x, void* y, int grid_cap, hipStream_t st,
+                       const double* na = nullptr, const double* nb = nullptr, const void* z = nullptr);
 // Mixed precision: one matrix-powers step of the FP64 panel (FP32 operator values, FP64
 // vectors), and the widening copy of an FP32 basis column into the panel.
-hipError_t launch_spmv_panel(const CsrView& A, const double* x, double* y, int grid_cap, hipStream_t st);
+hipError_t launch_spmv_panel(const CsrView& A, const double* x, double* y, int grid_cap, hipStream_t st,
+                             const double* na = nullptr, const double* nb = nullptr, const double* z = nullptr);
 hipError_t launch_widen(int64_t n, const float* x, double* y, int grid_cap, hipStream_t st);
 int residual_grid(int64_t n, int grid_cap);
 hipError_t launch_residual(const CsrView& A, const double* x, const double* b, bool f32, void* r, double* partials,
@@ -65,9 +69,13 @@ struct GmSmallArgs {
     const double* Rh;  // GM_BIGCLOSE: Wb x Wb
     const double* Rt;  // GM_BIGCLOSE: Wb x Wb or null (identity)
     const double* C2;  // GM_BIGCLOSE: k0 x Wb or null
+    // GM_BLOCK with the Newton basis: recurrence coefficients a (s) then b (s); null: monomial
+    const double* newton;
 };
 
 hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st, const BatchReloc* br = nullptr);
+// Ritz values of the leading k x k Hessenberg matrix (k <= 64) -> Newton coefficients (2 s).
+hipError_t launch_ritz(const GmSmallArgs& a, int k, double* newton, hipStream_t st);
 
 // Batched forms (batch.h): one launch for every active system; x, y, r and Q are template
 // basis addresses, partials and y template workspace addresses.

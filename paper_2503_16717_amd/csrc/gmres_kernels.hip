@@ -10,6 +10,7 @@
 
 #include "batch.h"
 #include "gmres_internal.h"
+#include "hessenberg_eig.h"
 #include "uniform.h"
 
 namespace sko {
@@ -28,11 +29,30 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Newton-basis step of the matrix-powers kernel (a device pair, null for a monomial step):
+// y = A x - a x + b z, with a = *na, b = *nb (z: the vector before x, read only if b != 0).
+template <typename TX>
+struct NewtonStep {
+    const double* na = nullptr;
+    const double* nb = nullptr;
+    const TX* z = nullptr;
+};
+
+template <typename TX>
+__device__ __forceinline__ double newton_term(const NewtonStep<TX>& ns, const TX* __restrict__ x, int64_t row) {
+    if (!ns.na) return 0.0;
+    double t = -(*ns.na) * ld_(x + row);
+    const double b = *ns.nb;
+    if (b != 0.0) t += b * ld_(ns.z + row);
+    return t;
+}
+
 // y = A x with L lanes per row, workgroup wg of nwg striding over groups of NT/L rows.
 template <int L, typename TV, typename TX, typename TY>
 __device__ __forceinline__ void spmv_rows(int64_t n, const int32_t* __restrict__ rowptr,
                                           const int32_t* __restrict__ colind, const TV* __restrict__ val,
-                                          const TX* __restrict__ x, TY* __restrict__ y, int wg, int nwg) {
+                                          const TX* __restrict__ x, TY* __restrict__ y, int wg, int nwg,
+                                          const NewtonStep<TX>& ns = NewtonStep<TX>{}) {
     const int tid = threadIdx.x;
     const int sub = tid % L;
     const int64_t rows_per_block = NT / L;
@@ -45,15 +65,16 @@ __device__ __forceinline__ void spmv_rows(int64_t n, const int32_t* __restrict__
         }
 #pragma unroll
         for (int o = L / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-        if (sub == 0 && row < n) y[row] = static_cast<TY>(sum);
+        if (sub == 0 && row < n) y[row] = static_cast<TY>(sum + newton_term(ns, x, row));
     }
 }
 
 template <int L, typename TV, typename TX, typename TY>
 __global__ void __launch_bounds__(NT) spmv_kernel(int64_t n, const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colind, const TV* __restrict__ val,
-                                                  const TX* __restrict__ x, TY* __restrict__ y) {
-    spmv_rows<L, TV, TX, TY>(n, rowptr, colind, val, x, y, blockIdx.x, gridDim.x);
+                                                  const TX* __restrict__ x, TY* __restrict__ y,
+                                                  const NewtonStep<TX> ns) {
+    spmv_rows<L, TV, TX, TY>(n, rowptr, colind, val, x, y, blockIdx.x, gridDim.x, ns);
 }
 
 // One row per thread; each workgroup first copies the contiguous nonzero range of its NT
@@ -64,7 +85,8 @@ constexpr int STAGE = 8 * NT;
 template <typename TV, typename TX, typename TY>
 __device__ __forceinline__ void spmv_staged_body(int64_t n, const int32_t* __restrict__ rowptr,
                                                  const int32_t* __restrict__ colind, const TV* __restrict__ val,
-                                                 const TX* __restrict__ x, TY* __restrict__ y, int wg, int nwg) {
+                                                 const TX* __restrict__ x, TY* __restrict__ y, int wg, int nwg,
+                                                 const NewtonStep<TX>& ns = NewtonStep<TX>{}) {
     __shared__ TV sv[STAGE];
     __shared__ int32_t sc[STAGE];
     const int tid = threadIdx.x;
@@ -86,7 +108,7 @@ __device__ __forceinline__ void spmv_staged_body(int64_t n, const int32_t* __res
                 for (int32_t e = a; e < b; ++e) sum += ld_(sv + e) * ld_(x + sc[e]);
             else
                 for (int32_t e = a; e < b; ++e) sum += ld_(val + e0 + e) * ld_(x + colind[e0 + e]);
-            y[row] = static_cast<TY>(sum);
+            y[row] = static_cast<TY>(sum + newton_term(ns, x, row));
         }
         __syncthreads();
     }
@@ -96,8 +118,8 @@ template <typename TV, typename TX, typename TY>
 __global__ void __launch_bounds__(NT) spmv_staged_kernel(int64_t n, const int32_t* __restrict__ rowptr,
                                                          const int32_t* __restrict__ colind,
                                                          const TV* __restrict__ val, const TX* __restrict__ x,
-                                                         TY* __restrict__ y) {
-    spmv_staged_body<TV, TX, TY>(n, rowptr, colind, val, x, y, blockIdx.x, gridDim.x);
+                                                         TY* __restrict__ y, const NewtonStep<TX> ns) {
+    spmv_staged_body<TV, TX, TY>(n, rowptr, colind, val, x, y, blockIdx.x, gridDim.x, ns);
 }
 
 template <typename TV, typename TX, typename TY>
@@ -342,13 +364,23 @@ __device__ void replace_row(const GmSmallArgs& a, int row, const double* sub) {
 }
 
 __device__ void store_block(const GmSmallArgs& a, int kk, const double* coef) {
-    // inputs coef[:, 0..s-1] -> T_in[:, kk..kk+s-1]; outputs coef[:, 1..s] -> T_out
+    // inputs coef[:, 0..s-1] -> T_in[:, kk..kk+s-1]; outputs coef[:, 1..s] -> T_out, or with
+    // the Newton recurrence (a_i, b_i) the output A v_i = v_{i+1} + a_i v_i - b_i v_{i-1}
     const int ld = a.m + 1;
     const int rows = kk + a.s + 1;
     for (int idx = threadIdx.x; idx < ld * a.s; idx += NT) {
         const int r = idx % ld, i = idx / ld;
+        double out = 0.0;
+        if (r < rows) {
+            out = coef[r + (int64_t)(i + 1) * ld];
+            if (a.newton) {
+                out += a.newton[i] * coef[r + (int64_t)i * ld];
+                const double bi = a.newton[a.s + i];
+                if (bi != 0.0) out -= bi * coef[r + (int64_t)(i - 1) * ld];
+            }
+        }
         a.Tin[r + (int64_t)(kk + i) * ld] = r < rows ? coef[r + (int64_t)i * ld] : 0.0;
-        a.Tout[r + (int64_t)(kk + i) * ld] = r < rows ? coef[r + (int64_t)(i + 1) * ld] : 0.0;
+        a.Tout[r + (int64_t)(kk + i) * ld] = out;
     }
     __syncthreads();
 }
@@ -614,6 +646,39 @@ __device__ __forceinline__ void gm_small_body(const GmSmallArgs& a) {
 
 __global__ void __launch_bounds__(NT) gm_small_kernel(const GmSmallArgs a) { gm_small_body(a); }
 
+// Newton basis shifts: the Ritz values of the cycle just finished (eigenvalues of the square
+// k x k Hessenberg matrix H = T_out T_in^{-1}) in Leja order give the recurrence coefficients
+// of s matrix-powers steps, newton[0..s) = a and newton[s..2s) = b.  The rows of H are formed
+// in parallel as in the least squares (entries below the subdiagonal, rounding noise of an
+// exactly Hessenberg matrix, are set to zero); the QR iteration and the ordering run on one
+// thread.  Without convergence the coefficients stay zero (monomial steps).
+__global__ void __launch_bounds__(NT) ritz_kernel(const GmSmallArgs a, int k, double* newton) {
+    extern __shared__ double rz[];
+    const int ld = a.m + 1;
+    double* Hs = rz;
+    double* wr = Hs + k * k;
+    double* wi = wr + k;
+    double* cre = wi + k;
+    double* cim = cre + k;
+    double* ore = cim + k;
+    double* oim = ore + 2 * k;
+    for (int r = threadIdx.x; r < k; r += NT) {
+        for (int c = 0; c < k; ++c) {
+            double v = a.Tout[r + (int64_t)c * ld];
+            for (int q = 0; q < c; ++q) v -= Hs[r + q * k] * a.Tin[q + (int64_t)c * ld];
+            Hs[r + c * k] = v / a.Tin[c + (int64_t)c * ld];
+        }
+        for (int c = 0; c + 1 < r; ++c) Hs[r + c * k] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* A = newton;
+        double* B = newton + a.s;
+        for (int j = 0; j < a.s; ++j) A[j] = B[j] = 0.0;
+        if (hessenberg_eigenvalues(Hs, k, k, wr, wi)) leja_newton_coefficients(wr, wi, k, a.s, cre, cim, ore, oim, A, B);
+    }
+}
+
 __global__ void __launch_bounds__(NT) gm_small_kernel_batched(const GmSmallArgs t, const BatchReloc br) {
     const int sys = batch_system(br);
     const BatchSys& d = br.sys[sys];
@@ -650,23 +715,23 @@ int spmv_rows_per_block(SpmvKind k) { return k == SPMV_L8 ? NT / 8 : k == SPMV_L
 
 template <typename TV, typename TX, typename TY>
 hipError_t spmv_dispatch(int64_t n, double avg, const int32_t* rp, const int32_t* ci, const TV* v, const TX* x, TY* y,
-                         int grid_cap, hipStream_t st) {
+                         int grid_cap, hipStream_t st, const NewtonStep<TX>& ns = NewtonStep<TX>{}) {
     const SpmvKind k = spmv_kind<TV>(avg);
     const int rpb = spmv_rows_per_block(k);
     const int64_t groups = (n + rpb - 1) / rpb;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, grid_cap));
     switch (k) {
         case SPMV_L8:
-            hipLaunchKernelGGL((spmv_kernel<8, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+            hipLaunchKernelGGL((spmv_kernel<8, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y, ns);
             break;
         case SPMV_L4:
-            hipLaunchKernelGGL((spmv_kernel<4, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+            hipLaunchKernelGGL((spmv_kernel<4, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y, ns);
             break;
         case SPMV_L2:
-            hipLaunchKernelGGL((spmv_kernel<2, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+            hipLaunchKernelGGL((spmv_kernel<2, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y, ns);
             break;
         case SPMV_STAGED:
-            hipLaunchKernelGGL((spmv_staged_kernel<TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y);
+            hipLaunchKernelGGL((spmv_staged_kernel<TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y, ns);
             break;
     }
     return hipGetLastError();
@@ -674,19 +739,23 @@ hipError_t spmv_dispatch(int64_t n, double avg, const int32_t* rp, const int32_t
 
 }  // namespace
 
-hipError_t launch_spmv(const CsrView& A, bool f32, const void* x, void* y, int grid_cap, hipStream_t st) {
+hipError_t launch_spmv(const CsrView& A, bool f32, const void* x, void* y, int grid_cap, hipStream_t st,
+                       const double* na, const double* nb, const void* z) {
     const double avg = (double)A.nnz / (double)std::max<int64_t>(1, A.n);
     if (f32)
         return spmv_dispatch<float, float, float>(A.n, avg, A.rowptr, A.colind, static_cast<const float*>(A.val_op),
-                                                  static_cast<const float*>(x), static_cast<float*>(y), grid_cap, st);
+                                                  static_cast<const float*>(x), static_cast<float*>(y), grid_cap, st,
+                                                  NewtonStep<float>{na, nb, static_cast<const float*>(z)});
     return spmv_dispatch<double, double, double>(A.n, avg, A.rowptr, A.colind, static_cast<const double*>(A.val_op),
-                                                 static_cast<const double*>(x), static_cast<double*>(y), grid_cap, st);
+                                                 static_cast<const double*>(x), static_cast<double*>(y), grid_cap, st,
+                                                 NewtonStep<double>{na, nb, static_cast<const double*>(z)});
 }
 
-hipError_t launch_spmv_panel(const CsrView& A, const double* x, double* y, int grid_cap, hipStream_t st) {
+hipError_t launch_spmv_panel(const CsrView& A, const double* x, double* y, int grid_cap, hipStream_t st,
+                             const double* na, const double* nb, const double* z) {
     const double avg = (double)A.nnz / (double)std::max<int64_t>(1, A.n);
     return spmv_dispatch<float, double, double>(A.n, avg, A.rowptr, A.colind, static_cast<const float*>(A.val_op), x,
-                                                y, grid_cap, st);
+                                                y, grid_cap, st, NewtonStep<double>{na, nb, z});
 }
 
 hipError_t launch_widen(int64_t n, const float* x, double* y, int grid_cap, hipStream_t st) {
@@ -760,6 +829,13 @@ hipError_t launch_scale_values(int64_t nnz, const int32_t* colind, const double*
     else
         hipLaunchKernelGGL((scale_values_kernel<double>), dim3(grid), dim3(NT), 0, st, nnz, colind, val, dinv,
                            static_cast<double*>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_ritz(const GmSmallArgs& a, int k, double* newton, hipStream_t st) {
+    if (k < 1 || k > 64 || k > a.m || !newton) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * ((size_t)k * k + 8 * (size_t)k);
+    hipLaunchKernelGGL(ritz_kernel, dim3(1), dim3(NT), lds, st, a, k, newton);
     return hipGetLastError();
 }
 
