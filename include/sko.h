@@ -150,6 +150,11 @@ typedef struct {
  *                 v_j + b_j v_{j-1} (a real shift theta: (theta, 0); a complex pair alpha +- i
  *                 beta: two steps (alpha, 0), (alpha, beta^2)).  Requires m <= 64; batches with
  *                 it are solved system by system.
+ *  eager          0: the one-stage single-system solver captures the launches of each s-step
+ *                 block (matrix powers, orthogonalisation, Hessenberg step) into a HIP graph
+ *                 once per block position and solve, and replays it (one graph launch per
+ *                 block instead of about 20 kernel launches; not while the kernel profiler or
+ *                 phase timing is on); 1: plain launches.  Results are the same either way.
  */
 typedef struct {
     int32_t s, shat, m, two_stage;
@@ -161,7 +166,7 @@ typedef struct {
     double tol;
     int64_t maxiter;
     int32_t basis;         /* sko_basis */
-    int32_t reserved_;
+    int32_t eager;         /* 1: no launch graphs */
 } sko_gmres_opts;
 
 typedef struct {

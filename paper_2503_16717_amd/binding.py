@@ -47,7 +47,7 @@ class sko_gmres_opts(C.Structure):
     _fields_ = [("s", C.c_int32), ("shat", C.c_int32), ("m", C.c_int32), ("two_stage", C.c_int32),
                 ("precond", C.c_int32), ("intra", C.c_int32), ("precision", C.c_int32),
                 ("phase_timing", C.c_int32), ("sketch", sko_sketch), ("tol", C.c_double),
-                ("maxiter", C.c_int64), ("basis", C.c_int32), ("reserved_", C.c_int32)]
+                ("maxiter", C.c_int64), ("basis", C.c_int32), ("eager", C.c_int32)]
 
 
 class sko_gmres_info(C.Structure):
@@ -186,9 +186,10 @@ def orth_opts(intra="randcholqr", two_stage=False, panels_per_big=1, reorth=True
 
 def gmres_opts(s=5, m=30, shat=0, two_stage=False, precond=0, intra="randcholqr", precision="f64",
                sketch: sko_sketch | None = None, tol=1e-10, maxiter=0, phase_timing=False,
-               basis: str = "monomial") -> sko_gmres_opts:
+               basis: str = "monomial", eager: bool = False) -> sko_gmres_opts:
     o = sko_gmres_opts()
     o.phase_timing = int(bool(phase_timing))
+    o.eager = int(bool(eager))
     bases = {"monomial": SKO_BASIS_MONOMIAL, "newton": SKO_BASIS_NEWTON}
     if basis not in bases:
         raise ValueError(f"unknown basis {basis!r}")

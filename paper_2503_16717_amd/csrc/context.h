@@ -181,6 +181,8 @@ struct sko_ctx_s {
     unsigned tickets = 0;        // reduce-kernel arrivals on the workspace counter since it was zeroed
     // sko_autotune_orth: workgroups per CU per (pass kernel, log2 of its strip count)
     std::map<std::pair<const void*, int>, int> grid_wpc;
+    // private stream on which launch graphs are captured (created on first use)
+    hipStream_t cap_stream = nullptr;
 };
 
 namespace sko {

@@ -52,6 +52,11 @@ struct GmCtx {
     // cycle's Ritz values (newton_on from then on)
     double* newton = nullptr;
     bool newton_on = false;
+    // launch graphs of the one-stage blocks, one per block position (null: eager launches);
+    // cap_st: the private stream the launches are captured on
+    std::vector<hipGraphExec_t>* graphs = nullptr;
+    hipStream_t cap_st = nullptr;
+    unsigned* counter = nullptr;  // reduction arrival counter (zeroed around each graph)
     BlockBufs bb;
     int* status;
     int grid_cap;
@@ -222,23 +227,87 @@ sko_status gm_op(GmCtx& g, GmSmallArgs a) {
     return SKO_OK;
 }
 
+// The launches of one one-stage block at basis position k: matrix powers, BCGS2, the
+// Hessenberg step; then the implicit residual and the status word to the pinned host words.
+sko_status one_stage_block_launches(GmCtx& g, Engine& e, int k) {
+    sko_status s;
+    if ((s = mpk(g, k, g.s))) return s;
+    void* Vk = col_ptr(g, k);
+    g.phase(PhaseTimer::ORTH);
+    if ((s = one_stage_block(e, g.bb, g.intra, k, g.Q, g.ld, Vk, g.ld, Vk, g.ld, g.coef, g.m + 1, k))) return s;
+    GmSmallArgs a{};
+    a.op = GM_BLOCK;
+    a.kk = k;
+    a.do_lsq = 1;
+    if ((s = gm_op(g, a))) return s;
+    if (g.pt) g.pt->stop(g.st);
+    SKO_HIP(hipMemcpyAsync(g.host, g.res, sizeof(double), hipMemcpyDeviceToHost, g.st));
+    SKO_HIP(hipMemcpyAsync(reinterpret_cast<int*>(g.host + 4), g.status, sizeof(int), hipMemcpyDeviceToHost, g.st));
+    return SKO_OK;
+}
+
+// Ends a stream capture on every return path (a failed capture leaves no stream capturing).
+struct CaptureGuard {
+    hipStream_t st;
+    bool active = false;
+    hipGraph_t graph = nullptr;
+    explicit CaptureGuard(hipStream_t s) : st(s) {}
+    hipError_t begin() {
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        active = e == hipSuccess;
+        return e;
+    }
+    hipError_t end() {
+        active = false;
+        return hipStreamEndCapture(st, &graph);
+    }
+    ~CaptureGuard() {
+        if (active) (void)hipStreamEndCapture(st, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+// Block at position k through its launch graph: captured (on the private stream) the first
+// time the position is reached in this solve, replayed on the solve's stream after that.  The
+// reduction tickets are counted from zero inside the graph, which zeroes the counter at its
+// start and end.
+sko_status one_stage_block_graph(GmCtx& g, Engine& e, int k) {
+    hipGraphExec_t& ge = (*g.graphs)[k / g.s];
+    if (!ge) {
+        const hipStream_t st0 = g.st;
+        CaptureGuard cap(g.cap_st);
+        SKO_HIP(cap.begin());
+        g.st = e.st = g.cap_st;
+        unsigned tickets = 0;
+        unsigned* saved = e.tickets;
+        e.tickets = &tickets;
+        sko_status s = SKO_OK;
+        if (launch_zero(g.counter, sizeof(unsigned), g.st) != hipSuccess) s = SKO_EDEVICE;
+        if (!s) s = one_stage_block_launches(g, e, k);
+        if (!s && launch_zero(g.counter, sizeof(unsigned), g.st) != hipSuccess) s = SKO_EDEVICE;
+        g.st = e.st = st0;
+        e.tickets = saved;
+        const hipError_t ce = cap.end();
+        if (s) return s;
+        if (ce != hipSuccess) return SKO_EDEVICE;
+        SKO_HIP(hipGraphInstantiate(&ge, cap.graph, nullptr, nullptr, 0));
+    }
+    SKO_HIP(hipGraphLaunch(ge, g.st));
+    *e.tickets = 0;  // the graph left the counter at zero
+    return SKO_OK;
+}
+
 // One cycle; returns the basis size k reached (y[0:k] on the device), or 0 on breakdown.
 sko_status cycle_one_stage(GmCtx& g, Engine& e, double bnorm, double tol, sko_gmres_info& inf, int64_t maxiter,
                            int* k_out) {
     int k = 0;
     sko_status s;
     while (k < g.m) {
-        if ((s = mpk(g, k, g.s))) return s;
-        void* Vk = col_ptr(g, k);
-        g.phase(PhaseTimer::ORTH);
-        if ((s = one_stage_block(e, g.bb, g.intra, k, g.Q, g.ld, Vk, g.ld, Vk, g.ld, g.coef, g.m + 1, k))) return s;
-        GmSmallArgs a{};
-        a.op = GM_BLOCK;
-        a.kk = k;
-        a.do_lsq = 1;
-        if ((s = gm_op(g, a))) return s;
-        int status = 0;
-        if ((s = read_scalars(g, g.res, 1, &status))) return s;
+        if ((s = g.graphs ? one_stage_block_graph(g, e, k) : one_stage_block_launches(g, e, k))) return s;
+        SKO_HIP(hipStreamSynchronize(g.st));
+        g.c->prof.flush();
+        if (g.pt) g.pt->flush();
+        const int status = *reinterpret_cast<int*>(g.host + 4);
         inf.iters += g.s;
         k += g.s;
         if (status) {
@@ -540,6 +609,23 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     e.gmax = gmax;
     e.status = g.status;
     e.counter = reinterpret_cast<unsigned*>(g.status + 16);
+    g.counter = e.counter;
+    // launch graphs for the one-stage blocks (not while launches are timed one by one)
+    std::vector<hipGraphExec_t> graphs;
+    struct GraphsGuard {
+        std::vector<hipGraphExec_t>& v;
+        ~GraphsGuard() {
+            for (hipGraphExec_t ge : v)
+                if (ge) (void)hipGraphExecDestroy(ge);
+        }
+    } graphs_guard{graphs};
+    if (!g.two && !o->eager && !c->prof.on && !pt.on) {
+        if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return SKO_EDEVICE;
+        graphs.assign(g.m / g.s, nullptr);
+        g.graphs = &graphs;
+        g.cap_st = c->cap_stream;
+    }
     Engine e1(c, A->n, 1, false, g.sk);
     e1.partials = e.partials;
     e1.part_stride = part_stride;
@@ -629,6 +715,12 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
                 g.phase(PhaseTimer::SMALL);
                 SKO_HIP(launch_ritz(ra, kreached, g.newton, g.st));
                 g.newton_on = true;
+                // the captured blocks ran the monomial steps: capture again
+                for (hipGraphExec_t& ge : graphs)
+                    if (ge) {
+                        SKO_HIP(hipGraphExecDestroy(ge));
+                        ge = nullptr;
+                    }
             }
             {
                 g.phase(PhaseTimer::SMALL);
