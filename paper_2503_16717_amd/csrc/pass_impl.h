@@ -414,7 +414,80 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
             } else {
                 __syncthreads();
             }
-            if constexpr (MF) {
+            if constexpr (SP4 && MT == 8) {
+                // ---------------- phase B, sparse-sign sketch on bucketed 4 x 4 x 4 blocks ----------------
+                // (sketches of more than 64 rows; for up to 64 rows the rows-in-order form below
+                // issues fewer instructions)
+                // Block b of instruction (m, cb) produces sketch rows 16m + 4b .. 16m + 4b + 3 (its
+                // "quarter" q = b) and takes its 4 K rows from its own list: the wave's rows that
+                // have a nonzero in that quarter, in ascending order.  A row has one nonzero per
+                // slot block of B sketch rows, so it belongs to about 4 / B of a tile's quarters
+                // (one of four for B = 16), and the blocks multiply mostly nonzero operands instead
+                // of one nonzero in sixteen.  Lists hold lane indices (bytes) in this wave's part
+                // of the cross-wave tile buffer (the 4 * 64 doubles its final sums use, so a wave
+                // that finishes first writes only over its own lists); counts are wave-uniform.
+                constexpr int WROWS = STRIP / C::NWAVE;  // rows this wave staged (64 or 128)
+                static_assert(MT * 4 * 64 <= 4 * 64 * (int)sizeof(double), "lists exceed the wave's region");
+                const int wrow0 = wave * WROWS;
+                unsigned char* lst = reinterpret_cast<unsigned char*>(pred + wave * 4 * 64);
+                const int B = a.sk_k / a.sk_zeta;
+                const int q = (lane >> 2) & 3, kk = lane >> 4, i4 = lane & 3;
+#pragma unroll 1
+                for (int ch = 0; ch < WROWS / 64; ++ch) {
+                    const int r = wrow0 + ch * 64 + lane;  // strip-local row of this lane
+                    // quarters (m, q) of the launch's sketch rows holding a nonzero of row r
+                    unsigned member = 0u;
+                    if (base + r < n) {
+                        const uint64_t h = hs[r];
+                        for (int t = 0; t < a.sk_zeta; ++t) {
+                            const unsigned b8 = (unsigned)(h >> (8 * t)) & 0xffu;
+                            const int g = t * B + (int)(((b8 >> 1) * (unsigned)B) >> 7) - a.red_row0;
+                            if (g >= 0 && g < 16 * MT) member |= 1u << (g >> 2);
+                        }
+                    }
+                    unsigned cnt[MT][4];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+#pragma unroll
+                        for (int qq = 0; qq < 4; ++qq) {
+                            const bool in = (member >> (4 * m + qq)) & 1u;
+                            const uint64_t bal = __ballot(in);
+                            cnt[m][qq] = (unsigned)__popcll(bal);
+                            if (in) {
+                                const unsigned pos =
+                                    __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                                lst[(m * 4 + qq) * 64 + pos] = (unsigned char)lane;
+                            }
+                        }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        const unsigned c0 = cnt[m][0], c1 = cnt[m][1], c2 = cnt[m][2], c3 = cnt[m][3];
+                        const unsigned cmax = max(max(c0, c1), max(c2, c3));
+                        const unsigned myc = q == 0 ? c0 : q == 1 ? c1 : q == 2 ? c2 : c3;
+#pragma unroll 1
+                        for (unsigned it = 0; 4 * it < cmax; ++it) {
+                            const unsigned idx = 4 * it + kk;
+                            const bool live = idx < myc;
+                            const int rr = wrow0 + ch * 64 + (live ? (int)lst[(m * 4 + q) * 64 + idx] : 0);
+                            const uint64_t h = hs[rr];
+                            const unsigned hw = sk_half[m] ? (unsigned)(h >> 32) : (unsigned)h;
+                            const unsigned b8 = (hw >> sk_off[m]) & 0xffu;
+                            // +-1.0 from the sign bit (bit 0 of the byte), 0.0 off the slot
+                            const unsigned top = (live && (b8 - sk_lo[m]) < sk_wid[m]) ? ((b8 << 31) | 0x3FF00000u) : 0u;
+                            const double av = __hiloint2double((int)top, 0);
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) {
+                                const int col = 4 * cb + i4;
+                                const double bx = (live && col < W) ? (double)xs[col * LDX + rr] : 0.0;
+                                acc4[m * CB + cb] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bx, acc4[m * CB + cb], 0, 0, 0);
+                            }
+                        }
+                    }
+                }
+            } else if constexpr (MF) {
                 // ---------------- phase B, MFMA tiles ----------------
                 const int g = lane >> 4, ci = lane & 15;
                 const TQ* Qp = static_cast<const TQ*>(a.Qp);
