@@ -22,6 +22,11 @@ template <typename T>
 __device__ __forceinline__ double ld_(const T* p) {
     return static_cast<double>(*p);
 }
+// Streamed operands read exactly once (the staged copy of a workgroup's matrix values and
+// column indices) are loaded non-temporally, so they do not push the gathered vector out of
+// the L2.  (The lanes-per-row kernels read each line of them in two passes and keep normal
+// loads.)
+__device__ __forceinline__ int32_t ldnt_i(const int32_t* p) { return __builtin_nontemporal_load(p); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -96,8 +101,8 @@ __device__ __forceinline__ void spmv_staged_body(int64_t n, const int32_t* __res
         const bool staged = cnt <= STAGE;
         if (staged)
             for (int i = tid; i < cnt; i += NT) {
-                sv[i] = val[e0 + i];
-                sc[i] = colind[e0 + i];
+                sv[i] = __builtin_nontemporal_load(val + e0 + i);
+                sc[i] = ldnt_i(colind + e0 + i);
             }
         __syncthreads();
         const int64_t row = base + tid;
@@ -699,15 +704,17 @@ __global__ void __launch_bounds__(NT) gm_small_kernel_batched(const GmSmallArgs 
     gm_small_body(a);
 }
 
-// Kernel choice (measured on the 7-point 192^3 matrix, ~7 entries per row): FP64 values
-// run fastest with 4 lanes per row, FP32 values with one row per thread over an LDS-staged
-// nonzero range; rows much longer than 8 entries go to 8 lanes per row.
+// Kernel choice (measured on the 7-point 192^3 matrix, ~7 entries per row): one row per
+// thread over an LDS-staged nonzero range, one workgroup per NT rows (no grid stride, so
+// workgroups waiting at the staging barriers leave room for others), is fastest for FP64
+// and FP32 values (FP64: 161 us against 183 us for 4 lanes per row under a capped grid);
+// rows much longer than 8 entries go to 8 lanes per row.
 enum SpmvKind { SPMV_L2, SPMV_L4, SPMV_L8, SPMV_STAGED };
 
 template <typename TV>
 SpmvKind spmv_kind(double avg) {
     if (avg > 12.0) return SPMV_L8;
-    if (sizeof(TV) == 4 && avg <= 8.0) return SPMV_STAGED;
+    if (avg <= 8.0) return SPMV_STAGED;
     return avg > 3.0 ? SPMV_L4 : SPMV_L2;
 }
 
@@ -719,7 +726,8 @@ hipError_t spmv_dispatch(int64_t n, double avg, const int32_t* rp, const int32_t
     const SpmvKind k = spmv_kind<TV>(avg);
     const int rpb = spmv_rows_per_block(k);
     const int64_t groups = (n + rpb - 1) / rpb;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, grid_cap));
+    const int64_t cap = k == SPMV_STAGED ? std::max<int64_t>(grid_cap, (int64_t)1 << 30) : grid_cap;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, cap));
     switch (k) {
         case SPMV_L8:
             hipLaunchKernelGGL((spmv_kernel<8, TV, TX, TY>), dim3(grid), dim3(NT), 0, st, n, rp, ci, v, x, y, ns);

@@ -2,7 +2,7 @@
 
     python -m paper_2503_16717_amd.rocprof_summary stats KERNEL_STATS_CSV [--top N]
     python -m paper_2503_16717_amd.rocprof_summary traffic --fetch CSV --write CSV \\
-        --copy-fetch CSV --copy-write CSV --copy-bytes BYTES
+        --copy-fetch CSV --copy-write CSV --copy-bytes BYTES [--all --source FILE --top N]
     python -m paper_2503_16717_amd.rocprof_summary last KERNEL_TRACE_CSV --kernel NAME --last N
 
 `stats` lists the kernels of a `--kernel-trace --stats` run by total time.  `traffic`
@@ -11,7 +11,9 @@ per launch of each pass kernel.  Each counter is scaled by the factor that makes
 the known size of a plain device copy (`bench.py --copy-calibration`: read and written
 bytes per launch given by --copy-bytes).  Pass kernels are named as the library's
 profiler names them (sko_profile_read), and each row carries the digest of the pass-kernel
-source, so a reader can tell whether the counts still describe the current kernels.
+source, so a reader can tell whether the counts still describe the current kernels.  With
+--all every kernel is listed (others under their demangled names), with the digest of the
+source file given by --source.
 """
 from __future__ import annotations
 
@@ -99,15 +101,17 @@ def cmd_traffic(a) -> int:
     fw = a.copy_bytes / (cw[copy[0]][1] * 1024.0)
     pf = counter_means(a.fetch, "FETCH_SIZE")
     pw = counter_means(a.write, "WRITE_SIZE")
-    dig = source_digest()
+    dig = source_digest(a.source) if a.source else source_digest()
     print(f"Calibration (plain copy of {a.copy_bytes} bytes): FETCH_SIZE x {fr:.4f}, WRITE_SIZE x {fw:.4f}")
     print()
     print("| kernel | HBM read bytes / launch | HBM write bytes / launch | HBM bytes / launch | source digest |")
     print("|---|---:|---:|---:|---|")
+    shown = 0
     for k in sorted(pf, key=lambda k: -pf[k][1] * pf[k][0]):
-        name = profiler_name(k)
-        if not name or k not in pw:
+        name = short_name(k) if a.all else profiler_name(k)
+        if not name or k not in pw or (a.top and shown >= a.top):
             continue
+        shown += 1
         rb = pf[k][1] * 1024.0 * fr
         wb = pw[k][1] * 1024.0 * fw
         print(f"| {name} | {rb:.4g} | {wb:.4g} | {rb + wb:.6g} | {dig} |")
@@ -126,6 +130,9 @@ def main(argv=None) -> int:
     t.add_argument("--copy-fetch", required=True)
     t.add_argument("--copy-write", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--all", action="store_true", help="list every kernel, not only the pass kernels")
+    t.add_argument("--source", default=None, help="source file whose digest the rows carry")
+    t.add_argument("--top", type=int, default=0, help="at most this many kernels (by total fetch)")
     la = sub.add_parser("last")
     la.add_argument("csv")
     la.add_argument("--kernel", required=True)
