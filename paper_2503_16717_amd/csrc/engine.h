@@ -146,7 +146,7 @@ struct Engine {
     // handed to `small`.
     sko_status gemm_reduction(const void* A, int64_t lda, int ma, const void* B, int64_t ldb, int nbc,
                               SmallArgs small, int64_t ldo) {
-        const int G = gemm_grid(A == B && lda == ldb && ma == nbc);
+        const int G = gemm_grid(A == B && lda == ldb && ma == nbc, ma, nbc);
         const int ev = pbegin(
             [&] { return std::string("wide_gemm_tn ") + (A == B ? "gram" : "proj") + " f" + (f32 ? "32" : "64"); },
             rows_bytes * (A == B ? ma : ma + nbc) * (f32 ? 4.0 : 8.0));
@@ -196,12 +196,12 @@ struct Engine {
     // launch already holds many systems).
     // One system: at most the resident workgroups, so no second, partly idle round of
     // workgroups follows the first (each walks its 16-row groups).
-    int gemm_grid(bool sym) const {
+    int gemm_grid(bool sym, int ma, int nbc) const {
         const int64_t ns32 = (n + 31) / 32;
         const int64_t want = br ? (ns32 + 63) / 64 : ns32;
         int64_t cap = skinny_gemm_grid_cap();
         if (!br) {
-            const int res = skinny_gemm_resident(sym, f32);
+            const int res = skinny_gemm_resident(sym, f32, ma, nbc);
             if (res > 0) cap = std::min<int64_t>(cap, res);
         }
         return (int)std::max<int64_t>(1, std::min<int64_t>(want, cap));

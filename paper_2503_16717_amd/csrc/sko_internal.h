@@ -204,9 +204,9 @@ hipError_t launch_skinny_gemm_tn(int64_t n, const void* A, int64_t lda, int ma,
                                  double* partials, int grid, hipStream_t stream,
                                  const BatchReloc* br = nullptr);
 int skinny_gemm_grid_cap();
-// Workgroups of the one-system wide Gram (sym) / projection kernel that are resident at once
-// (-1 if the runtime cannot tell).
-int skinny_gemm_resident(bool sym, bool f32);
+// Workgroups of the one-system wide Gram (sym) / projection kernel for ma x nb outputs that
+// are resident at once (-1 if the runtime cannot tell).
+int skinny_gemm_resident(bool sym, bool f32, int ma, int nb);
 
 // Row-wise X = (Y - Qu Cu) * R^{-1} for wide blocks (w <= 64); used by the big-panel
 // close of the two-stage scheme.  Rpk is R in the packed form of SmallArgs::Rpk (null: no

@@ -207,12 +207,12 @@ __device__ __forceinline__ void load_piece(const T* col, bool live, bool vec, in
 // (lines already requested) and is zeroed after the loads, so all loads of the group are in
 // flight together.  A branch per piece would wait for each load in turn.  The group at the
 // end of the rows keeps the guarded loads.
-template <typename T>
+template <typename T, int NTL>
 __device__ __forceinline__ void load_pieces(const T* base, int64_t ld, int m, int ci, bool vec, bool full,
-                                            int64_t row0, int64_t n, double (&v)[4][4]) {
+                                            int64_t row0, int64_t n, double (&v)[NTL][4]) {
     if (full && vec) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < NTL; ++t) {
             const int c = 16 * t + ci;
             const T* col = base + (int64_t)(c < m ? c : m - 1) * ld;
             if constexpr (sizeof(T) == 8) {
@@ -232,61 +232,61 @@ __device__ __forceinline__ void load_pieces(const T* base, int64_t ld, int m, in
         }
     } else if (full) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < NTL; ++t) {
             const int c = 16 * t + ci;
             const T* col = base + (int64_t)(c < m ? c : m - 1) * ld;
 #pragma unroll
             for (int u = 0; u < 4; ++u) v[t][u] = ldv(col + row0 + u);
         }
     } else {
-        const int tiles = (m + 15) / 16;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < NTL; ++t) {
             const int c = 16 * t + ci;
-            if (t < tiles) load_piece(base + (int64_t)(c < m ? c : 0) * ld, c < m, vec, row0, n, v[t]);
+            load_piece(base + (int64_t)(c < m ? c : 0) * ld, c < m, vec, row0, n, v[t]);
         }
         return;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NTL; ++t)
         if (16 * t + ci >= m) v[t][0] = v[t][1] = v[t][2] = v[t][3] = 0.0;
 }
 
-template <typename T, bool SYM>
+// TA = ceil(ma / 16) and TB = ceil(nb / 16) tiles at compile time: only the accumulators
+// and pieces a launch uses occupy registers (more resident waves to cover the load latency).
+template <typename T, bool SYM, int TA, int TB>
 __device__ __forceinline__ void gemm_body(const GemmArgs& ga) {
     __shared__ double red[4 * 64 * (GT / 64)];
     const int64_t n = ga.n;
     const T* A = static_cast<const T*>(ga.A);
     const T* B = static_cast<const T*>(ga.B);
     const int ma = ga.ma, nb = ga.nb;
-    const int ta = (ma + 15) / 16, tb = (nb + 15) / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ci = lane & 15, g = lane >> 4;
     constexpr int NW = GT / 64;
     // 4-row pieces can be read as vectors when every column start is aligned
     const bool veca = (ga.lda % 4) == 0 && ((uintptr_t)A % (4 * sizeof(T))) == 0;
     const bool vecb = (ga.ldb % 4) == 0 && ((uintptr_t)B % (4 * sizeof(T))) == 0;
-    double4_t acc[4][4];
+    double4_t acc[TA][TB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TA; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < TB; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
     const int64_t ngroups = (n + 15) / 16;
     for (int64_t grp = (int64_t)blockIdx.x * NW + wave; grp < ngroups; grp += (int64_t)gridDim.x * NW) {
         const int64_t row0 = grp * 16 + 4 * g;
         const bool full = grp * 16 + 16 <= n;
-        double a[4][4], b[SYM ? 1 : 4][4];
-        load_pieces(A, ga.lda, ma, ci, veca, full, row0, n, a);
-        if constexpr (!SYM) load_pieces(B, ga.ldb, nb, ci, vecb, full, row0, n, b);
+        double a[TA][4], b[SYM ? 1 : TB][4];
+        load_pieces<T, TA>(A, ga.lda, ma, ci, veca, full, row0, n, a);
+        if constexpr (!SYM) load_pieces<T, TB>(B, ga.ldb, nb, ci, vecb, full, row0, n, b);
         // row step outermost: consecutive MFMAs go to different accumulator tiles
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TA; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (i < ta && j < tb && (!SYM || i <= j)) {
+                for (int j = 0; j < TB; ++j) {
+                    if (!SYM || i <= j) {
                         const double bj = SYM ? a[j][u] : b[SYM ? 0 : j][u];
                         acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][u], bj, acc[i][j], 0, 0, 0);
                     }
@@ -297,10 +297,10 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& ga) {
     // summed through LDS in wave order and written once per workgroup
     double* out = ga.partials + (int64_t)blockIdx.x * ga.stride;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TA; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (i < ta && j < tb && (!SYM || i <= j)) {
+        for (int j = 0; j < TB; ++j) {
+            if (!SYM || i <= j) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) red[(wave * 4 + r) * 64 + lane] = acc[i][j][r];
                 __syncthreads();
@@ -318,12 +318,12 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& ga) {
         }
 }
 
-template <typename T, bool SYM>
+template <typename T, bool SYM, int TA, int TB>
 __global__ void __launch_bounds__(GT) wide_gemm_tn_kernel(const GemmArgs ga) {
-    gemm_body<T, SYM>(ga);
+    gemm_body<T, SYM, TA, TB>(ga);
 }
 
-template <typename T, bool SYM>
+template <typename T, bool SYM, int TA, int TB>
 __global__ void __launch_bounds__(GT) wide_gemm_tn_kernel_batched(const GemmArgs t, const BatchReloc br) {
     const int sys = batch_system(br);
     const BatchSys& d = br.sys[sys];
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(GT) wide_gemm_tn_kernel_batched(const GemmArgs
     ga.B = batch_ptr(br, sys, d, t.B);
     ga.ldb = batch_ld(br, d, t.ldb);
     ga.partials = batch_ptr(br, sys, d, t.partials);
-    gemm_body<T, SYM>(ga);
+    gemm_body<T, SYM, TA, TB>(ga);
 }
 
 template <int WB, typename T, bool UPD, bool TRSM>
@@ -377,12 +377,53 @@ hipError_t rowop_dispatch(const RowopArgs& ra, hipStream_t st, const BatchReloc*
     return hipGetLastError();
 }
 
+template <typename T, bool SYM, int TA, int TB>
+void gemm_launch_t(const GemmArgs& ga, int grid, hipStream_t st, const BatchReloc* br) {
+    if (br)
+        hipLaunchKernelGGL((wide_gemm_tn_kernel_batched<T, SYM, TA, TB>), dim3(grid, br->nact), dim3(GT), 0, st, ga,
+                           *br);
+    else
+        hipLaunchKernelGGL((wide_gemm_tn_kernel<T, SYM, TA, TB>), dim3(grid), dim3(GT), 0, st, ga);
+}
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Calls f(IC<TA>, IC<TB>) for the tile counts of ma x nb (each 1..4).
+template <typename F>
+void tile_dispatch(int ma, int nb, F&& f) {
+    const int ta = (ma + 15) / 16, tb = (nb + 15) / 16;
+    auto inner = [&](auto tac) {
+        switch (tb) {
+            case 1: f(tac, IC<1>{}); break;
+            case 2: f(tac, IC<2>{}); break;
+            case 3: f(tac, IC<3>{}); break;
+            default: f(tac, IC<4>{}); break;
+        }
+    };
+    switch (ta) {
+        case 1: inner(IC<1>{}); break;
+        case 2: inner(IC<2>{}); break;
+        case 3: inner(IC<3>{}); break;
+        default: inner(IC<4>{}); break;
+    }
+}
+
 template <typename T, bool SYM>
 void gemm_launch(const GemmArgs& ga, int grid, hipStream_t st, const BatchReloc* br) {
-    if (br)
-        hipLaunchKernelGGL((wide_gemm_tn_kernel_batched<T, SYM>), dim3(grid, br->nact), dim3(GT), 0, st, ga, *br);
-    else
-        hipLaunchKernelGGL((wide_gemm_tn_kernel<T, SYM>), dim3(grid), dim3(GT), 0, st, ga);
+    if constexpr (SYM) {
+        // A == B: square tile grid
+        switch ((ga.ma + 15) / 16) {
+            case 1: gemm_launch_t<T, true, 1, 1>(ga, grid, st, br); break;
+            case 2: gemm_launch_t<T, true, 2, 2>(ga, grid, st, br); break;
+            case 3: gemm_launch_t<T, true, 3, 3>(ga, grid, st, br); break;
+            default: gemm_launch_t<T, true, 4, 4>(ga, grid, st, br); break;
+        }
+    } else {
+        tile_dispatch(ga.ma, ga.nb, [&](auto ta, auto tb) {
+            gemm_launch_t<T, false, decltype(ta)::value, decltype(tb)::value>(ga, grid, st, br);
+        });
+    }
 }
 
 }  // namespace
@@ -401,15 +442,15 @@ hipError_t launch_wide_rowop(int64_t n, int W, bool f32, const void* Y, int64_t 
     return f32 ? rowop_dispatch<64, float>(ra, st, br) : rowop_dispatch<64, double>(ra, st, br);
 }
 
-template <typename T, bool SYM>
-int gemm_resident() {
+template <typename T, bool SYM, int TA, int TB>
+int gemm_resident_t() {
     static int cached = 0;
     if (cached == 0) {
         int dev = 0, cus = 0, per_cu = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(&wide_gemm_tn_kernel<T, SYM>), GT, 0) == hipSuccess &&
+                &per_cu, reinterpret_cast<const void*>(&wide_gemm_tn_kernel<T, SYM, TA, TB>), GT, 0) == hipSuccess &&
             per_cu > 0 && cus > 0)
             cached = per_cu * cus;
         else
@@ -418,9 +459,26 @@ int gemm_resident() {
     return cached;
 }
 
-int skinny_gemm_resident(bool sym, bool f32) {
-    if (f32) return sym ? gemm_resident<float, true>() : gemm_resident<float, false>();
-    return sym ? gemm_resident<double, true>() : gemm_resident<double, false>();
+template <typename T>
+int gemm_resident(bool sym, int ma, int nb) {
+    int r = -1;
+    if (sym) {
+        switch ((ma + 15) / 16) {
+            case 1: r = gemm_resident_t<T, true, 1, 1>(); break;
+            case 2: r = gemm_resident_t<T, true, 2, 2>(); break;
+            case 3: r = gemm_resident_t<T, true, 3, 3>(); break;
+            default: r = gemm_resident_t<T, true, 4, 4>(); break;
+        }
+    } else {
+        tile_dispatch(ma, nb, [&](auto ta, auto tb) {
+            r = gemm_resident_t<T, false, decltype(ta)::value, decltype(tb)::value>();
+        });
+    }
+    return r;
+}
+
+int skinny_gemm_resident(bool sym, bool f32, int ma, int nb) {
+    return f32 ? gemm_resident<float>(sym, ma, nb) : gemm_resident<double>(sym, ma, nb);
 }
 
 int skinny_gemm_grid_cap() {
