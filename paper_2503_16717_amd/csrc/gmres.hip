@@ -421,29 +421,48 @@ sko_status two_stage_bigclose(GmCtx& g, Engine& e, int k0) {
         sm.R = g.Rh;
         sm.Rpk = g.Rpk;
         if ((s = e.gemm_reduction(Qb, g.ld, Wb, Qb, g.ld, Wb, sm, Wb))) return s;
+    }
+    // With the second pass, each row operation also accumulates the reduction that follows
+    // it (the projection on the previous big panels, or the second Gram matrix).
+    const bool proj2 = g.reorth && k0 > 0;
+    const bool fuse_proj = proj2 && k0 <= 64;
+    SmallArgs chol2{};
+    chol2.op = OP_CHOL;
+    chol2.w = Wb;
+    chol2.col0 = k0;
+    chol2.out = g.Gb;
+    chol2.R = g.Rt;
+    chol2.Rpk = g.Rpk;
+    if (g.reorth && !proj2) {
+        if ((s = e.rowop_reduction(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rpk, Qb, g.ld, nullptr, 0, 0, chol2, Wb)))
+            return s;
+    } else if (fuse_proj) {
+        SmallArgs sp2{};
+        sp2.op = OP_STORE;
+        sp2.w = Wb;
+        sp2.out = g.C2b;
+        if ((s = e.rowop_reduction(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rpk, Qb, g.ld, col_ptr(g, 0), g.ld, k0, sp2,
+                                   k0)))
+            return s;
+    } else {
         if ((s = e.rowop(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rpk, Qb, g.ld))) return s;
     }
-    const bool proj2 = g.reorth && k0 > 0;
     if (g.reorth) {
         if (proj2) {
-            for (int a0 = 0; a0 < k0; a0 += 64) {
-                const int ma = std::min(64, k0 - a0);
-                SmallArgs sm{};
-                sm.op = OP_STORE;
-                sm.w = Wb;
-                sm.out = g.C2b + a0;
-                if ((s = e.gemm_reduction(col_ptr(g, a0), g.ld, ma, Qb, g.ld, Wb, sm, k0))) return s;
+            if (!fuse_proj) {
+                for (int a0 = 0; a0 < k0; a0 += 64) {
+                    const int ma = std::min(64, k0 - a0);
+                    SmallArgs sm{};
+                    sm.op = OP_STORE;
+                    sm.w = Wb;
+                    sm.out = g.C2b + a0;
+                    if ((s = e.gemm_reduction(col_ptr(g, a0), g.ld, ma, Qb, g.ld, Wb, sm, k0))) return s;
+                }
             }
-            if ((s = e.rowop(Wb, Qb, g.ld, g.Q, g.ld, k0, g.C2b, nullptr, Qb, g.ld))) return s;
+            if ((s = e.rowop_reduction(Wb, Qb, g.ld, g.Q, g.ld, k0, g.C2b, nullptr, Qb, g.ld, nullptr, 0, 0, chol2,
+                                       Wb)))
+                return s;
         }
-        SmallArgs sm{};
-        sm.op = OP_CHOL;
-        sm.w = Wb;
-        sm.col0 = k0;
-        sm.out = g.Gb;
-        sm.R = g.Rt;
-        sm.Rpk = g.Rpk;
-        if ((s = e.gemm_reduction(Qb, g.ld, Wb, Qb, g.ld, Wb, sm, Wb))) return s;
         if ((s = e.rowop(Wb, Qb, g.ld, nullptr, 0, 0, nullptr, g.Rpk, Qb, g.ld))) return s;
     }
     GmSmallArgs ga{};

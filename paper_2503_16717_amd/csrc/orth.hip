@@ -844,7 +844,26 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
                 if ((s = e.plain(key, a))) return s;
             }
         }
-        // ---- second stage: CholQR of the big panel (Line 15), BCGS + CholQR (Line 19)
+        // ---- second stage: CholQR of the big panel (Line 15), BCGS + CholQR (Line 19).
+        // With the second pass, each row operation also accumulates the reduction that
+        // follows it (the projection on the previous big panels, or the second Gram matrix),
+        // so the panel it writes is not read again for that reduction.
+        SmallArgs chol2{};   // second CholQR (R_t), which also assembles the final R
+        chol2.op = OP_CHOL;
+        chol2.w = Wb;
+        chol2.col0 = p_old;
+        chol2.out = Gb;
+        chol2.R = Rt;
+        chol2.Rpk = Rpk;
+        chol2.assemble = 1;
+        chol2.Ra = Rh;
+        chol2.Rb = Rbar;
+        chol2.C1 = p_old > 0 ? C : nullptr;
+        chol2.C2 = p_old > 0 ? C2 : nullptr;
+        chol2.p = p_old;
+        chol2.Rout = Rfull + (int64_t)p_old * N;
+        chol2.ldr = N;
+        const bool fuse_proj = reorth && p_old > 0 && p_old <= 64;
         {
             SmallArgs sm{};
             sm.op = OP_CHOL;
@@ -864,37 +883,43 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
                 sm.ldr = N;
             }
             if ((s = e.gemm_reduction(Qb, ldq, Wb, Qb, ldq, Wb, sm, Wb))) return s;
-            if ((s = e.rowop(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rpk, Qb, ldq))) return s;
+            if (reorth && p_old == 0) {
+                // Q_b = Q_bar R_h^{-1} and its Gram matrix -> R_t
+                if ((s = e.rowop_reduction(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rpk, Qb, ldq, nullptr, 0, 0, chol2,
+                                           Wb)))
+                    return s;
+            } else if (fuse_proj) {
+                // Q_b = Q_bar R_h^{-1} and C_2 = Q_old^T Q_b
+                SmallArgs sp2{};
+                sp2.op = OP_STORE;
+                sp2.w = Wb;
+                sp2.out = C2;
+                if ((s = e.rowop_reduction(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rpk, Qb, ldq, Q, ldq, p_old, sp2,
+                                           p_old)))
+                    return s;
+            } else {
+                if ((s = e.rowop(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rpk, Qb, ldq))) return s;
+            }
         }
         if (reorth) {
             if (p_old > 0) {
-                for (int a0 = 0; a0 < p_old; a0 += 64) {
-                    const int ma = std::min(64, p_old - a0);
-                    SmallArgs sm{};
-                    sm.op = OP_STORE;
-                    sm.w = Wb;
-                    sm.out = C2 + a0;
-                    if ((s = e.gemm_reduction(offset_elems(Q, (int64_t)a0 * ldq, f32), ldq, ma, Qb, ldq, Wb, sm, p_old)))
-                        return s;
+                if (!fuse_proj) {
+                    for (int a0 = 0; a0 < p_old; a0 += 64) {
+                        const int ma = std::min(64, p_old - a0);
+                        SmallArgs sm{};
+                        sm.op = OP_STORE;
+                        sm.w = Wb;
+                        sm.out = C2 + a0;
+                        if ((s = e.gemm_reduction(offset_elems(Q, (int64_t)a0 * ldq, f32), ldq, ma, Qb, ldq, Wb, sm,
+                                                  p_old)))
+                            return s;
+                    }
                 }
-                if ((s = e.rowop(Wb, Qb, ldq, Q, ldq, p_old, C2, nullptr, Qb, ldq))) return s;
+                // Q_b -= Q_old C_2 and its Gram matrix -> R_t
+                if ((s = e.rowop_reduction(Wb, Qb, ldq, Q, ldq, p_old, C2, nullptr, Qb, ldq, nullptr, 0, 0, chol2,
+                                           Wb)))
+                    return s;
             }
-            SmallArgs sm{};
-            sm.op = OP_CHOL;
-            sm.w = Wb;
-            sm.col0 = p_old;
-            sm.out = Gb;
-            sm.R = Rt;
-            sm.Rpk = Rpk;
-            sm.assemble = 1;
-            sm.Ra = Rh;
-            sm.Rb = Rbar;
-            sm.C1 = p_old > 0 ? C : nullptr;
-            sm.C2 = p_old > 0 ? C2 : nullptr;
-            sm.p = p_old;
-            sm.Rout = Rfull + (int64_t)p_old * N;
-            sm.ldr = N;
-            if ((s = e.gemm_reduction(Qb, ldq, Wb, Qb, ldq, Wb, sm, Wb))) return s;
             if ((s = e.rowop(Wb, Qb, ldq, nullptr, 0, 0, nullptr, Rpk, Qb, ldq))) return s;
         }
     }
