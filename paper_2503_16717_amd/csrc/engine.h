@@ -176,8 +176,8 @@ struct Engine {
     // gemm_reduction does.  Batched launches keep the two sweeps apart, and so do panels
     // wider than kFusedMaxW (the row and the accumulators no longer fit two waves' registers),
     // projections on more than 48 columns, and the update form: its Q_u loads and the MFMA
-    // accumulators together leave too few waves resident (measured 5.6 ms against 4.3 ms for
-    // the two sweeps, 36 columns, n = 2^24).
+    // accumulators together run slower than two sweeps (measured 5.4-5.6 ms against 4.3 ms,
+    // 36 columns on 36, n = 2^24, with four or eight update columns in flight).
     sko_status rowop_reduction(int Wd, const void* Y, int64_t ldy, const void* Qu, int64_t ldqu, int pu,
                                const double* Cu, const double* Rpk, void* X, int64_t ldx, const void* E, int64_t lde,
                                int me, SmallArgs small, int64_t ldo) {

@@ -205,16 +205,21 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[i][c] = 0.0;
     // MFMA accumulators: tile m covers output rows 16m..16m+15 of this launch
-    // The sparse sketch runs on v_mfma_f64_4x4x4 (four independent 4 x 4 x 4 blocks per
-    // instruction, the same FP64 rate as 16 x 16 x 4): a block covers 4 sketch rows x 4 columns
-    // of x, so narrow panels do not pay for 16 padded columns.  Instruction (m, cb) holds the
-    // sketch rows 16m..16m+15 (block b: rows 16m + 4b..+3) and the columns 4cb..4cb+3.
+    // The sparse sketch, and the projection and dense sketch of blocks up to 12 columns, run
+    // on v_mfma_f64_4x4x4 (four independent 4 x 4 x 4 blocks per instruction, the same FP64
+    // rate as 16 x 16 x 4): a block covers 4 output rows x 4 columns of x, so narrow blocks
+    // do not pay for 16 padded columns (three instructions of a quarter of the time instead
+    // of one 16 x 16 x 4 for 11 columns).  Instruction (m, cb) holds the output rows
+    // 16m..16m+15 (block b: rows 16m + 4b..+3) and the columns 4cb..4cb+3.  The A operand
+    // uses the lane mapping of the 16 x 16 x 4 tile (lane l: output row 16m + l % 16, data
+    // row l / 16), so the same pieces feed both forms.
     constexpr bool SP4 = RED == RED_SKETCH_SPARSE;
+    constexpr bool B4 = MF && (SP4 || W <= 12);
     constexpr int CB = (W + 3) / 4;
-    double4_t dacc[(MF && !SP4) ? MT : 1];
-    double acc4[SP4 ? MT * CB : 1];
+    double4_t dacc[(MF && !B4) ? MT : 1];
+    double acc4[B4 ? MT * CB : 1];
 #pragma unroll
-    for (int i = 0; i < (SP4 ? MT * CB : 1); ++i) acc4[i] = 0.0;
+    for (int i = 0; i < (B4 ? MT * CB : 1); ++i) acc4[i] = 0.0;
     const int ntiles = (a.red_rows + 15) / 16;
 #pragma unroll
     for (int m = 0; m < (MF ? MT : 1); ++m) dacc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
@@ -507,9 +512,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                     const bool full = base + r0 + 3 < n;
                     // B operands: 16 x 16 x 4 tiles take column ci of the 4 rows; 4 x 4 x 4 blocks
                     // take column 4cb + lane % 4
-                    double bv[SP4 ? 1 : 4];
-                    double bq[SP4 ? CB : 1][4];
-                    if constexpr (SP4) {
+                    double bv[B4 ? 1 : 4];
+                    double bq[B4 ? CB : 1][4];
+                    if constexpr (B4) {
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb) {
                             const int col = 4 * cb + (lane & 3);
@@ -565,9 +570,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                                 else
                                     load_col4(Th + (int64_t)col * a.ldtheta + base + r0, vec, full, base + r0, n, av);
                             }
+                            if constexpr (B4) {
 #pragma unroll
-                            for (int u = 0; u < 4; ++u)
-                                dacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], dacc[m], 0, 0, 0);
+                                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                                    for (int cb = 0; cb < CB; ++cb)
+                                        acc4[m * CB + cb] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[u], bq[cb][u],
+                                                                                               acc4[m * CB + cb], 0, 0, 0);
+                            } else {
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    dacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], dacc[m], 0, 0, 0);
+                            }
                         }
                     }
                     }
@@ -601,9 +615,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
         }
     }
 
-    if constexpr (SP4) {
+    if constexpr (B4) {
         // v_mfma_f64_4x4x4 output layout (measured on gfx950): D[i][j] of block b sits in lane
-        // 4b + j + 16i, so lane l holds sketch row 16m + 4((l % 16) / 4) + l / 16 and column
+        // 4b + j + 16i, so lane l holds output row 16m + 4((l % 16) / 4) + l / 16 and column
         // 4cb + l % 4 of instruction (m, cb).  The waves' values are summed through LDS in wave
         // order.
         double* out = a.partials + (int64_t)wg * a.part_stride;

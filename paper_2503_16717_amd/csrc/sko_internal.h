@@ -209,8 +209,7 @@ int skinny_gemm_grid_cap();
 int skinny_gemm_resident(bool sym, bool f32, int ma, int nb);
 
 // The wide row operation with the following reduction in the same sweep: X as
-// launch_wide_rowop (W <= kFusedMaxW; either the update or the solve, or, with E, the solve
-// only), plus the per-workgroup partials of E^T X (E: n x me tall, me <= 48; stride me * W)
+// launch_wide_rowop (W <= kFusedMaxW; the solve only, no update), plus the per-workgroup partials of E^T X (E: n x me tall, me <= 48; stride me * W)
 // or, with E null, of the Gram X^T X (upper tiles; stride W * W).  The grid (workgroups =
 // partial blocks, at most skinny_gemm_grid_cap()) is returned in grid_out.  One system only.
 constexpr int kFusedMaxW = 40;

@@ -81,56 +81,59 @@ __device__ __forceinline__ RawRows<R, T> load_raw(const T* p) {
     return r;
 }
 
-// x[r][c] -= sum_{u<4} Q(r, j + u) C(j + u, c): one group of four update columns.
-template <int W, int R, typename T>
-__device__ __forceinline__ void update_group(double (&x)[R][W], const RawRows<R, T> (&q)[4], CD C, int j, int pu,
+// x[r][c] -= sum_{u<G} Q(r, j + u) C(j + u, c): one group of G update columns.
+template <int W, int R, typename T, int G>
+__device__ __forceinline__ void update_group(double (&x)[R][W], const RawRows<R, T> (&q)[G], CD C, int j, int pu,
                                              int w) {
 #pragma unroll
     for (int c = 0; c < W; ++c) {
         if (c < w) {
-            double cu[4];
+            double cu[G];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) cu[u] = C[j + u + c * pu];
+            for (int u = 0; u < G; ++u) cu[u] = C[j + u + c * pu];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double v = x[r][c];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v -= static_cast<double>(q[u].v[r]) * cu[u];
+                for (int u = 0; u < G; ++u) v -= static_cast<double>(q[u].v[r]) * cu[u];
                 x[r][c] = v;
             }
         }
     }
 }
 
-template <int R, typename T>
-__device__ __forceinline__ void load_group(RawRows<R, T> (&q)[4], const T* Q, int64_t ldq, int j) {
+template <int R, typename T, int G>
+__device__ __forceinline__ void load_group(RawRows<R, T> (&q)[G], const T* Q, int64_t ldq, int j) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) q[u] = load_raw<R>(Q + (int64_t)(j + u) * ldq);
+    for (int u = 0; u < G; ++u) q[u] = load_raw<R>(Q + (int64_t)(j + u) * ldq);
     // keep the loads here: the scheduler would otherwise sink them to their first use
     __builtin_amdgcn_sched_barrier(0);
 }
 
 // x[r][c] -= sum_j Q(r, j) C(j, c) over the pu columns of Q for the w <= W live columns of
-// x (Q points at this thread's first row; all R rows lie below n).  Columns go in groups of four, and the next group's
-// loads are issued before the current group's FMAs (two register buffers in turn), so each
-// wave keeps a group of loads in flight while it computes.  The subtraction order (j
-// ascending per output column) is the same as in the generic path.
+// x (Q points at this thread's first row; all R rows lie below n).  Columns go in groups of
+// G, and the next group's loads are issued before the current group's FMAs (two register
+// buffers in turn), so each wave keeps a group of loads in flight while it computes.  Single
+// rows of 4-byte storage take groups of eight: each load moves half the bytes of a double
+// one, so twice as many are kept in flight.  The subtraction order (j ascending per output
+// column) is the same as in the generic path and does not depend on G.
 template <int W, int R, typename T>
 __device__ __forceinline__ void update_rows(double (&x)[R][W], const T* Q, int64_t ldq, int pu, CD C, int w = W) {
+    constexpr int G = (sizeof(T) == 4 && R == 1) ? 8 : 4;
     int j = 0;
-    if (pu >= 4) {
-        RawRows<R, T> qa[4], qb[4];
-        load_group<R, T>(qa, Q, ldq, 0);
+    if (pu >= G) {
+        RawRows<R, T> qa[G], qb[G];
+        load_group<R, T, G>(qa, Q, ldq, 0);
         // the last group's look-ahead loads it again (from cache) instead of branching
         while (true) {
-            load_group<R, T>(qb, Q, ldq, min(j + 4, pu - 4));
-            update_group<W, R, T>(x, qa, C, j, pu, w);
-            j += 4;
-            if (j + 4 > pu) break;
-            load_group<R, T>(qa, Q, ldq, min(j + 4, pu - 4));
-            update_group<W, R, T>(x, qb, C, j, pu, w);
-            j += 4;
-            if (j + 4 > pu) break;
+            load_group<R, T, G>(qb, Q, ldq, min(j + G, pu - G));
+            update_group<W, R, T, G>(x, qa, C, j, pu, w);
+            j += G;
+            if (j + G > pu) break;
+            load_group<R, T, G>(qa, Q, ldq, min(j + G, pu - G));
+            update_group<W, R, T, G>(x, qb, C, j, pu, w);
+            j += G;
+            if (j + G > pu) break;
         }
     }
     for (; j < pu; ++j) {
