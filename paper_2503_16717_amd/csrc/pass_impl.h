@@ -227,10 +227,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
     // Sparse sketch: the MFMA A operand of lane l is Theta[row][16m + l % 16]; that sketch
     // row is slot j of hash byte t (B = k / zeta slots per byte).  Byte b selects slot
     // floor((b >> 1) B / 128), which equals j exactly when 2 ceil(128 j / B) <= b <
-    // 2 ceil(128 (j + 1) / B); the lane keeps, per tile, which 32-bit half of the hash holds
-    // byte t, the byte's bit offset there, and that range (empty for lanes past the sketch).
-    unsigned sk_half[RED == RED_SKETCH_SPARSE ? MT : 1];
-    unsigned sk_off[RED == RED_SKETCH_SPARSE ? MT : 1];
+    // 2 ceil(128 (j + 1) / B); the lane keeps, per tile, the v_perm_b32 selector that moves
+    // byte t of the 64-bit hash into the low byte of a zeroed word (one instruction), and that
+    // range (empty for lanes past the sketch).
+    unsigned sk_sel[RED == RED_SKETCH_SPARSE ? MT : 1];
     unsigned sk_lo[RED == RED_SKETCH_SPARSE ? MT : 1];
     unsigned sk_wid[RED == RED_SKETCH_SPARSE ? MT : 1];
     if constexpr (RED == RED_SKETCH_SPARSE) {
@@ -243,8 +243,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
             const int j = g - t * B;
             const bool live = loc < a.red_rows && t < a.sk_zeta;
             const unsigned lo = (unsigned)((128 * j + B - 1) / B), hi = (unsigned)((128 * (j + 1) + B - 1) / B);
-            sk_half[m] = live ? (unsigned)(t >> 2) : 0u;
-            sk_off[m] = live ? 8u * (unsigned)(t & 3) : 0u;
+            // selector bytes: byte t of {hi word, lo word} (0..7), then three zero bytes (0x0c)
+            sk_sel[m] = live ? (0x0c0c0c00u | (unsigned)t) : 0x0c0c0c0cu;
             sk_lo[m] = 2u * lo;
             sk_wid[m] = live ? 2u * (hi - lo) : 0u;
         }
@@ -478,8 +478,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                             const bool live = idx < myc;
                             const int rr = wrow0 + ch * 64 + (live ? (int)lst[(m * 4 + q) * 64 + idx] : 0);
                             const uint64_t h = hs[rr];
-                            const unsigned hw = sk_half[m] ? (unsigned)(h >> 32) : (unsigned)h;
-                            const unsigned b8 = (hw >> sk_off[m]) & 0xffu;
+                            const unsigned b8 = __builtin_amdgcn_perm((unsigned)(h >> 32), (unsigned)h, sk_sel[m]);
                             // +-1.0 from the sign bit (bit 0 of the byte), 0.0 off the slot
                             const unsigned top = (live && (b8 - sk_lo[m]) < sk_wid[m]) ? ((b8 << 31) | 0x3FF00000u) : 0u;
                             const double av = __hiloint2double((int)top, 0);
@@ -544,7 +543,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                         for (int m = 0; m < MT; ++m)
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
-                                const unsigned b = ((sk_half[m] ? hh[u] : hl[u]) >> sk_off[m]) & 0xffu;
+                                const unsigned b = __builtin_amdgcn_perm(hh[u], hl[u], sk_sel[m]);
                                 // +-1.0 from the sign bit (bit 0 of the byte), 0.0 off the slot
                                 top[m][u] = (b - sk_lo[m]) < sk_wid[m] ? ((b << 31) | 0x3FF00000u) : 0u;
                             }
