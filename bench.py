@@ -67,8 +67,12 @@ def alg_bytes_two_stage_method(n: int, nb: int, w: int, ppb: int, eb: int = 8) -
 
 def alg_bytes_two_stage(n: int, nb: int, w: int, ppb: int, eb: int = 8) -> float:
     """Pass schedule the library executes for the two-stage scheme (each tall operand once
-    per pass; the big-panel close runs unfused)."""
+    per pass).  In the big-panel close of panels up to 40 columns, the row solve by R_h also
+    accumulates the reduction that follows it: the Gram matrix of the second CholQR (first
+    big panel) or the projection on up to 48 previous columns; the row update and its Gram
+    matrix stay two sweeps."""
     Wb = ppb * w
+    fuse = Wb <= 40
     cols = 0
     for big in range(nb // ppb):
         p = big * Wb
@@ -79,10 +83,16 @@ def alg_bytes_two_stage(n: int, nb: int, w: int, ppb: int, eb: int = 8) -> float
             else:
                 cols += w              # sketch of V_i
             cols += (i * w + w) + w    # forward substitution, written
-        cols += Wb + 2 * Wb            # Gram of Q_bar, Q_hat = Q_bar R^{-1}
+        cols += Wb + 2 * Wb            # Gram of Q_bar, Q_hat = Q_bar R^{-1} (+ fused reduction)
         if p > 0:
-            cols += (p + Wb) + (p + 2 * Wb)  # C_2 = Q_old^T Q_hat, V_bar = Q_hat - Q_old C_2
-        cols += Wb + 2 * Wb            # Gram of V_bar, Q_P = V_bar R^{-1}
+            if fuse and p <= 48:
+                cols += p              # Q_old read by the fused C_2 = Q_old^T Q_hat
+            else:
+                cols += p + Wb         # C_2 = Q_old^T Q_hat
+            cols += (p + 2 * Wb) + Wb  # V_bar = Q_hat - Q_old C_2, Gram of V_bar
+        elif not fuse:
+            cols += Wb                 # Gram of Q_hat
+        cols += 2 * Wb                 # Q_P = V_bar R^{-1}
     return float(cols) * n * eb
 
 
