@@ -48,6 +48,7 @@ sko_status sko_destroy(sko_ctx c) {
     if (c->ws) (void)hipFree(c->ws);
     if (c->status_host) (void)hipHostFree(c->status_host);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->zc_host) (void)hipHostFree(c->zc_host);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->prof.release();
     delete c;

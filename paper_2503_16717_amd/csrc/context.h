@@ -177,8 +177,12 @@ struct sko_ctx_s {
     int* status_host = nullptr;  // pinned host word for the breakdown status
     void* pinned = nullptr;      // pinned staging for small results copied to the host
     size_t pinned_bytes = 0;
+    // four host words that kernels write directly (mapped, coherent pinned memory): the
+    // one-stage GMRES block publishes its implicit residual and status word there, so no
+    // copy launch follows each block.  zc_dev: the device's address of the same words.
+    double* zc_host = nullptr;
+    double* zc_dev = nullptr;
     sko::Profiler prof;
-    unsigned tickets = 0;        // reduce-kernel arrivals on the workspace counter since it was zeroed
     // sko_autotune_orth: workgroups per CU per (pass kernel, log2 of its strip count)
     std::map<std::pair<const void*, int>, int> grid_wpc;
     // private stream on which launch graphs are captured (created on first use)
@@ -243,6 +247,22 @@ inline sko_status ensure_pinned(sko_ctx c, size_t bytes) {
         return SKO_ENOMEM;
     }
     c->pinned_bytes = bytes;
+    return SKO_OK;
+}
+
+// The mapped host words kernels write results into (allocated once per context).
+inline sko_status ensure_zerocopy(sko_ctx c) {
+    if (c->zc_host) return SKO_OK;
+    void* h = nullptr;
+    if (hipHostMalloc(&h, 4 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        return SKO_ENOMEM;
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        (void)hipHostFree(h);
+        return SKO_EDEVICE;
+    }
+    c->zc_host = static_cast<double*>(h);
+    c->zc_dev = static_cast<double*>(d);
     return SKO_OK;
 }
 

@@ -39,15 +39,12 @@ struct Engine {
     // total, for the byte accounting.
     const BatchReloc* br = nullptr;
     double rows_bytes = 0.0;
-    // Host count of arrivals on `counter` since it was zeroed (the context's, unless a call
-    // keeps its own).
-    unsigned* tickets;
     // false: no profiler events (no host-side bookkeeping at all) for this engine's launches
     bool profile = true;
     int sk_rows;  // sketch rows the passes produce (k_count for a Count-Gauss sketch)
 
     Engine(sko_ctx c_, int64_t n_, int W_, bool f32_, const sko_sketch& sk_)
-        : c(c_), st(c_->stream), n(n_), W(W_), f32(f32_), sk(sk_), tickets(&c_->tickets) {
+        : c(c_), st(c_->stream), n(n_), W(W_), f32(f32_), sk(sk_) {
         nstrips = (n + kPassThreads - 1) / kPassThreads;
         rows_bytes = (double)n;
         sk_rows = sketch_plan(sk).rows;
@@ -130,7 +127,6 @@ struct Engine {
         ra.count = rows_total * W;
         ra.scale = scale;
         ra.counter = counter;
-        ra.ticket0 = take_tickets(*tickets, ra.count, br);
         ra.rows = ra.count;
         ra.ldo = ra.count;
         ra.small = small;
@@ -159,7 +155,6 @@ struct Engine {
         ra.count = ma * nbc;
         ra.scale = 1.0;
         ra.counter = counter;
-        ra.ticket0 = take_tickets(*tickets, ra.count, br);
         ra.rows = ma;
         ra.ldo = ldo;
         ra.small = small;
@@ -204,7 +199,6 @@ struct Engine {
         ra.count = ma * Wd;
         ra.scale = 1.0;
         ra.counter = counter;
-        ra.ticket0 = take_tickets(*tickets, ra.count, br);
         ra.rows = ma;
         ra.ldo = ldo;
         ra.small = small;

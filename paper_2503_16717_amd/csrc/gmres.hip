@@ -56,7 +56,7 @@ struct GmCtx {
     // cap_st: the private stream the launches are captured on
     std::vector<hipGraphExec_t>* graphs = nullptr;
     hipStream_t cap_st = nullptr;
-    unsigned* counter = nullptr;  // reduction arrival counter (zeroed around each graph)
+    unsigned* counter = nullptr;  // reduction arrival counter (each reduction leaves it at zero)
     BlockBufs bb;
     int* status;
     int grid_cap;
@@ -228,7 +228,8 @@ sko_status gm_op(GmCtx& g, GmSmallArgs a) {
 }
 
 // The launches of one one-stage block at basis position k: matrix powers, BCGS2, the
-// Hessenberg step; then the implicit residual and the status word to the pinned host words.
+// Hessenberg step, which also writes the implicit residual and the status word into the
+// context's mapped host words.
 sko_status one_stage_block_launches(GmCtx& g, Engine& e, int k) {
     sko_status s;
     if ((s = mpk(g, k, g.s))) return s;
@@ -239,10 +240,11 @@ sko_status one_stage_block_launches(GmCtx& g, Engine& e, int k) {
     a.op = GM_BLOCK;
     a.kk = k;
     a.do_lsq = 1;
+    // the step itself writes the residual and the status word into the mapped host words
+    a.host_res = g.c->zc_dev;
+    a.status_in = g.status;
     if ((s = gm_op(g, a))) return s;
     if (g.pt) g.pt->stop(g.st);
-    SKO_HIP(hipMemcpyAsync(g.host, g.res, sizeof(double), hipMemcpyDeviceToHost, g.st));
-    SKO_HIP(hipMemcpyAsync(reinterpret_cast<int*>(g.host + 4), g.status, sizeof(int), hipMemcpyDeviceToHost, g.st));
     return SKO_OK;
 }
 
@@ -268,9 +270,8 @@ struct CaptureGuard {
 };
 
 // Block at position k through its launch graph: captured (on the private stream) the first
-// time the position is reached in this solve, replayed on the solve's stream after that.  The
-// reduction tickets are counted from zero inside the graph, which zeroes the counter at its
-// start and end.
+// time the position is reached in this solve, replayed on the solve's stream after that.  Every
+// reduction leaves its arrival counter at zero, so a replay needs no clearing launch.
 sko_status one_stage_block_graph(GmCtx& g, Engine& e, int k) {
     hipGraphExec_t& ge = (*g.graphs)[k / g.s];
     if (!ge) {
@@ -278,22 +279,14 @@ sko_status one_stage_block_graph(GmCtx& g, Engine& e, int k) {
         CaptureGuard cap(g.cap_st);
         SKO_HIP(cap.begin());
         g.st = e.st = g.cap_st;
-        unsigned tickets = 0;
-        unsigned* saved = e.tickets;
-        e.tickets = &tickets;
-        sko_status s = SKO_OK;
-        if (launch_zero(g.counter, sizeof(unsigned), g.st) != hipSuccess) s = SKO_EDEVICE;
-        if (!s) s = one_stage_block_launches(g, e, k);
-        if (!s && launch_zero(g.counter, sizeof(unsigned), g.st) != hipSuccess) s = SKO_EDEVICE;
+        const sko_status s = one_stage_block_launches(g, e, k);
         g.st = e.st = st0;
-        e.tickets = saved;
         const hipError_t ce = cap.end();
         if (s) return s;
         if (ce != hipSuccess) return SKO_EDEVICE;
         SKO_HIP(hipGraphInstantiate(&ge, cap.graph, nullptr, nullptr, 0));
     }
     SKO_HIP(hipGraphLaunch(ge, g.st));
-    *e.tickets = 0;  // the graph left the counter at zero
     return SKO_OK;
 }
 
@@ -307,7 +300,8 @@ sko_status cycle_one_stage(GmCtx& g, Engine& e, double bnorm, double tol, sko_gm
         SKO_HIP(hipStreamSynchronize(g.st));
         g.c->prof.flush();
         if (g.pt) g.pt->flush();
-        const int status = *reinterpret_cast<int*>(g.host + 4);
+        const volatile double* zc = g.c->zc_host;
+        const int status = reinterpret_cast<const volatile int*>(zc + 1)[0];
         inf.iters += g.s;
         k += g.s;
         if (status) {
@@ -315,7 +309,7 @@ sko_status cycle_one_stage(GmCtx& g, Engine& e, double bnorm, double tol, sko_gm
             *k_out = 0;
             return SKO_EBREAKDOWN;
         }
-        inf.relres_implicit = g.host[0] / bnorm;
+        inf.relres_implicit = zc[0] / bnorm;
         if (inf.relres_implicit <= tol || inf.iters >= maxiter) break;
     }
     *k_out = k;
@@ -587,6 +581,7 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     sko_status s = ensure_workspace(c, ar.used());
     if (s) return s;
     if ((s = ensure_pinned(c, 64))) return s;
+    if ((s = ensure_zerocopy(c))) return s;
     g.host = static_cast<double*>(c->pinned);
     g.newton = ar.at<double>(o_newton);
     g.Q = ar.at<void>(o_Q);
@@ -601,7 +596,6 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
     g.pt = &pt;
     SKO_HIP(hipEventRecord(ev_total.a, g.st));
     SKO_HIP(launch_zero(g.status, 256, g.st));
-    c->tickets = 0;
 
     // ---- CSR structure check before any kernel indexes through it
     {
@@ -682,7 +676,6 @@ sko_status gmres_impl(sko_ctx c, const sko_csr* A, const double* b, double* x, c
                 ra.count = 1;
                 ra.scale = 1.0;
                 ra.counter = e.counter;
-                ra.ticket0 = take_tickets(c->tickets, 1, nullptr);
                 ra.rows = 1;
                 ra.ldo = 1;
                 ra.small.op = OP_CHOL;
@@ -960,7 +953,6 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
         e1.gmax = Gp;
         e1.status = gi.status;
         e1.counter = reinterpret_cast<unsigned*>(gi.status + 16);
-        c->tickets = 0;  // each system's counter is fresh
         if ((s = norm2(gi, e1, b[i], gi.bnorm))) return s;
     }
     if ((s = read_dbl(g.bnorm))) return s;
@@ -1013,8 +1005,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     e1f.counter = e.counter;
     e1f.br = &br;
 
-    // New active list (largest systems first, so their workgroups are dispatched first);
-    // the reduction counters restart from zero with it.
+    // New active list (largest systems first, so their workgroups are dispatched first).
     auto set_active = [&](std::vector<int> list) -> sko_status {
         std::sort(list.begin(), list.end(), [&](int a, int q) { return A[a].n > A[q].n || (A[a].n == A[q].n && a < q); });
         double nr = 0.0, nz = 0.0;
@@ -1041,8 +1032,7 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
         SKO_HIP(hipMemcpyAsync(blk_d, blk_h, sizeof(int) * (list.size() + 1), hipMemcpyHostToDevice, g.st));
         SKO_HIP(launch_zero_2d(small0 + st_off + 16 * sizeof(int), L.bytes, sizeof(unsigned), nsys, g.st));
         SKO_HIP(hipStreamSynchronize(g.st));
-        c->tickets = 0;
-        return SKO_OK;
+            return SKO_OK;
     };
 
     while (true) {
@@ -1065,7 +1055,6 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
             ra.count = 1;
             ra.scale = 1.0;
             ra.counter = e.counter;
-            ra.ticket0 = take_tickets(c->tickets, 1, &br);
             ra.rows = 1;
             ra.ldo = 1;
             ra.small.op = OP_CHOL;

@@ -71,6 +71,10 @@ struct GmSmallArgs {
     const double* C2;  // GM_BIGCLOSE: k0 x Wb or null
     // GM_BLOCK with the Newton basis: recurrence coefficients a (s) then b (s); null: monomial
     const double* newton;
+    // GM_BLOCK with least squares, one system: mapped host words that receive the implicit
+    // residual ([0]) and the status word (int at [1]) when the step ends (null: none)
+    double* host_res;
+    const int* status_in;
 };
 
 hipError_t launch_gm_small(const GmSmallArgs& a, hipStream_t st, const BatchReloc* br = nullptr);

@@ -28,6 +28,13 @@ __device__ __forceinline__ double ld_(const T* p) {
 // loads.)
 __device__ __forceinline__ int32_t ldnt_i(const int32_t* p) { return __builtin_nontemporal_load(p); }
 
+// Orders one wave's LDS accesses: writes before the barrier are seen by reads after it.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -439,15 +446,14 @@ __device__ void lsq(const GmSmallArgs& a, int k) {
     __syncthreads();
 }
 
-// lsq with T_in, H and g staged in LDS (rows 0..k, leading dimension k + 1): the row-wise
-// substitutions, the rotations and the back substitution then read no global memory.
-// Lds holds 2 k (k + 1) + (k + 1) doubles.
+// lsq with T_in, H and g staged in LDS (rows 0..k, leading dimension k + 1), k <= 62: the
+// workgroup loads them, then one wave forms H, applies the rotations and back-substitutes
+// without global memory or workgroup barriers.  Lds holds 2 k (k + 1) + (k + 1) doubles.
 __device__ void lsq_lds(const GmSmallArgs& a, int k, double* lds) {
     const int ld = a.m + 1, lh = k + 1;
     double* Hs = lds;
     double* Ts = lds + (int64_t)lh * k;
     double* gs = Ts + (int64_t)lh * k;
-    __shared__ double cs[2];
     // T_in into Ts and T_out into Hs (each row of H then overwrites its own T_out row),
     // eight loads of each in flight per thread
     for (int b = threadIdx.x; b < lh * k; b += 8 * NT) {
@@ -472,47 +478,52 @@ __device__ void lsq_lds(const GmSmallArgs& a, int k, double* lds) {
     }
     for (int i = threadIdx.x; i <= k; i += NT) gs[i] = a.g[i];
     __syncthreads();
-    // H[r, c] = (T_out[r, c] - sum_{q<c} H[r, q] T_in[q, c]) / T_in[c, c]
-    for (int r = threadIdx.x; r <= k; r += NT) {
-        for (int c = 0; c < k; ++c) {
-            double v = Hs[r + c * lh];
-            for (int q = 0; q < c; ++q) v -= Hs[r + q * lh] * Ts[q + c * lh];
-            Hs[r + c * lh] = v / Ts[c + c * lh];
+    // The rest runs on wave 0 alone (k + 1 <= 63 rows, k <= 62 columns: one lane each), in
+    // wave order, with no workgroup barrier per column.
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        // H = T_out T_in^{-1}, right-looking: lane r finishes H[r, c], then removes its term
+        // from the later columns of its row.  Each entry H[r, c2] is formed as
+        // T_out[r, c2] - H[r, 0] T_in[0, c2] - ... - H[r, c2 - 1] T_in[c2 - 1, c2], divided by
+        // T_in[c2, c2]: the row-wise recurrence, term for term.
+        if (lane <= k) {
+            for (int c = 0; c < k; ++c) {
+                const double h = Hs[lane + c * lh] / Ts[c + c * lh];
+                Hs[lane + c * lh] = h;
+#pragma unroll 4
+                for (int c2 = c + 1; c2 < k; ++c2) Hs[lane + c2 * lh] -= h * Ts[c + c2 * lh];
+            }
         }
-    }
-    __syncthreads();
-    for (int i = 0; i < k; ++i) {
-        if (threadIdx.x == 0) {
+        wave_lds_sync();
+        // Givens rotations, lane j owning column j; every lane forms the rotation itself
+        for (int i = 0; i < k; ++i) {
             const double x = Hs[i + i * lh], z = Hs[i + 1 + i * lh];
             const double rad = hypot(x, z);
-            cs[0] = rad == 0.0 ? 1.0 : x / rad;
-            cs[1] = rad == 0.0 ? 0.0 : z / rad;
+            const double c = rad == 0.0 ? 1.0 : x / rad;
+            const double sn = rad == 0.0 ? 0.0 : z / rad;
+            if (lane >= i && lane < k) {
+                const double top = Hs[i + lane * lh], bot = Hs[i + 1 + lane * lh];
+                Hs[i + lane * lh] = c * top + sn * bot;
+                Hs[i + 1 + lane * lh] = -sn * top + c * bot;
+            }
+            if (lane == 0) {
+                const double gi = gs[i], gj = gs[i + 1];
+                gs[i] = c * gi + sn * gj;
+                gs[i + 1] = -sn * gi + c * gj;
+            }
+            wave_lds_sync();
         }
-        __syncthreads();
-        const double c = cs[0], sn = cs[1];
-        for (int j = i + threadIdx.x; j < k; j += NT) {
-            const double top = Hs[i + j * lh], bot = Hs[i + 1 + j * lh];
-            Hs[i + j * lh] = c * top + sn * bot;
-            Hs[i + 1 + j * lh] = -sn * top + c * bot;
-        }
-        if (threadIdx.x == 0) {
-            const double gi = gs[i], gj = gs[i + 1];
-            gs[i] = c * gi + sn * gj;
-            gs[i + 1] = -sn * gi + c * gj;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        // y overwrites gs[0..k) from the bottom up
+        // back substitution by columns: lane i holds y[i]; y[i] is final once the columns to
+        // its right have been removed from it
+        double yv = lane < k ? gs[lane] : 0.0;
         for (int i = k - 1; i >= 0; --i) {
-            double v = gs[i];
-            for (int j = i + 1; j < k; ++j) v -= Hs[i + j * lh] * gs[j];
-            gs[i] = v / Hs[i + i * lh];
+            const double yi = __shfl(yv, i, 64) / Hs[i + i * lh];
+            if (lane == i) yv = yi;
+            if (lane < i) yv -= Hs[lane + i * lh] * yi;
         }
-        a.res[0] = fabs(gs[k]);
+        if (lane < k) a.y[lane] = yv;
+        if (lane == 0) a.res[0] = fabs(gs[k]);
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < k; i += NT) a.y[i] = gs[i];
     __syncthreads();
 }
 
@@ -556,6 +567,13 @@ __device__ __forceinline__ void gm_small_body(const GmSmallArgs& a) {
                 lsq_lds(a, kk + a.s, gm_dyn);
             else
                 lsq(a, kk + a.s);
+            // publish the residual (thread 0 wrote it) and the block's status word to the host
+            if (a.host_res && threadIdx.x == 0) {
+                volatile double* hr = a.host_res;
+                hr[0] = a.res[0];
+                reinterpret_cast<volatile int*>(a.host_res + 1)[0] = *a.status_in;
+                __threadfence_system();
+            }
         }
         return;
     }

@@ -475,7 +475,6 @@ sko_status orth_blocks_impl(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
     double* Rfull = ar.at<double>(L.rfull);
     SKO_HIP(launch_zero(e.status, 256, c->stream));
-    c->tickets = 0;
     SKO_HIP(launch_zero(Rfull, sizeof(double) * (size_t)N * N, c->stream));
     BlockBufs bb = carve(ar, L, N - w, k, w);
     for (int j = 0; j < nb; ++j) {
@@ -530,7 +529,6 @@ sko_status orth_block_run(sko_ctx c, const Arena& ar, const OneStageLayout& L, E
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
     double* Rcol = ar.at<double>(L.rfull);  // (p + w) x w, ld p + w
     SKO_HIP(launch_zero(e.status, 256, c->stream));
-    *e.tickets = 0;
     BlockBufs bb = carve(ar, L, p, k, w);
     *Rcol_out = Rcol;
     return one_stage_block(e, bb, o->intra, p, Q, ldq, V, ldv, Qo, ldqo, Rcol, p + w, 0);
@@ -584,8 +582,6 @@ sko_status orth_block_noalloc_impl(sko_ctx c, int64_t n, int32_t p, int32_t w, c
     if (L.total > kNoallocScratchBytes) return SKO_ESCRATCH;
     Arena ar(c, scratch);
     Engine e(c, n, w, f32, o->sketch);
-    unsigned tickets = 0;
-    e.tickets = &tickets;
     e.profile = false;
     double* Rcol = nullptr;
     s = orth_block_run(c, ar, L, e, n, p, w, Q, ldq, V, ldv, Qo, ldqo, o, &Rcol);
@@ -631,7 +627,6 @@ sko_status sketch_apply_impl(sko_ctx c, int64_t n, int32_t w, const void* X, int
     e.status = ar.at<int>(L.status);
     e.counter = reinterpret_cast<unsigned*>(e.status + 16);
     SKO_HIP(launch_zero(e.status, 256, c->stream));
-    c->tickets = 0;
     BlockBufs bb = carve(ar, L, k, sp.rows, w);
     PassArgs a{};
     a.Y = X;
@@ -716,7 +711,6 @@ sko_status two_stage_blocks(sko_ctx c, int64_t n, int32_t nb, int32_t w, const v
     double* Rpk = ar.at<double>(o_Rpk);  // packed copy of Rh, then of Rt, for the row solves
     double* Rfull = ar.at<double>(o_Rf);
     SKO_HIP(launch_zero(e.status, 256, c->stream));
-    c->tickets = 0;
     SKO_HIP(launch_zero(Rfull, sizeof(double) * (size_t)N * N, c->stream));
 
     const int red_sk = sp.red;

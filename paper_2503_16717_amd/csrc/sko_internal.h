@@ -150,11 +150,11 @@ struct ReduceArgs {
     int G;
     int count;
     double scale;
-    // Arrival ticket: the counter is zeroed once per call and never reset; the launch
-    // whose workgroups arrive with tickets [ticket0, ticket0 + grid) elects the one that
-    // draws ticket0 + grid - 1 as the last workgroup.
+    // Arrival counter, zero when the launch starts: the workgroup that draws ticket
+    // grid - 1 is the last one; it runs the small step and resets the counter to zero, so
+    // the next launch on it (stream order, so never concurrent) counts from zero again and
+    // no launch is needed to clear it (nor inside a captured graph).
     unsigned int* counter;
-    unsigned int ticket0;
     // Placement of reduced element e (= r + c * rows): small.out[r + c * ldo].  OP_STORE
     // may write into a sub-block of a larger matrix; the other ops need ldo == rows.
     int rows;
@@ -191,10 +191,6 @@ inline void sketch_small(SmallArgs& sm, const SketchPlan& sp) {
 // Number of workgroups launch_reduce uses for `count` reduced values.
 int reduce_grid(int count);
 
-// Ticket0 for a reduction launch over `count` values: the host's running count of arrivals
-// on the counter, advanced by the launch's workgroups when they take tickets (single-system
-// launches; batched launches run their small steps in a launch of their own, without one).
-unsigned take_tickets(unsigned& tickets, int count, const BatchReloc* br);
 hipError_t launch_reduce(const ReduceArgs& args, hipStream_t stream, const BatchReloc* br = nullptr);
 
 // Small dense kernels used outside a reduction.

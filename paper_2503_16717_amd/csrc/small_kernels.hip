@@ -540,7 +540,8 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
     __syncthreads();
     if (tid == 0) {
         const unsigned prev = atomicAdd(a.counter, 1u);
-        s_last = (prev == a.ticket0 + gridDim.x - 1) ? 1 : 0;
+        s_last = (prev == gridDim.x - 1) ? 1 : 0;
+        if (s_last) atomicExch(a.counter, 0u);  // every workgroup has arrived: reset for the next launch
     }
     __syncthreads();
     if (!s_last) return;
@@ -658,12 +659,6 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream, const BatchRel
         hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(RT), lds, stream, a);
     }
     return hipGetLastError();
-}
-
-unsigned take_tickets(unsigned& tickets, int count, const BatchReloc* br) {
-    const unsigned t0 = tickets;
-    if (!br) tickets += (unsigned)reduce_grid(count);
-    return t0;
 }
 
 hipError_t launch_assemble(const SmallArgs& s, double* rh, hipStream_t stream) {
