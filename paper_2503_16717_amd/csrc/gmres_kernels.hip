@@ -448,7 +448,7 @@ __device__ void lsq(const GmSmallArgs& a, int k) {
 
 // lsq with T_in, H and g staged in LDS (rows 0..k, leading dimension k + 1), k <= 62: the
 // workgroup loads them, then one wave forms H, applies the rotations and back-substitutes
-// without global memory or workgroup barriers.  Lds holds 2 k (k + 1) + (k + 1) doubles.
+// without global memory or workgroup barriers.  Lds holds 2 k (k + 1) + (k + 1) + k doubles.
 __device__ void lsq_lds(const GmSmallArgs& a, int k, double* lds) {
     const int ld = a.m + 1, lh = k + 1;
     double* Hs = lds;
@@ -482,25 +482,36 @@ __device__ void lsq_lds(const GmSmallArgs& a, int k, double* lds) {
     // wave order, with no workgroup barrier per column.
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
+        // reciprocals of T_in's diagonal, one per lane, off the sequential path below
+        double* rinv = gs + lh;  // k doubles past g (the LDS holds 2 k (k + 1) + (k + 1) + k)
+        if (lane < k) rinv[lane] = 1.0 / Ts[lane + lane * lh];
+        wave_lds_sync();
         // H = T_out T_in^{-1}, right-looking: lane r finishes H[r, c], then removes its term
         // from the later columns of its row.  Each entry H[r, c2] is formed as
-        // T_out[r, c2] - H[r, 0] T_in[0, c2] - ... - H[r, c2 - 1] T_in[c2 - 1, c2], divided by
-        // T_in[c2, c2]: the row-wise recurrence, term for term.
+        // (T_out[r, c2] - H[r, 0] T_in[0, c2] - ... - H[r, c2 - 1] T_in[c2 - 1, c2]) / T_in[c2, c2],
+        // the row-wise recurrence with the division taken as a product by the reciprocal.
         if (lane <= k) {
             for (int c = 0; c < k; ++c) {
-                const double h = Hs[lane + c * lh] / Ts[c + c * lh];
+                const double h = Hs[lane + c * lh] * rinv[c];
                 Hs[lane + c * lh] = h;
 #pragma unroll 4
                 for (int c2 = c + 1; c2 < k; ++c2) Hs[lane + c2 * lh] -= h * Ts[c + c2 * lh];
             }
         }
         wave_lds_sync();
-        // Givens rotations, lane j owning column j; every lane forms the rotation itself
+        // Givens rotations, lane j owning column j; every lane forms the rotation itself from
+        // 1 / sqrt(x^2 + z^2) (hardware estimate plus one Newton step: no division or hypot on
+        // the sequential path; the Hessenberg entries are far from the FP64 range limits)
         for (int i = 0; i < k; ++i) {
             const double x = Hs[i + i * lh], z = Hs[i + 1 + i * lh];
-            const double rad = hypot(x, z);
-            const double c = rad == 0.0 ? 1.0 : x / rad;
-            const double sn = rad == 0.0 ? 0.0 : z / rad;
+            const double ss = x * x + z * z;
+            double c = 1.0, sn = 0.0;
+            if (ss > 0.0) {
+                double r = __builtin_amdgcn_rsq(ss);
+                r = r * (1.5 - 0.5 * ss * r * r);
+                c = x * r;
+                sn = z * r;
+            }
             if (lane >= i && lane < k) {
                 const double top = Hs[i + lane * lh], bot = Hs[i + 1 + lane * lh];
                 Hs[i + lane * lh] = c * top + sn * bot;
@@ -514,10 +525,11 @@ __device__ void lsq_lds(const GmSmallArgs& a, int k, double* lds) {
             wave_lds_sync();
         }
         // back substitution by columns: lane i holds y[i]; y[i] is final once the columns to
-        // its right have been removed from it
+        // its right have been removed from it (the diagonal's reciprocals formed in parallel)
         double yv = lane < k ? gs[lane] : 0.0;
+        const double dinv = lane < k ? 1.0 / Hs[lane + lane * lh] : 0.0;
         for (int i = k - 1; i >= 0; --i) {
-            const double yi = __shfl(yv, i, 64) / Hs[i + i * lh];
+            const double yi = __shfl(yv, i, 64) * __shfl(dinv, i, 64);
             if (lane == i) yv = yi;
             if (lane < i) yv -= Hs[lane + i * lh] * yi;
         }
@@ -528,7 +540,7 @@ __device__ void lsq_lds(const GmSmallArgs& a, int k, double* lds) {
 }
 
 // Doubles of dynamic LDS the staged least squares needs for basis size up to m.
-constexpr int lsq_lds_doubles(int m) { return 2 * m * (m + 1) + (m + 1); }
+constexpr int lsq_lds_doubles(int m) { return 2 * m * (m + 1) + (m + 1) + m; }
 constexpr int kLsqLdsMax = 8000;  // 62.5 KiB
 
 __device__ __forceinline__ void gm_small_body(const GmSmallArgs& a) {
