@@ -168,21 +168,25 @@ struct Engine {
 
     // X = (Y - Qu Cu) R^{-1} (rowop) and, in the same sweep over X, C = E^T X (E: me <= 64
     // tall columns, solve only) or the Gram X^T X (E null), reduced into `small` as
-    // gemm_reduction does.  Batched launches keep the two sweeps apart, and so do panels
-    // wider than kFusedMaxW (the row and the accumulators no longer fit two waves' registers),
-    // projections on more than 48 columns, and the update form: its Q_u loads and the MFMA
-    // accumulators together run slower than two sweeps (measured 5.4-5.6 ms against 4.3 ms,
-    // 36 columns on 36, n = 2^24, with four or eight update columns in flight).
+    // gemm_reduction does.  Panels wider than kFusedMaxW keep the two sweeps apart (the row
+    // and the accumulators no longer fit two waves' registers), and so do projections on more
+    // than 48 columns and the update form: its Q_u loads and the MFMA accumulators together
+    // run slower than two sweeps (measured 5.4-5.6 ms against 4.3 ms, 36 columns on 36,
+    // n = 2^24, with four or eight update columns in flight).
     sko_status rowop_reduction(int Wd, const void* Y, int64_t ldy, const void* Qu, int64_t ldqu, int pu,
                                const double* Cu, const double* Rpk, void* X, int64_t ldx, const void* E, int64_t lde,
                                int me, SmallArgs small, int64_t ldo) {
-        if (br || pu > 0 || Wd > kFusedMaxW || (E && me > 48)) {
+        if (pu > 0 || Wd > kFusedMaxW || (E && me > 48)) {
             sko_status s = rowop(Wd, Y, ldy, Qu, ldqu, pu, Cu, Rpk, X, ldx);
             if (s) return s;
             return E ? gemm_reduction(E, lde, me, X, ldx, Wd, small, ldo) : gemm_reduction(X, ldx, Wd, X, ldx, Wd, small, ldo);
         }
         const int ma = E ? me : Wd;
-        int G = 0;
+        // batched: as many workgroups per system as the wide Gram / projection would take (its
+        // partial-sum regions), at most one per strip of the largest system
+        int G = br ? (int)std::max<int64_t>(1, std::min<int64_t>(gemm_grid(!E, ma, Wd),
+                                                                  (n + kFusedUnitRows - 1) / kFusedUnitRows))
+                   : 0;
         const int ev = pbegin(
             [&] {
                 return std::string("wide_rowop+") + (E ? "proj" : "gram") + " f" + (f32 ? "32" : "64") +
@@ -190,7 +194,7 @@ struct Engine {
             },
             rows_bytes * (2 * Wd + pu + (E ? me : 0)) * (f32 ? 4.0 : 8.0));
         SKO_HIP(launch_wide_rowop_reduce(n, Wd, f32, Y, ldy, Qu, ldqu, pu, Cu, Rpk, X, ldx, E, lde, me, partials, &G,
-                                         st));
+                                         st, br));
         pend(ev);
         ReduceArgs ra{};
         ra.partials = partials;
@@ -203,7 +207,7 @@ struct Engine {
         ra.ldo = ldo;
         ra.small = small;
         ra.small.status = status;
-        ra.unit_rows = kGemmUnitRows;
+        ra.unit_rows = kFusedUnitRows;
         const int ev2 = pbegin([&] { return std::string(reduce_name(small.op)); }, 8.0 * G * ra.count);
         SKO_HIP(launch_reduce(ra, st, br));
         pend(ev2);

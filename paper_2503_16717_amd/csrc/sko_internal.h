@@ -206,13 +206,16 @@ int skinny_gemm_resident(bool sym, bool f32, int ma, int nb);
 
 // The wide row operation with the following reduction in the same sweep: X as
 // launch_wide_rowop (W <= kFusedMaxW; the solve only, no update), plus the per-workgroup partials of E^T X (E: n x me tall, me <= 48; stride me * W)
-// or, with E null, of the Gram X^T X (upper tiles; stride W * W).  The grid (workgroups =
-// partial blocks, at most skinny_gemm_grid_cap()) is returned in grid_out.  One system only.
+// or, with E null, of the Gram X^T X (upper tiles; stride W * W).  One system: the grid
+// (workgroups = partial blocks, at most skinny_gemm_grid_cap()) is returned in *grid_out.
+// Batched (br): *grid_out workgroups per system are launched, and those past a system's
+// ceil(n / kFusedUnitRows) write no partials.
 constexpr int kFusedMaxW = 40;
+constexpr int kFusedUnitRows = 256;
 hipError_t launch_wide_rowop_reduce(int64_t n, int W, bool f32, const void* Y, int64_t ldy, const void* Qu,
                                     int64_t ldqu, int pu, const double* Cu, const double* Rpk, void* X, int64_t ldx,
                                     const void* E, int64_t lde, int me, double* partials, int* grid_out,
-                                    hipStream_t st);
+                                    hipStream_t st, const BatchReloc* br = nullptr);
 
 // Row-wise X = (Y - Qu Cu) * R^{-1} for wide blocks (w <= 64); used by the big-panel
 // close of the two-stage scheme.  Rpk is R in the packed form of SmallArgs::Rpk (null: no

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <mutex>
 
+#include "batch.h"
 #include "sko_internal.h"
 #include "uniform.h"
 #include "wide_common.h"
@@ -44,7 +45,7 @@ __device__ __forceinline__ void wave_sync() {
 // the row's values and the tile accumulators are live together, and up to 40 columns with up
 // to three tiles of E fit 256 VGPRs without spilling (wider panels keep the two sweeps apart).
 template <int WB, typename T, bool UPD, bool TRSM, int TE>
-__global__ void __launch_bounds__(ROW_NT, 2) wide_rowop_red_kernel(const FusedArgs fa) {
+__device__ __forceinline__ void rowop_red_body(const FusedArgs& fa, const int wg, const int nwg) {
     constexpr int TX = (WB + 15) / 16;  // 16-column tiles of X
     constexpr bool GRAM = TE == 0;
     constexpr int TA = GRAM ? TX : TE;
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(ROW_NT, 2) wide_rowop_red_kernel(const FusedAr
 #pragma unroll
         for (int j = 0; j < TX; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
-    for (int64_t r0 = (int64_t)blockIdx.x * ROW_NT; r0 < n; r0 += (int64_t)gridDim.x * ROW_NT) {
+    for (int64_t r0 = (int64_t)wg * ROW_NT; r0 < n; r0 += (int64_t)nwg * ROW_NT) {
         const int64_t row = r0 + tid;
         double xa[1][WB];
         double(&x)[WB] = xa[0];
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(ROW_NT, 2) wide_rowop_red_kernel(const FusedAr
     __syncthreads();
     double* red = stage;
     const int ma = GRAM ? w0 : fa.me;
-    double* out = fa.partials + (int64_t)blockIdx.x * fa.stride;
+    double* out = fa.partials + (int64_t)wg * fa.stride;
 #pragma unroll
     for (int i = 0; i < TA; ++i)
 #pragma unroll
@@ -169,6 +170,35 @@ __global__ void __launch_bounds__(ROW_NT, 2) wide_rowop_red_kernel(const FusedAr
 }
 
 template <int WB, typename T, bool UPD, bool TRSM, int TE>
+__global__ void __launch_bounds__(ROW_NT, 2) wide_rowop_red_kernel(const FusedArgs fa) {
+    rowop_red_body<WB, T, UPD, TRSM, TE>(fa, blockIdx.x, gridDim.x);
+}
+
+// Many systems at once (blockIdx.y): workgroup x walks strips x, x + gridDim.x, ... of its
+// system; workgroups past the system's strips write no partial sums (the batched reduction
+// reads the first ceil(n / ROW_NT) of them).
+template <int WB, typename T, bool UPD, bool TRSM, int TE>
+__global__ void __launch_bounds__(ROW_NT, 2) wide_rowop_red_kernel_batched(const FusedArgs t, const BatchReloc br) {
+    const int sys = batch_system(br);
+    const BatchSys& d = br.sys[sys];
+    if ((int64_t)blockIdx.x * ROW_NT >= d.n) return;
+    FusedArgs fa = t;
+    fa.ra.n = d.n;
+    fa.ra.Y = batch_ptr(br, sys, d, t.ra.Y);
+    fa.ra.ldy = batch_ld(br, d, t.ra.ldy);
+    fa.ra.Qu = batch_ptr(br, sys, d, t.ra.Qu);
+    fa.ra.ldqu = batch_ld(br, d, t.ra.ldqu);
+    fa.ra.Cu = batch_ptr(br, sys, d, t.ra.Cu);
+    fa.ra.Rpk = batch_ptr(br, sys, d, t.ra.Rpk);
+    fa.ra.X = batch_ptr(br, sys, d, t.ra.X);
+    fa.ra.ldx = batch_ld(br, d, t.ra.ldx);
+    fa.E = batch_ptr(br, sys, d, t.E);
+    fa.lde = batch_ld(br, d, t.lde);
+    fa.partials = batch_ptr(br, sys, d, t.partials);
+    rowop_red_body<WB, T, UPD, TRSM, TE>(fa, blockIdx.x, gridDim.x);
+}
+
+template <int WB, typename T, bool UPD, bool TRSM, int TE>
 int fused_resident() {
     static std::mutex mu;
     static int cached[64] = {};
@@ -189,31 +219,37 @@ int fused_resident() {
     return cached[dev];
 }
 
+// One system: as many workgroups as are resident (at most the partial-sum capacity), the
+// grid returned in *grid.  Batched (br): *grid workgroups per system, given by the caller.
 template <int WB, typename T, bool UPD, bool TRSM, int TE>
-hipError_t fused_launch(const FusedArgs& fa, int* grid_out, hipStream_t st) {
+hipError_t fused_launch(const FusedArgs& fa, int* grid, hipStream_t st, const BatchReloc* br) {
+    if (br) {
+        hipLaunchKernelGGL((wide_rowop_red_kernel_batched<WB, T, UPD, TRSM, TE>), dim3(*grid, br->nact), dim3(ROW_NT),
+                           0, st, fa, *br);
+        return hipGetLastError();
+    }
     const int64_t strips = (fa.ra.n + ROW_NT - 1) / ROW_NT;
     int64_t cap = skinny_gemm_grid_cap();  // the partial-sum buffers hold this many workgroups
     const int res = fused_resident<WB, T, UPD, TRSM, TE>();
     if (res > 0) cap = std::min<int64_t>(cap, res);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(strips, cap));
-    hipLaunchKernelGGL((wide_rowop_red_kernel<WB, T, UPD, TRSM, TE>), dim3(grid), dim3(ROW_NT), 0, st, fa);
-    *grid_out = grid;
+    *grid = (int)std::max<int64_t>(1, std::min<int64_t>(strips, cap));
+    hipLaunchKernelGGL((wide_rowop_red_kernel<WB, T, UPD, TRSM, TE>), dim3(*grid), dim3(ROW_NT), 0, st, fa);
     return hipGetLastError();
 }
 
 template <int WB, typename T>
-hipError_t fused_dispatch(const FusedArgs& fa, int* grid_out, hipStream_t st) {
+hipError_t fused_dispatch(const FusedArgs& fa, int* grid_out, hipStream_t st, const BatchReloc* br) {
     const bool upd = fa.ra.pu > 0, trsm = fa.ra.Rpk != nullptr;
     if (fa.E) {
         if (upd || !trsm) return hipErrorInvalidValue;
         switch ((fa.me + 15) / 16) {
-            case 1: return fused_launch<WB, T, false, true, 1>(fa, grid_out, st);
-            case 2: return fused_launch<WB, T, false, true, 2>(fa, grid_out, st);
-            default: return fused_launch<WB, T, false, true, 3>(fa, grid_out, st);
+            case 1: return fused_launch<WB, T, false, true, 1>(fa, grid_out, st, br);
+            case 2: return fused_launch<WB, T, false, true, 2>(fa, grid_out, st, br);
+            default: return fused_launch<WB, T, false, true, 3>(fa, grid_out, st, br);
         }
     }
     // the update form (upd && !trsm) is not fused: measured slower than two sweeps
-    if (!upd && trsm) return fused_launch<WB, T, false, true, 0>(fa, grid_out, st);
+    if (!upd && trsm) return fused_launch<WB, T, false, true, 0>(fa, grid_out, st, br);
     return hipErrorInvalidValue;
 }
 
@@ -222,15 +258,16 @@ hipError_t fused_dispatch(const FusedArgs& fa, int* grid_out, hipStream_t st) {
 hipError_t launch_wide_rowop_reduce(int64_t n, int W, bool f32, const void* Y, int64_t ldy, const void* Qu,
                                     int64_t ldqu, int pu, const double* Cu, const double* Rpk, void* X, int64_t ldx,
                                     const void* E, int64_t lde, int me, double* partials, int* grid_out,
-                                    hipStream_t st) {
+                                    hipStream_t st, const BatchReloc* br) {
     if (W < 1 || W > kFusedMaxW || n < 1 || !grid_out || !partials) return hipErrorInvalidValue;
+    if (br && (br->nact < 1 || *grid_out < 1)) return hipErrorInvalidValue;
     if (E && (me < 1 || me > 48)) return hipErrorInvalidValue;
     const FusedArgs fa{RowopArgs{n, W, Y, ldy, Qu, ldqu, pu, Cu, Rpk, X, ldx}, E, lde, E ? me : 0, partials,
                        (int64_t)(E ? me : W) * W};
-    if (W <= 16) return f32 ? fused_dispatch<16, float>(fa, grid_out, st) : fused_dispatch<16, double>(fa, grid_out, st);
-    if (W <= 24) return f32 ? fused_dispatch<24, float>(fa, grid_out, st) : fused_dispatch<24, double>(fa, grid_out, st);
-    if (W <= 32) return f32 ? fused_dispatch<32, float>(fa, grid_out, st) : fused_dispatch<32, double>(fa, grid_out, st);
-    return f32 ? fused_dispatch<40, float>(fa, grid_out, st) : fused_dispatch<40, double>(fa, grid_out, st);
+    if (W <= 16) return f32 ? fused_dispatch<16, float>(fa, grid_out, st, br) : fused_dispatch<16, double>(fa, grid_out, st, br);
+    if (W <= 24) return f32 ? fused_dispatch<24, float>(fa, grid_out, st, br) : fused_dispatch<24, double>(fa, grid_out, st, br);
+    if (W <= 32) return f32 ? fused_dispatch<32, float>(fa, grid_out, st, br) : fused_dispatch<32, double>(fa, grid_out, st, br);
+    return f32 ? fused_dispatch<40, float>(fa, grid_out, st, br) : fused_dispatch<40, double>(fa, grid_out, st, br);
 }
 
 }  // namespace sko

@@ -155,3 +155,34 @@ def test_two_stage_widest_big_panels(B, ctx, mixed, n):
         assert_rel(R, ref.R, tol_r(e))
         assert metrics.orth_error(Q)[0] <= 1e-13
         assert metrics.backward_error(V, Q, R) <= 1e-14
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_two_stage_fused_close_widths(B, ctx, mixed):
+    """Three big panels of 40 columns (5 blocks of 8), n = 4099: the close of the first big
+    panel runs its row solve with the second Gram matrix in the same sweep, the second its
+    row solve with the projection on 40 previous columns, and the third (80 previous
+    columns, more than the fused projection takes) the separate projection; the widest
+    panel the fused row solve accepts, with a ragged last strip.  FP32 storage is compared
+    with the oracle on the float-rounded input to single-precision tolerances."""
+    n, w, nb, ppb, e = 4099, 8, 15, 5, 4
+    V = wl.glued_blocks(n, nb, w, e)
+    kw = {}
+    dtype = torch.float64
+    if mixed:
+        V = V.astype(np.float32).astype(np.float64)
+        kw["precision"] = "mixed"
+        dtype = torch.float32
+    Q, R, st, col = run(B, ctx, V, w, ppb, k=64, dtype=dtype, **kw)
+    assert st == B.SKO_OK, (st, col)
+    ref = orth.orth_blocks_two_stage(V, w, ppb, Sketch.sparse_sign(64, 8, 0))
+    assert ref.info == 0
+    if mixed:
+        assert metrics.orth_error(Q)[0] <= 1e-5
+        assert metrics.backward_error(V, Q, R) <= 1e-6
+        assert_rel(R, ref.R, 1e-5)
+    else:
+        assert_rel(R, ref.R, tol_r(e))
+        assert metrics.orth_error(Q)[0] <= 1e-13
+        assert metrics.backward_error(V, Q, R) <= 1e-14
+        assert np.max(np.abs(Q - ref.Q)) <= max(1e-12, 100 * 10.0 ** e * U)
