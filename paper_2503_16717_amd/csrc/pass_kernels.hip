@@ -1,5 +1,6 @@
 // Dispatch and launch of the row-strip pass kernels (kernel template in pass_impl.h,
 // instantiated per panel width in pass_wNN.hip).
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -44,29 +45,32 @@ const void* pass_kernel_id(const PassKey& key) { return reinterpret_cast<const v
 
 // Resident workgroups of a pass kernel, queried once per (kernel, device): the occupancy
 // query costs more than a launch.
-int pass_grid_cap(const PassKey& key) {
-    PassSel s = select_kernel(key);
-    if (!s.fn) return 0;
+int resident_grid(const void* kernel, int threads) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (!kernel || hipGetDevice(&dev) != hipSuccess) return -1;
     static std::mutex mu;
     static std::map<std::pair<const void*, int>, int> cache;
-    const std::pair<const void*, int> id{reinterpret_cast<const void*>(s.fn), dev};
+    const std::pair<const void*, int> id{kernel, dev};
     {
         std::lock_guard<std::mutex> lk(mu);
         const auto it = cache.find(id);
         if (it != cache.end()) return it->second;
     }
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(s.fn), s.threads, 0) !=
-        hipSuccess)
-        return 0;
-    if (per_cu < 1) per_cu = 1;
+    int cus = 0, per_cu = 0;
+    int res = -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) == hipSuccess && cus > 0)
+        res = std::max(1, per_cu) * cus;
     std::lock_guard<std::mutex> lk(mu);
-    cache[id] = per_cu * cus;
-    return per_cu * cus;
+    cache[id] = res;
+    return res;
+}
+
+int pass_grid_cap(const PassKey& key) {
+    PassSel s = select_kernel(key);
+    if (!s.fn) return 0;
+    const int r = resident_grid(reinterpret_cast<const void*>(s.fn), s.threads);
+    return r > 0 ? r : 0;
 }
 
 hipError_t launch_pass(const PassKey& key, const PassArgs& args, int grid, hipStream_t stream, const BatchReloc* br) {

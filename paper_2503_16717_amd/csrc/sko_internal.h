@@ -87,6 +87,9 @@ const void* pass_kernel_id(const PassKey& key);
 int pass_strip_rows(const PassKey& key);
 // Largest useful grid for a pass variant on the current device (resident workgroups).
 int pass_grid_cap(const PassKey& key);
+// Workgroups of `threads` threads of `kernel` resident on the current device at once
+// (cached per kernel and device; -1 if the runtime cannot tell).
+int resident_grid(const void* kernel, int threads);
 constexpr int kPassThreads = 256;
 constexpr int kMaxPassW = 16;
 constexpr int kMaxUpdCoef = 4096;   // pu * W update coefficients of one pass (p * w of one block step)

@@ -12,7 +12,6 @@
 // LDS banks), and reads back the 4-row pieces of every 16-column tile.  Columns past the
 // panel width hold stale values; they only reach output entries that are never written.
 #include <algorithm>
-#include <mutex>
 
 #include "batch.h"
 #include "sko_internal.h"
@@ -200,23 +199,7 @@ __global__ void __launch_bounds__(ROW_NT, 2) wide_rowop_red_kernel_batched(const
 
 template <int WB, typename T, bool UPD, bool TRSM, int TE>
 int fused_resident() {
-    static std::mutex mu;
-    static int cached[64] = {};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
-    std::lock_guard<std::mutex> lk(mu);
-    if (cached[dev] == 0) {
-        int cus = 0, per_cu = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(&wide_rowop_red_kernel<WB, T, UPD, TRSM, TE>), ROW_NT, 0) ==
-                hipSuccess &&
-            per_cu > 0 && cus > 0)
-            cached[dev] = per_cu * cus;
-        else
-            cached[dev] = -1;
-    }
-    return cached[dev];
+    return resident_grid(reinterpret_cast<const void*>(&wide_rowop_red_kernel<WB, T, UPD, TRSM, TE>), ROW_NT);
 }
 
 // One system: as many workgroups as are resident (at most the partial-sum capacity), the

@@ -190,18 +190,8 @@ void rowop_launch(const RowopArgs& ra, hipStream_t st, const BatchReloc* br) {
         return;
     }
     // resident workgroups only: each walks its strips
-    static int cap = 0;
-    if (cap == 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(&wide_rowop_kernel<WB, T, UPD, TRSM>), ROW_NT, 0) ==
-                hipSuccess)
-            cap = std::max(1, per_cu) * std::max(1, cus);
-        else
-            cap = 1024;
-    }
+    int cap = resident_grid(reinterpret_cast<const void*>(&wide_rowop_kernel<WB, T, UPD, TRSM>), ROW_NT);
+    if (cap < 1) cap = 1024;
     const int grid = (int)std::min<int64_t>(strips, cap);
     hipLaunchKernelGGL((wide_rowop_kernel<WB, T, UPD, TRSM>), dim3(grid), dim3(ROW_NT), 0, st, ra);
 }
@@ -286,19 +276,7 @@ hipError_t launch_wide_rowop(int64_t n, int W, bool f32, const void* Y, int64_t 
 
 template <typename T, bool SYM, int TA, int TB>
 int gemm_resident_t() {
-    static int cached = 0;
-    if (cached == 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(&wide_gemm_tn_kernel<T, SYM, TA, TB>), GT, 0) == hipSuccess &&
-            per_cu > 0 && cus > 0)
-            cached = per_cu * cus;
-        else
-            cached = -1;
-    }
-    return cached;
+    return resident_grid(reinterpret_cast<const void*>(&wide_gemm_tn_kernel<T, SYM, TA, TB>), GT);
 }
 
 template <typename T>

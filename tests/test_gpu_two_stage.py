@@ -158,14 +158,16 @@ def test_two_stage_widest_big_panels(B, ctx, mixed, n):
 
 
 @pytest.mark.parametrize("mixed", [False, True])
-def test_two_stage_fused_close_widths(B, ctx, mixed):
-    """Three big panels of 40 columns (5 blocks of 8), n = 4099: the close of the first big
-    panel runs its row solve with the second Gram matrix in the same sweep, the second its
-    row solve with the projection on 40 previous columns, and the third (80 previous
-    columns, more than the fused projection takes) the separate projection; the widest
-    panel the fused row solve accepts, with a ragged last strip.  FP32 storage is compared
-    with the oracle on the float-rounded input to single-precision tolerances."""
-    n, w, nb, ppb, e = 4099, 8, 15, 5, 4
+@pytest.mark.parametrize("nb,ppb", [(15, 5), (12, 3)])
+def test_two_stage_fused_close_widths(B, ctx, mixed, nb, ppb):
+    """Big panels of 40 columns (5 blocks of 8; three big panels) or 24 columns (3 blocks of
+    8; four big panels), n = 4099: the close of the first big panel runs its row solve with
+    the second Gram matrix in the same sweep, later ones their row solve with the projection
+    on the previous columns while there are at most 48 of them (40; 24 and 48), and the
+    separate projection beyond (80; 72).  40 columns is the widest panel the fused row solve
+    accepts; the last strip is ragged.  FP32 storage is compared with the oracle on the
+    float-rounded input to single-precision tolerances."""
+    n, w, e = 4099, 8, 4
     V = wl.glued_blocks(n, nb, w, e)
     kw = {}
     dtype = torch.float64
