@@ -172,6 +172,93 @@ def c3_suite(B, torch, wl, n: int, no_autotune: bool = False) -> dict:
     return out
 
 
+def next_rows_suite(B, torch, wl, n: int) -> dict:
+    """The rows beyond the core path, on the config-2 shape (n rows, 12 blocks of 6 columns):
+    f1  BCGS-PIP pre-processing in the two-stage scheme (s_hat = 30), against the RandBCGS2
+        pre-processing on the same blocks (kappa 1e6 per block: PIP needs the accumulated
+        condition number below about u^{-1/2}), and recursive CholQR2 as the intra-block step
+        of the one-stage scheme (kappa 1e12: the first Cholesky of every block breaks down
+        and recurses);
+    f2  the Count-Gaussian sketch (Count part: 2 s^2 = 50 rows, one nonzero per input row;
+        Gaussian part 2 (s + 1) = 12 rows) in one-stage RandCholQR-BCGS2 (kappa 1e12), against
+        the sparse-sign sketch;
+    f3  the Newton basis in s-step GMRES on the config-1 Laplacian: s = 10 and 15 against the
+        monomial basis (restart 30, Gaussian sketch of max(24, 2 (s + 1)) rows)."""
+    import numpy as np
+    out = {}
+    ctx = B.Context(0)
+    N = NB * W
+    R = np.zeros((N, N), order="F")
+
+    def timed(V, Q, o, steps=3):
+        def step():
+            st, col = ctx.sko_orth_blocks(n, NB, W, V.data_ptr(), n, Q.data_ptr(), n, R, N, o)
+            return st, col
+        st, col = step()
+        torch.cuda.synchronize()
+        if st != B.SKO_OK:
+            return {"status": int(st), "breakdown_col": int(col)}
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        return {"status": 0, "ms_per_step": round(ms, 3)}
+
+    Q = torch.empty((N, n), dtype=torch.float64, device="cuda").t()
+    for e in (6.0, 12.0):
+        V = build_inputs(n, torch, wl, e)
+        if e == 6.0:
+            sk = B.make_sketch("sparse_sign", SK_K, SK_ZETA, SK_SEED)
+            r_pip = timed(V, Q, B.orth_opts(two_stage=True, panels_per_big=6, reorth=True, preproc="pip", sketch=sk))
+            r_rb = timed(V, Q, B.orth_opts(two_stage=True, panels_per_big=6, reorth=True, sketch=sk))
+            ab = alg_bytes_two_stage_method(n, NB, W, 6)
+            for r in (r_pip, r_rb):
+                if r.get("ms_per_step"):
+                    r["GBps_on_method_bytes"] = round(ab / (r["ms_per_step"] * 1e-3) / 1e9, 1)
+            out["f1_pip_two_stage_kappa1e6"] = {"pip": r_pip, "randbcgs2": r_rb}
+            log(f"f1 PIP two-stage: {out['f1_pip_two_stage_kappa1e6']}")
+        else:
+            sk = B.make_sketch("sparse_sign", SK_K, SK_ZETA, SK_SEED)
+            r_rec = timed(V, Q, B.orth_opts(intra="cholqr2_recursive", sketch=sk))
+            r_c2 = timed(V, Q, B.orth_opts(intra="cholqr2", sketch=sk))
+            out["f1_recursive_cholqr2_kappa1e12"] = {"recursive": r_rec, "cholqr2": r_c2}
+            log(f"f1 recursive CholQR2: {out['f1_recursive_cholqr2_kappa1e12']}")
+            tg = B.colmajor_from_numpy(wl.gaussian_theta(50, 12, 7), "cuda")
+            r_cg = timed(V, Q, B.orth_opts(sketch=B.make_sketch("count_gauss", zeta=1, seed=SK_SEED, theta=tg)))
+            r_ss = timed(V, Q, B.orth_opts(sketch=sk))
+            ab = alg_bytes_one_stage(n, NB, W)
+            for r in (r_cg, r_ss):
+                if r.get("ms_per_step"):
+                    r["GBps"] = round(ab / (r["ms_per_step"] * 1e-3) / 1e9, 1)
+            out["f2_count_gauss_kappa1e12"] = {"count_gauss_50x12": r_cg, "sparse_sign_64": r_ss}
+            log(f"f2 Count-Gauss: {out['f2_count_gauss_kappa1e12']}")
+            del tg
+        del V
+        torch.cuda.empty_cache()
+    del Q
+    # f3: Newton basis, config-1 Laplacian
+    A1 = wl.laplacian_2d(100)
+    b1 = wl.rhs_uniform(A1.n, 1)
+    Ad = B.csr_to_device(A1)
+    bt = torch.from_numpy(b1).cuda()
+    res = {}
+    for s_, basis in ((5, "monomial"), (10, "monomial"), (10, "newton"), (15, "monomial"), (15, "newton")):
+        k = max(24, 2 * (s_ + 1))
+        th = B.colmajor_from_numpy(wl.gaussian_theta(A1.n, k, 0), "cuda")
+        kw = dict(s=s_, m=30, tol=1e-10, basis=basis, sketch=B.make_sketch("gaussian", theta=th))
+        ctx.gmres(Ad, bt, **kw)
+        torch.cuda.synchronize()
+        x, info, st = ctx.gmres(Ad, bt, **kw)
+        torch.cuda.synchronize()
+        res[f"s{s_}_{basis}"] = {"status": int(st), "converged": info["converged"], "iters": info["iters"],
+                                 "relres": info["relres"], "time_s": round(info["t_total"], 5)}
+    out["f3_newton_laplace2d_100"] = res
+    log(f"f3 Newton basis: {res}")
+    ctx.close()
+    return out
+
+
 def gmres_suite(B, torch, wl, args) -> dict:
     """Time to relative residual 1e-10 (explicit, FP64) for the solver configurations."""
     import numpy as np
@@ -281,14 +368,14 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def build_inputs(n: int, torch, wl):
+def build_inputs(n: int, torch, wl, log10_cond: float = LOG10_COND):
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
     N = NB * W
     Vd = torch.empty((N, n), dtype=torch.float64, device="cuda").t()
 
     def one(j):
-        blk = wl.glued_block(n, W, LOG10_COND, j)
+        blk = wl.glued_block(n, W, log10_cond, j)
         Vd[:, j * W:(j + 1) * W].copy_(torch.from_numpy(np.ascontiguousarray(blk.T)).t())
         return j
 
@@ -392,6 +479,8 @@ def main() -> int:
     ap.add_argument("--skip-gmres", action="store_true", help="skip the GMRES time-to-solution runs")
     ap.add_argument("--skip-two-stage", action="store_true", help="skip the two-stage orthogonalisation run")
     ap.add_argument("--skip-c3", action="store_true", help="skip the mixed-precision block orthogonalisation run")
+    ap.add_argument("--skip-next-rows", action="store_true",
+                    help="skip the BCGS-PIP, recursive CholQR2, Count-Gauss and Newton-basis runs")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (counter calibration)")
@@ -550,6 +639,8 @@ def main() -> int:
         extra["config3_mixed_blockorth"] = c3_suite(B, torch, wl, n, args.no_autotune)
     if not args.skip_gmres:
         extra["gmres"] = gmres_suite(B, torch, wl, args)
+    if not args.skip_next_rows:
+        extra["next_rows"] = next_rows_suite(B, torch, wl, n)
 
     cpu = None
     if not args.no_cpu_baseline:
