@@ -49,13 +49,14 @@ struct Cfg {
     static constexpr int ROWS = MF ? 16 * MT : NWAVE * MAXA;
 };
 
+// The tall operands stream through a pass once: loads and stores are non-temporal.
 template <typename T>
 __device__ __forceinline__ double ldv(const T* p) {
-    return static_cast<double>(*p);
+    return static_cast<double>(__builtin_nontemporal_load(p));
 }
 template <typename T>
 __device__ __forceinline__ void stv(T* p, double v) {
-    *p = static_cast<T>(v);
+    __builtin_nontemporal_store(static_cast<T>(v), p);
 }
 
 // SplitMix64 output number c+1 of the stream started at `seed` (Steele, Lea, Flood 2014).

@@ -76,7 +76,7 @@ __device__ __forceinline__ RawRows<R, T> load_raw(const T* p) {
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < R; ++i) r.v[i] = p[i];
+        for (int i = 0; i < R; ++i) r.v[i] = __builtin_nontemporal_load(p + i);
     }
     return r;
 }
