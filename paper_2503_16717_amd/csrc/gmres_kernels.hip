@@ -306,7 +306,7 @@ __device__ __forceinline__ void update_body(int64_t n, const T* __restrict__ Q, 
     __syncthreads();
     for (int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x; row < n; row += (int64_t)gridDim.x * NT) {
         double s = 0.0;
-        for (int a = 0; a < k; ++a) s += ld_(Q + row + (int64_t)a * ldq) * sy[a];
+        for (int a = 0; a < k; ++a) s += static_cast<double>(__builtin_nontemporal_load(Q + row + (int64_t)a * ldq)) * sy[a];
         x[row] += dinv ? dinv[row] * s : s;
     }
 }

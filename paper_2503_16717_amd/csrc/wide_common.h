@@ -17,6 +17,15 @@ template <typename T>
 __device__ __forceinline__ double ldv(const T* p) {
     return static_cast<double>(*p);
 }
+// The row operation's input and output columns stream through it once: non-temporal.
+template <typename T>
+__device__ __forceinline__ double ldv_nt(const T* p) {
+    return static_cast<double>(__builtin_nontemporal_load(p));
+}
+template <typename T>
+__device__ __forceinline__ void stv_nt(T* p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
 
 constexpr int ROW_NT = 256;
 

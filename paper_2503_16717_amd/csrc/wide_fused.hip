@@ -85,14 +85,14 @@ __device__ __forceinline__ void rowop_red_body(const FusedArgs& fa, const int wg
             const int w = per_strip(w0);
 #pragma unroll
             for (int c = 0; c < WB; ++c)
-                x[c] = ldv(lane_elem(Y + r0 + (int64_t)(c < w ? c : w - 1) * ldy, lane_bytes));
+                x[c] = ldv_nt(lane_elem(Y + r0 + (int64_t)(c < w ? c : w - 1) * ldy, lane_bytes));
             if constexpr (UPD) update_rows<WB, 1, T>(xa, Qu + row, ldqu, pu, Cs, w);
             if constexpr (TRSM) solve_cols<WB, 0>(x, Rs, w, sD);
 #pragma unroll
             for (int c = 0; c < WB; ++c) {
                 if (c < w) {
                     const T v = static_cast<T>(x[c]);
-                    *lane_elem(X + r0 + (int64_t)c * ldx, lane_bytes) = v;
+                    stv_nt(lane_elem(X + r0 + (int64_t)c * ldx, lane_bytes), v);
                     x[c] = static_cast<double>(v);  // reduce what was stored (FP32 storage: rounded)
                 }
             }

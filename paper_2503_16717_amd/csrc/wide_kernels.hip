@@ -62,12 +62,12 @@ __device__ __forceinline__ void rowop_body(const RowopArgs& ra, const int wg, co
         // around the load would hold the FP32-to-FP64 conversion, and with it a wait for
         // that load, inside the branch, one column at a time.
 #pragma unroll
-        for (int c = 0; c < WB; ++c) x[c] = ldv(lane_elem(Y + r0 + (int64_t)(c < w ? c : w - 1) * ldy, lane_bytes));
+        for (int c = 0; c < WB; ++c) x[c] = ldv_nt(lane_elem(Y + r0 + (int64_t)(c < w ? c : w - 1) * ldy, lane_bytes));
         if constexpr (UPD) update_rows<WB, 1, T>(xa, Qu + row, ldqu, pu, Cs, w);
         if constexpr (TRSM) solve_cols<WB, 0>(x, Rs, w, sD);
 #pragma unroll
         for (int c = 0; c < WB; ++c)
-            if (c < w) *lane_elem(X + r0 + (int64_t)c * ldx, lane_bytes) = static_cast<T>(x[c]);
+            if (c < w) stv_nt(lane_elem(X + r0 + (int64_t)c * ldx, lane_bytes), static_cast<T>(x[c]));
     }
 }
 
