@@ -405,13 +405,13 @@ def copy_ceiling(torch, nbytes: int = 1 << 31, reps: int = 20) -> float:
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-PASS_SOURCE = os.path.join(ROOT, "paper_2503_16717_amd", "csrc", "pass_impl.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass_kernels_blockorth_n2p24_w6.md")
 
 
 def pass_source_digest() -> str:
-    import hashlib
-    return hashlib.sha256(open(PASS_SOURCE, "rb").read()).hexdigest()[:16]
+    """Digest of the pass kernels' sources, as the traffic summary's rows carry it."""
+    from paper_2503_16717_amd.rocprof_summary import source_digest
+    return source_digest()
 
 
 def measured_traffic(kernel: str):

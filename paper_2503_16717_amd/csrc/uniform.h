@@ -110,13 +110,28 @@ __device__ __forceinline__ void load_group(RawRows<R, T> (&q)[G], const T* Q, in
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// x[r][c] -= Q(r, j) C(j, c) for one loaded column j.
+template <int W, int R, typename T>
+__device__ __forceinline__ void update_col(double (&x)[R][W], const RawRows<R, T>& q, CD C, int j, int pu, int w) {
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        if (c < w) {
+            const double cj = C[j + c * pu];
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r][c] -= static_cast<double>(q.v[r]) * cj;
+        }
+    }
+}
+
 // x[r][c] -= sum_j Q(r, j) C(j, c) over the pu columns of Q for the w <= W live columns of
 // x (Q points at this thread's first row; all R rows lie below n).  Columns go in groups of
 // G, and the next group's loads are issued before the current group's FMAs (two register
-// buffers in turn), so each wave keeps a group of loads in flight while it computes.  Single
-// rows of 4-byte storage take groups of eight: each load moves half the bytes of a double
-// one, so twice as many are kept in flight.  The subtraction order (j ascending per output
-// column) is the same as in the generic path and does not depend on G.
+// buffers in turn), so each wave keeps a group of loads in flight while it computes; the
+// pu mod G remaining columns follow one by one.  Every column is loaded once: non-temporal
+// lines leave the cache early, so a second load of a column would come from HBM again.
+// Single rows of 4-byte storage take groups of eight: each load moves half the bytes of a
+// double one, so twice as many are kept in flight.  The subtraction order (j ascending per
+// output column) is the same as in the generic path and does not depend on G.
 template <int W, int R, typename T>
 __device__ __forceinline__ void update_rows(double (&x)[R][W], const T* Q, int64_t ldq, int pu, CD C, int w = W) {
     constexpr int G = (sizeof(T) == 4 && R == 1) ? 8 : 4;
@@ -124,29 +139,20 @@ __device__ __forceinline__ void update_rows(double (&x)[R][W], const T* Q, int64
     if (pu >= G) {
         RawRows<R, T> qa[G], qb[G];
         load_group<R, T, G>(qa, Q, ldq, 0);
-        // the last group's look-ahead loads it again (from cache) instead of branching
         while (true) {
-            load_group<R, T, G>(qb, Q, ldq, min(j + G, pu - G));
+            const bool more = j + 2 * G <= pu;
+            if (more) load_group<R, T, G>(qb, Q, ldq, j + G);
             update_group<W, R, T, G>(x, qa, C, j, pu, w);
             j += G;
-            if (j + G > pu) break;
-            load_group<R, T, G>(qa, Q, ldq, min(j + G, pu - G));
+            if (!more) break;
+            const bool more2 = j + 2 * G <= pu;
+            if (more2) load_group<R, T, G>(qa, Q, ldq, j + G);
             update_group<W, R, T, G>(x, qb, C, j, pu, w);
             j += G;
-            if (j + G > pu) break;
+            if (!more2) break;
         }
     }
-    for (; j < pu; ++j) {
-        const RawRows<R, T> q = load_raw<R>(Q + (int64_t)j * ldq);
-#pragma unroll
-        for (int c = 0; c < W; ++c) {
-            if (c < w) {
-                const double cj = C[j + c * pu];
-#pragma unroll
-                for (int r = 0; r < R; ++r) x[r][c] -= static_cast<double>(q.v[r]) * cj;
-            }
-        }
-    }
+    for (; j < pu; ++j) update_col<W, R, T>(x, load_raw<R>(Q + (int64_t)j * ldq), C, j, pu, w);
 }
 
 }  // namespace sko
