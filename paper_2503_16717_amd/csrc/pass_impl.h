@@ -215,7 +215,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
     // uses the lane mapping of the 16 x 16 x 4 tile (lane l: output row 16m + l % 16, data
     // row l / 16), so the same pieces feed both forms.
     constexpr bool SP4 = RED == RED_SKETCH_SPARSE;
-    constexpr bool B4 = MF && (SP4 || W <= 12);
+    // sparse-sign sketches of up to 64 rows per launch: one lane per sketch row, no MFMA
+    constexpr bool SPM = SP4 && MT == 4;
+    constexpr bool B4 = MF && !SPM && (SP4 || W <= 12);
     constexpr int CB = (W + 3) / 4;
     double4_t dacc[(MF && !B4) ? MT : 1];
     double acc4[B4 ? MT * CB : 1];
@@ -249,6 +251,28 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
             sk_lo[m] = 2u * lo;
             sk_wid[m] = live ? 2u * (hi - lo) : 0u;
         }
+    }
+    // Sparse sketch on row masks (SPM): lane l accumulates sketch row red_row0 + l, which is
+    // slot spm_j of hash byte spm_t (none: spm_t = -1).  Per 64 staged rows the wave forms,
+    // for every byte t, the ballots of the bits of each row's slot and of its sign; a lane
+    // keeps the rows whose slot bits all equal its own (spm_jn[i]: all ones where bit i of
+    // spm_j is 0, so that ballot is inverted) for its own byte, then adds those rows into its
+    // W sums in ascending row order.  Only the rows with a nonzero in the lane's sketch row
+    // are touched: zeta W products per row instead of k W on MFMA blocks.
+    constexpr int SPM_BITS = 6;  // slots per byte up to 64
+    int spm_t = -1, spm_nbits = 0;
+    unsigned spm_jn[SPM ? SPM_BITS : 1];
+    double sacc[SPM ? W : 1];
+#pragma unroll
+    for (int c = 0; c < (SPM ? W : 1); ++c) sacc[c] = 0.0;
+    if constexpr (SPM) {
+        const int B = a.sk_k / a.sk_zeta;
+        const int g = a.red_row0 + lane;
+        const int t = g / B, j = g - t * B;
+        if (lane < a.red_rows && t < a.sk_zeta) spm_t = t;
+        while ((1 << spm_nbits) < B) ++spm_nbits;
+#pragma unroll
+        for (int i = 0; i < SPM_BITS; ++i) spm_jn[i] = ((j >> i) & 1) ? 0u : ~0u;
     }
 
     // 2-row vector accesses need every tall operand's column starts 2-element aligned
@@ -492,6 +516,50 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                         }
                     }
                 }
+            } else if constexpr (SPM) {
+                // ---------------- phase B, sparse-sign sketch on row masks ----------------
+                constexpr int WROWS = STRIP / C::NWAVE;  // rows this wave staged (64 per thread row)
+                const unsigned B = (unsigned)(a.sk_k / a.sk_zeta);
+#pragma unroll
+                for (int u = 0; u < RPT; ++u) {
+                    const int rb = wave * WROWS + u * 64;  // strip-local row of mask bit 0
+                    const uint64_t h = hs[rb + lane];
+                    const uint64_t vm = __ballot(base + rb + lane < n);
+                    unsigned ml = 0u, mh = 0u, sl = 0u, sh = 0u;
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        if (t < a.sk_zeta) {
+                            const unsigned b8 = (unsigned)(h >> (8 * t)) & 0xffu;
+                            const unsigned slot = ((b8 >> 1) * B) >> 7;
+                            const bool mine = t == spm_t;
+                            unsigned cl = mine ? (unsigned)vm : 0u, ch = mine ? (unsigned)(vm >> 32) : 0u;
+#pragma unroll
+                            for (int i = 0; i < SPM_BITS; ++i) {
+                                if (i < spm_nbits) {
+                                    const uint64_t bi = __ballot((slot >> i) & 1u);
+                                    cl &= (unsigned)bi ^ spm_jn[i];
+                                    ch &= (unsigned)(bi >> 32) ^ spm_jn[i];
+                                }
+                            }
+                            const uint64_t sg = __ballot(b8 & 1u);
+                            ml |= cl;
+                            mh |= ch;
+                            sl |= mine ? (unsigned)sg : 0u;
+                            sh |= mine ? (unsigned)(sg >> 32) : 0u;
+                        }
+                    }
+                    uint64_t msk = ((uint64_t)mh << 32) | ml;
+                    const uint64_t sgm = ((uint64_t)sh << 32) | sl;
+                    while (msk) {
+                        const int bit = __builtin_ctzll(msk);
+                        msk ^= 1ull << bit;
+                        // +-1.0 from the row's sign bit for this byte
+                        const unsigned sb = (unsigned)(sgm >> bit) & 1u;
+                        const double sgn = __hiloint2double((int)((sb << 31) | 0x3FF00000u), 0);
+#pragma unroll
+                        for (int c = 0; c < W; ++c) sacc[c] = fma(sgn, (double)xs[c * LDX + rb + bit], sacc[c]);
+                    }
+                }
             } else if constexpr (MF) {
                 // ---------------- phase B, MFMA tiles ----------------
                 const int g = lane >> 4, ci = lane & 15;
@@ -615,7 +683,29 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
         }
     }
 
-    if constexpr (B4) {
+    if constexpr (SPM) {
+        // lane l holds sketch row red_row0 + l; the waves' sums are added through LDS in wave
+        // order, four columns at a time
+        double* out = a.partials + (int64_t)wg * a.part_stride;
+#pragma unroll
+        for (int c0 = 0; c0 < W; c0 += 4) {
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+                if (c0 + cc < W) pred[(wave * 4 + cc) * 64 + lane] = sacc[c0 + cc];
+            __syncthreads();
+            if (wave == 0 && lane < a.red_rows) {
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) {
+                    if (c0 + cc < W) {
+                        double v = 0.0;
+                        for (int w2 = 0; w2 < C::NWAVE; ++w2) v += pred[(w2 * 4 + cc) * 64 + lane];
+                        out[(a.red_row0 + lane) + (int64_t)(c0 + cc) * a.part_rows_total] = v;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    } else if constexpr (B4) {
         // v_mfma_f64_4x4x4 output layout (measured on gfx950): D[i][j] of block b sits in lane
         // 4b + j + 16i, so lane l holds output row 16m + 4((l % 16) / 4) + l / 16 and column
         // 4cb + l % 4 of instruction (m, cb).  The waves' values are summed through LDS in wave
