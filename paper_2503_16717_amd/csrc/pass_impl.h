@@ -43,8 +43,9 @@ struct Cfg {
     // Gram: output rows per wave (accumulators per lane = MAXA * W), spread over all waves
     static constexpr int MAXA = (W + NWAVE - 1) / NWAVE;
     // MFMA tiles of 16 output rows held by every wave (a dense sketch up to 64 rows in one
-    // launch; a sparse sketch up to 128 rows; projections up to 128 previous columns).  Fewer
-    // tiles are instantiated for launches that need fewer (more resident waves).
+    // launch; projections up to 128 previous columns); a sparse sketch covers 16 MT rows too,
+    // on row masks (MT = 4: one sketch row per lane, 8: two).  Fewer tiles are instantiated
+    // for launches that need fewer (more resident waves).
     static constexpr int MT = RED == RED_SKETCH_DENSE ? 4 : 8;
     static constexpr int ROWS = MF ? 16 * MT : NWAVE * MAXA;
 };
@@ -206,20 +207,20 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[i][c] = 0.0;
     // MFMA accumulators: tile m covers output rows 16m..16m+15 of this launch
-    // The sparse sketch, and the projection and dense sketch of blocks up to 12 columns, run
-    // on v_mfma_f64_4x4x4 (four independent 4 x 4 x 4 blocks per instruction, the same FP64
+    // The projection and dense sketch of blocks up to 12 columns run on v_mfma_f64_4x4x4 (four independent 4 x 4 x 4 blocks per instruction, the same FP64
     // rate as 16 x 16 x 4): a block covers 4 output rows x 4 columns of x, so narrow blocks
     // do not pay for 16 padded columns (three instructions of a quarter of the time instead
     // of one 16 x 16 x 4 for 11 columns).  Instruction (m, cb) holds the output rows
     // 16m..16m+15 (block b: rows 16m + 4b..+3) and the columns 4cb..4cb+3.  The A operand
     // uses the lane mapping of the 16 x 16 x 4 tile (lane l: output row 16m + l % 16, data
     // row l / 16), so the same pieces feed both forms.
-    constexpr bool SP4 = RED == RED_SKETCH_SPARSE;
-    // sparse-sign sketches of up to 64 rows per launch: one lane per sketch row, no MFMA
-    constexpr bool SPM = SP4 && MT == 4;
-    constexpr bool B4 = MF && !SPM && (SP4 || W <= 12);
+    // sparse-sign sketches on row masks (no MFMA): lane l accumulates the launch's sketch rows
+    // l and, for launches of up to 128 rows, l + 64
+    constexpr bool SPM = RED == RED_SKETCH_SPARSE;
+    constexpr int SPR = MT / 4;
+    constexpr bool B4 = MF && !SPM && W <= 12;
     constexpr int CB = (W + 3) / 4;
-    double4_t dacc[(MF && !B4) ? MT : 1];
+    double4_t dacc[(MF && !SPM && !B4) ? MT : 1];
     double acc4[B4 ? MT * CB : 1];
 #pragma unroll
     for (int i = 0; i < (B4 ? MT * CB : 1); ++i) acc4[i] = 0.0;
@@ -227,52 +228,33 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
 #pragma unroll
     for (int m = 0; m < (MF ? MT : 1); ++m) dacc[m] = double4_t{0.0, 0.0, 0.0, 0.0};
 
-    // Sparse sketch: the MFMA A operand of lane l is Theta[row][16m + l % 16]; that sketch
-    // row is slot j of hash byte t (B = k / zeta slots per byte).  Byte b selects slot
-    // floor((b >> 1) B / 128), which equals j exactly when 2 ceil(128 j / B) <= b <
-    // 2 ceil(128 (j + 1) / B); the lane keeps, per tile, the v_perm_b32 selector that moves
-    // byte t of the 64-bit hash into the low byte of a zeroed word (one instruction), and that
-    // range (empty for lanes past the sketch).
-    unsigned sk_sel[RED == RED_SKETCH_SPARSE ? MT : 1];
-    unsigned sk_lo[RED == RED_SKETCH_SPARSE ? MT : 1];
-    unsigned sk_wid[RED == RED_SKETCH_SPARSE ? MT : 1];
-    if constexpr (RED == RED_SKETCH_SPARSE) {
-        const int B = a.sk_k / a.sk_zeta;
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const int loc = 16 * m + (lane & 15);
-            const int g = a.red_row0 + loc;
-            const int t = g / B;
-            const int j = g - t * B;
-            const bool live = loc < a.red_rows && t < a.sk_zeta;
-            const unsigned lo = (unsigned)((128 * j + B - 1) / B), hi = (unsigned)((128 * (j + 1) + B - 1) / B);
-            // selector bytes: byte t of {hi word, lo word} (0..7), then three zero bytes (0x0c)
-            sk_sel[m] = live ? (0x0c0c0c00u | (unsigned)t) : 0x0c0c0c0cu;
-            sk_lo[m] = 2u * lo;
-            sk_wid[m] = live ? 2u * (hi - lo) : 0u;
-        }
-    }
-    // Sparse sketch on row masks (SPM): lane l accumulates sketch row red_row0 + l, which is
-    // slot spm_j of hash byte spm_t (none: spm_t = -1).  Per 64 staged rows the wave forms,
+    // Sparse sketch on row masks (SPM): lane l accumulates sketch row g = red_row0 + l (and
+    // g + 64), which is slot j of hash byte spm_t (none: spm_t = -1); byte b selects slot
+    // floor((b >> 1) B / 128) of its B = k / zeta and carries the sign in bit 0.  Per 64 staged rows the wave forms,
     // for every byte t, the ballots of the bits of each row's slot and of its sign; a lane
     // keeps the rows whose slot bits all equal its own (spm_jn[i]: all ones where bit i of
     // spm_j is 0, so that ballot is inverted) for its own byte, then adds those rows into its
     // W sums in ascending row order.  Only the rows with a nonzero in the lane's sketch row
     // are touched: zeta W products per row instead of k W on MFMA blocks.
-    constexpr int SPM_BITS = 6;  // slots per byte up to 64
-    int spm_t = -1, spm_nbits = 0;
-    unsigned spm_jn[SPM ? SPM_BITS : 1];
-    double sacc[SPM ? W : 1];
+    constexpr int SPM_BITS = 7;  // slots per byte up to 128 (k <= 128)
+    int spm_t[SPM ? SPR : 1], spm_nbits = 0;
+    unsigned spm_jn[SPM ? SPR : 1][SPM ? SPM_BITS : 1];
+    double sacc[SPM ? SPR : 1][SPM ? W : 1];
 #pragma unroll
-    for (int c = 0; c < (SPM ? W : 1); ++c) sacc[c] = 0.0;
+    for (int q = 0; q < (SPM ? SPR : 1); ++q)
+#pragma unroll
+        for (int c = 0; c < (SPM ? W : 1); ++c) sacc[q][c] = 0.0;
     if constexpr (SPM) {
         const int B = a.sk_k / a.sk_zeta;
-        const int g = a.red_row0 + lane;
-        const int t = g / B, j = g - t * B;
-        if (lane < a.red_rows && t < a.sk_zeta) spm_t = t;
         while ((1 << spm_nbits) < B) ++spm_nbits;
 #pragma unroll
-        for (int i = 0; i < SPM_BITS; ++i) spm_jn[i] = ((j >> i) & 1) ? 0u : ~0u;
+        for (int q = 0; q < SPR; ++q) {
+            const int g = a.red_row0 + lane + 64 * q;
+            const int t = g / B, j = g - t * B;
+            spm_t[q] = (lane + 64 * q < a.red_rows && t < a.sk_zeta) ? t : -1;
+#pragma unroll
+            for (int i = 0; i < SPM_BITS; ++i) spm_jn[q][i] = ((j >> i) & 1) ? 0u : ~0u;
+        }
     }
 
     // 2-row vector accesses need every tall operand's column starts 2-element aligned
@@ -444,79 +426,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
             } else {
                 __syncthreads();
             }
-            if constexpr (SP4 && MT == 8) {
-                // ---------------- phase B, sparse-sign sketch on bucketed 4 x 4 x 4 blocks ----------------
-                // (sketches of more than 64 rows; for up to 64 rows the rows-in-order form below
-                // issues fewer instructions)
-                // Block b of instruction (m, cb) produces sketch rows 16m + 4b .. 16m + 4b + 3 (its
-                // "quarter" q = b) and takes its 4 K rows from its own list: the wave's rows that
-                // have a nonzero in that quarter, in ascending order.  A row has one nonzero per
-                // slot block of B sketch rows, so it belongs to about 4 / B of a tile's quarters
-                // (one of four for B = 16), and the blocks multiply mostly nonzero operands instead
-                // of one nonzero in sixteen.  Lists hold lane indices (bytes) in this wave's part
-                // of the cross-wave tile buffer (the 4 * 64 doubles its final sums use, so a wave
-                // that finishes first writes only over its own lists); counts are wave-uniform.
-                constexpr int WROWS = STRIP / C::NWAVE;  // rows this wave staged (64 or 128)
-                static_assert(MT * 4 * 64 <= 4 * 64 * (int)sizeof(double), "lists exceed the wave's region");
-                const int wrow0 = wave * WROWS;
-                unsigned char* lst = reinterpret_cast<unsigned char*>(pred + wave * 4 * 64);
-                const int B = a.sk_k / a.sk_zeta;
-                const int q = (lane >> 2) & 3, kk = lane >> 4, i4 = lane & 3;
-#pragma unroll 1
-                for (int ch = 0; ch < WROWS / 64; ++ch) {
-                    const int r = wrow0 + ch * 64 + lane;  // strip-local row of this lane
-                    // quarters (m, q) of the launch's sketch rows holding a nonzero of row r
-                    unsigned member = 0u;
-                    if (base + r < n) {
-                        const uint64_t h = hs[r];
-                        for (int t = 0; t < a.sk_zeta; ++t) {
-                            const unsigned b8 = (unsigned)(h >> (8 * t)) & 0xffu;
-                            const int g = t * B + (int)(((b8 >> 1) * (unsigned)B) >> 7) - a.red_row0;
-                            if (g >= 0 && g < 16 * MT) member |= 1u << (g >> 2);
-                        }
-                    }
-                    unsigned cnt[MT][4];
-#pragma unroll
-                    for (int m = 0; m < MT; ++m)
-#pragma unroll
-                        for (int qq = 0; qq < 4; ++qq) {
-                            const bool in = (member >> (4 * m + qq)) & 1u;
-                            const uint64_t bal = __ballot(in);
-                            cnt[m][qq] = (unsigned)__popcll(bal);
-                            if (in) {
-                                const unsigned pos =
-                                    __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                                lst[(m * 4 + qq) * 64 + pos] = (unsigned char)lane;
-                            }
-                        }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-                    for (int m = 0; m < MT; ++m) {
-                        const unsigned c0 = cnt[m][0], c1 = cnt[m][1], c2 = cnt[m][2], c3 = cnt[m][3];
-                        const unsigned cmax = max(max(c0, c1), max(c2, c3));
-                        const unsigned myc = q == 0 ? c0 : q == 1 ? c1 : q == 2 ? c2 : c3;
-#pragma unroll 1
-                        for (unsigned it = 0; 4 * it < cmax; ++it) {
-                            const unsigned idx = 4 * it + kk;
-                            const bool live = idx < myc;
-                            const int rr = wrow0 + ch * 64 + (live ? (int)lst[(m * 4 + q) * 64 + idx] : 0);
-                            const uint64_t h = hs[rr];
-                            const unsigned b8 = __builtin_amdgcn_perm((unsigned)(h >> 32), (unsigned)h, sk_sel[m]);
-                            // +-1.0 from the sign bit (bit 0 of the byte), 0.0 off the slot
-                            const unsigned top = (live && (b8 - sk_lo[m]) < sk_wid[m]) ? ((b8 << 31) | 0x3FF00000u) : 0u;
-                            const double av = __hiloint2double((int)top, 0);
-#pragma unroll
-                            for (int cb = 0; cb < CB; ++cb) {
-                                const int col = 4 * cb + i4;
-                                const double bx = (live && col < W) ? (double)xs[col * LDX + rr] : 0.0;
-                                acc4[m * CB + cb] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bx, acc4[m * CB + cb], 0, 0, 0);
-                            }
-                        }
-                    }
-                }
-            } else if constexpr (SPM) {
+            if constexpr (SPM) {
                 // ---------------- phase B, sparse-sign sketch on row masks ----------------
                 constexpr int WROWS = STRIP / C::NWAVE;  // rows this wave staged (64 per thread row)
                 const unsigned B = (unsigned)(a.sk_k / a.sk_zeta);
@@ -525,39 +435,57 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                     const int rb = wave * WROWS + u * 64;  // strip-local row of mask bit 0
                     const uint64_t h = hs[rb + lane];
                     const uint64_t vm = __ballot(base + rb + lane < n);
-                    unsigned ml = 0u, mh = 0u, sl = 0u, sh = 0u;
+                    unsigned ml[SPR], mh[SPR], sl[SPR], sh[SPR];
+#pragma unroll
+                    for (int q = 0; q < SPR; ++q) ml[q] = mh[q] = sl[q] = sh[q] = 0u;
 #pragma unroll
                     for (int t = 0; t < 8; ++t) {
                         if (t < a.sk_zeta) {
                             const unsigned b8 = (unsigned)(h >> (8 * t)) & 0xffu;
                             const unsigned slot = ((b8 >> 1) * B) >> 7;
-                            const bool mine = t == spm_t;
-                            unsigned cl = mine ? (unsigned)vm : 0u, ch = mine ? (unsigned)(vm >> 32) : 0u;
+                            bool mine[SPR];
+                            unsigned cl[SPR], ch[SPR];
+#pragma unroll
+                            for (int q = 0; q < SPR; ++q) {
+                                mine[q] = t == spm_t[q];
+                                cl[q] = mine[q] ? (unsigned)vm : 0u;
+                                ch[q] = mine[q] ? (unsigned)(vm >> 32) : 0u;
+                            }
 #pragma unroll
                             for (int i = 0; i < SPM_BITS; ++i) {
                                 if (i < spm_nbits) {
                                     const uint64_t bi = __ballot((slot >> i) & 1u);
-                                    cl &= (unsigned)bi ^ spm_jn[i];
-                                    ch &= (unsigned)(bi >> 32) ^ spm_jn[i];
+#pragma unroll
+                                    for (int q = 0; q < SPR; ++q) {
+                                        cl[q] &= (unsigned)bi ^ spm_jn[q][i];
+                                        ch[q] &= (unsigned)(bi >> 32) ^ spm_jn[q][i];
+                                    }
                                 }
                             }
                             const uint64_t sg = __ballot(b8 & 1u);
-                            ml |= cl;
-                            mh |= ch;
-                            sl |= mine ? (unsigned)sg : 0u;
-                            sh |= mine ? (unsigned)(sg >> 32) : 0u;
+#pragma unroll
+                            for (int q = 0; q < SPR; ++q) {
+                                ml[q] |= cl[q];
+                                mh[q] |= ch[q];
+                                sl[q] |= mine[q] ? (unsigned)sg : 0u;
+                                sh[q] |= mine[q] ? (unsigned)(sg >> 32) : 0u;
+                            }
                         }
                     }
-                    uint64_t msk = ((uint64_t)mh << 32) | ml;
-                    const uint64_t sgm = ((uint64_t)sh << 32) | sl;
-                    while (msk) {
-                        const int bit = __builtin_ctzll(msk);
-                        msk ^= 1ull << bit;
-                        // +-1.0 from the row's sign bit for this byte
-                        const unsigned sb = (unsigned)(sgm >> bit) & 1u;
-                        const double sgn = __hiloint2double((int)((sb << 31) | 0x3FF00000u), 0);
 #pragma unroll
-                        for (int c = 0; c < W; ++c) sacc[c] = fma(sgn, (double)xs[c * LDX + rb + bit], sacc[c]);
+                    for (int q = 0; q < SPR; ++q) {
+                        uint64_t msk = ((uint64_t)mh[q] << 32) | ml[q];
+                        const uint64_t sgm = ((uint64_t)sh[q] << 32) | sl[q];
+                        while (msk) {
+                            const int bit = __builtin_ctzll(msk);
+                            msk ^= 1ull << bit;
+                            // +-1.0 from the row's sign bit for this byte
+                            const unsigned sb = (unsigned)(sgm >> bit) & 1u;
+                            const double sgn = __hiloint2double((int)((sb << 31) | 0x3FF00000u), 0);
+#pragma unroll
+                            for (int c = 0; c < W; ++c)
+                                sacc[q][c] = fma(sgn, (double)xs[c * LDX + rb + bit], sacc[q][c]);
+                        }
                     }
                 }
             } else if constexpr (MF) {
@@ -593,40 +521,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
 #pragma unroll
                         for (int u = 0; u < 4; ++u) bv[u] = (ci < W) ? xs[ci * LDX + r0 + u] : 0.0;
                     }
-                    unsigned hl[RED == RED_SKETCH_SPARSE ? 4 : 1], hh[RED == RED_SKETCH_SPARSE ? 4 : 1];
-                    if constexpr (RED == RED_SKETCH_SPARSE) {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const uint64_t h = hs[r0 + u];
-                            hl[u] = (unsigned)h;
-                            hh[u] = (unsigned)(h >> 32);
-                        }
-                    }
-                    if constexpr (RED == RED_SKETCH_SPARSE) {
-                        // decode every tile's operand first (high words of +-1.0 / 0.0), then
-                        // issue the MFMAs row step by row step across the tiles, so consecutive
-                        // MFMAs accumulate into different tiles.  Tiles past the launch's rows
-                        // decode to zero (no lane holds a live slot) and are not written out.
-                        unsigned top[MT][4];
-#pragma unroll
-                        for (int m = 0; m < MT; ++m)
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const unsigned b = __builtin_amdgcn_perm(hh[u], hl[u], sk_sel[m]);
-                                // +-1.0 from the sign bit (bit 0 of the byte), 0.0 off the slot
-                                top[m][u] = (b - sk_lo[m]) < sk_wid[m] ? ((b << 31) | 0x3FF00000u) : 0u;
-                            }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-#pragma unroll
-                            for (int m = 0; m < MT; ++m) {
-                                const double av = __hiloint2double((int)top[m][u], 0);
-#pragma unroll
-                                for (int cb = 0; cb < CB; ++cb)
-                                    acc4[m * CB + cb] =
-                                        __builtin_amdgcn_mfma_f64_4x4x4f64(av, bq[cb][u], acc4[m * CB + cb], 0, 0, 0);
-                            }
-                    } else {
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
                         if (m < ntiles) {
@@ -651,7 +545,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                                     dacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], dacc[m], 0, 0, 0);
                             }
                         }
-                    }
                     }
                 }
             } else if constexpr (GRAM) {
@@ -684,26 +577,30 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
     }
 
     if constexpr (SPM) {
-        // lane l holds sketch row red_row0 + l; the waves' sums are added through LDS in wave
-        // order, four columns at a time
+        // lane l holds sketch rows red_row0 + l + 64 q; the waves' sums are added through LDS in
+        // wave order, four columns at a time
         double* out = a.partials + (int64_t)wg * a.part_stride;
 #pragma unroll
-        for (int c0 = 0; c0 < W; c0 += 4) {
+        for (int q = 0; q < SPR; ++q) {
+            const int r = lane + 64 * q;
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc)
-                if (c0 + cc < W) pred[(wave * 4 + cc) * 64 + lane] = sacc[c0 + cc];
-            __syncthreads();
-            if (wave == 0 && lane < a.red_rows) {
+            for (int c0 = 0; c0 < W; c0 += 4) {
 #pragma unroll
-                for (int cc = 0; cc < 4; ++cc) {
-                    if (c0 + cc < W) {
-                        double v = 0.0;
-                        for (int w2 = 0; w2 < C::NWAVE; ++w2) v += pred[(w2 * 4 + cc) * 64 + lane];
-                        out[(a.red_row0 + lane) + (int64_t)(c0 + cc) * a.part_rows_total] = v;
+                for (int cc = 0; cc < 4; ++cc)
+                    if (c0 + cc < W) pred[(wave * 4 + cc) * 64 + lane] = sacc[q][c0 + cc];
+                __syncthreads();
+                if (wave == 0 && r < a.red_rows) {
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) {
+                        if (c0 + cc < W) {
+                            double v = 0.0;
+                            for (int w2 = 0; w2 < C::NWAVE; ++w2) v += pred[(w2 * 4 + cc) * 64 + lane];
+                            out[(a.red_row0 + r) + (int64_t)(c0 + cc) * a.part_rows_total] = v;
+                        }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
     } else if constexpr (B4) {
         // v_mfma_f64_4x4x4 output layout (measured on gfx950): D[i][j] of block b sits in lane
