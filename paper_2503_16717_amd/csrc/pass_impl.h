@@ -443,14 +443,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                         if (t < a.sk_zeta) {
                             const unsigned b8 = (unsigned)(h >> (8 * t)) & 0xffu;
                             const unsigned slot = ((b8 >> 1) * B) >> 7;
-                            bool mine[SPR];
                             unsigned cl[SPR], ch[SPR];
 #pragma unroll
-                            for (int q = 0; q < SPR; ++q) {
-                                mine[q] = t == spm_t[q];
-                                cl[q] = mine[q] ? (unsigned)vm : 0u;
-                                ch[q] = mine[q] ? (unsigned)(vm >> 32) : 0u;
-                            }
+                            for (int q = 0; q < SPR; ++q) cl[q] = ch[q] = ~0u;
 #pragma unroll
                             for (int i = 0; i < SPM_BITS; ++i) {
                                 if (i < spm_nbits) {
@@ -463,28 +458,51 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                                 }
                             }
                             const uint64_t sg = __ballot(b8 & 1u);
+                            // keep this byte's masks only in the lanes whose sketch row it holds
 #pragma unroll
                             for (int q = 0; q < SPR; ++q) {
-                                ml[q] |= cl[q];
-                                mh[q] |= ch[q];
-                                sl[q] |= mine[q] ? (unsigned)sg : 0u;
-                                sh[q] |= mine[q] ? (unsigned)(sg >> 32) : 0u;
+                                const unsigned mine = t == spm_t[q] ? ~0u : 0u;
+                                ml[q] |= cl[q] & mine;
+                                mh[q] |= ch[q] & mine;
+                                sl[q] |= (unsigned)sg & mine;
+                                sh[q] |= (unsigned)(sg >> 32) & mine;
                             }
                         }
                     }
 #pragma unroll
                     for (int q = 0; q < SPR; ++q) {
-                        uint64_t msk = ((uint64_t)mh[q] << 32) | ml[q];
-                        const uint64_t sgm = ((uint64_t)sh[q] << 32) | sl[q];
-                        while (msk) {
-                            const int bit = __builtin_ctzll(msk);
-                            msk ^= 1ull << bit;
-                            // +-1.0 from the row's sign bit for this byte
-                            const unsigned sb = (unsigned)(sgm >> bit) & 1u;
-                            const double sgn = __hiloint2double((int)((sb << 31) | 0x3FF00000u), 0);
+                        ml[q] &= (unsigned)vm;
+                        mh[q] &= (unsigned)(vm >> 32);
+                    }
+                    // one sketch row per lane: each mask in two 32-row halves (the lowest set bit,
+                    // its clearing and the sign are single 32-bit operations); two rows per lane:
+                    // whole 64-row masks (four half loops would each run to their own longest
+                    // half, and the sparser masks of larger sketches leave them short)
+                    constexpr int NH = SPR == 1 ? 2 : 1;
 #pragma unroll
-                            for (int c = 0; c < W; ++c)
-                                sacc[q][c] = fma(sgn, (double)xs[c * LDX + rb + bit], sacc[q][c]);
+                    for (int q = 0; q < SPR; ++q) {
+#pragma unroll
+                        for (int hf = 0; hf < NH; ++hf) {
+                            using MW = typename std::conditional<NH == 2, unsigned, uint64_t>::type;
+                            MW msk, sgm;
+                            if constexpr (NH == 2) {
+                                msk = hf ? mh[q] : ml[q];
+                                sgm = hf ? sh[q] : sl[q];
+                            } else {
+                                msk = ((uint64_t)mh[q] << 32) | ml[q];
+                                sgm = ((uint64_t)sh[q] << 32) | sl[q];
+                            }
+                            const int rh = rb + 32 * hf;
+                            while (msk) {
+                                const int bit = NH == 2 ? __builtin_ctz((unsigned)msk) : __builtin_ctzll((uint64_t)msk);
+                                msk &= msk - 1u;
+                                // +-1.0 from the row's sign bit for this byte
+                                const unsigned sb = (unsigned)(sgm >> bit) & 1u;
+                                const double sgn = __hiloint2double((int)((sb << 31) | 0x3FF00000u), 0);
+#pragma unroll
+                                for (int c = 0; c < W; ++c)
+                                    sacc[q][c] = fma(sgn, (double)xs[c * LDX + rh + bit], sacc[q][c]);
+                            }
                         }
                     }
                 }
