@@ -683,10 +683,12 @@ __device__ __forceinline__ void gm_small_body(const GmSmallArgs& a) {
                     col = a.Tout + (int64_t)(c - kend) * ld;
                 else
                     col = a.g;
-                double u[64];
+                // u = Rh t[k0:] in place (entry i reads only entries j >= i, still inputs), the
+                // projection term from u, then Rt u in place the same way
+                double* u = col + k0;
                 for (int i = 0; i < W; ++i) {
                     double v = 0.0;
-                    for (int j = i; j < W; ++j) v += a.Rh[i + j * W] * col[k0 + j];
+                    for (int j = i; j < W; ++j) v += a.Rh[i + j * W] * u[j];
                     u[i] = v;
                 }
                 if (a.C2) {
@@ -696,15 +698,12 @@ __device__ __forceinline__ void gm_small_body(const GmSmallArgs& a) {
                         col[r] += v;
                     }
                 }
-                for (int i = 0; i < W; ++i) {
-                    double v;
-                    if (a.Rt) {
-                        v = 0.0;
+                if (a.Rt) {
+                    for (int i = 0; i < W; ++i) {
+                        double v = 0.0;
                         for (int j = i; j < W; ++j) v += a.Rt[i + j * W] * u[j];
-                    } else {
-                        v = u[i];
+                        u[i] = v;
                     }
-                    col[k0 + i] = v;
                 }
             }
         }

@@ -82,6 +82,20 @@ def test_two_stage(B, ctx, shat, m):
     check(A, b, x.cpu().numpy(), info, ref, 1e-10, shat)
 
 
+@pytest.mark.parametrize("two_stage", [False, True])
+def test_large_restart_basis(B, ctx, two_stage):
+    """m = 80 is past what the least squares keeps in LDS (m <= 62): the Hessenberg solve and,
+    two-stage, the big-panel close run on global memory."""
+    A = wl.convdiff_2d(22, 40.0, 15.0)
+    b = wl.rhs_uniform(A.n, 6)
+    shat, k = (40, 88) if two_stage else (5, 64)
+    kw = dict(shat=shat, two_stage=True) if two_stage else {}
+    x, info, st = ctx.gmres(A, b, s=5, m=80, tol=1e-10, sketch=B.make_sketch("sparse_sign", k, 8, 1), **kw)
+    assert st == B.SKO_OK, info
+    ref = krylov.sstep_gmres(A, b, s=5, m=80, sk=Sketch.sparse_sign(k, 8, 1), tol=1e-10, **kw)
+    check(A, b, x.cpu().numpy(), info, ref, 1e-10, shat)
+
+
 def test_config5_shape_small_grid_jacobi(B, ctx):
     """Config-5 shape on a 16^3 grid: 3-D convection-diffusion, wind (10, 20, 30), Jacobi,
     two-stage s = 10, s_hat = m = 60, sparse-sign k = 128."""
