@@ -516,24 +516,32 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                 if constexpr (RED == RED_PROJ)
                     vec = (a.ldqp % 4) == 0 && ((uintptr_t)Qp % (4 * sizeof(TQ))) == 0;
                 if constexpr (RED == RED_SKETCH_DENSE) vec = (a.ldtheta % 4) == 0 && ((uintptr_t)Th % 32) == 0;
-                constexpr int GPW = STRIP / 16 / C::NWAVE;  // 16-row groups per wave
+                // rows per group: 16 (4 per lane), or 32 (8 per lane) for projections against an
+                // FP32 basis on 4 x 4 x 4 blocks: a 4-byte piece load moves half the bytes of a
+                // double one, so each lane loads two per column, as many bytes in flight as the
+                // FP64 form (the staged operand stays in float until its MFMA)
+                constexpr int UR = (RED == RED_PROJ && sizeof(TQ) == 4 && sizeof(XS) == 4 && B4) ? 8 : 4;
+                constexpr int GR = 4 * UR;
+                constexpr int GPW = STRIP / GR / C::NWAVE;  // row groups per wave
+                static_assert(STRIP % (GR * C::NWAVE) == 0, "row groups must tile the strip");
                 const int g0 = WAVE_LOCAL ? wave * GPW : wave, gstep = WAVE_LOCAL ? 1 : C::NWAVE;
                 // not unrolled: the unrolled groups hold more loads and tiles at once and cost a
                 // resident wave
 #pragma unroll 1
                 for (int gam = g0, it = 0; it < GPW; gam += gstep, ++it) {
-                    const int r0 = gam * 16 + 4 * g;  // strip-local rows r0..r0+3 for this lane
+                    const int r0 = gam * GR + UR * g;  // strip-local rows r0..r0+UR-1 for this lane
                     const bool full = base + r0 + 3 < n;
+                    const bool full2 = base + r0 + UR - 1 < n;
                     // B operands: 16 x 16 x 4 tiles take column ci of the 4 rows; 4 x 4 x 4 blocks
                     // take column 4cb + lane % 4
                     double bv[B4 ? 1 : 4];
-                    double bq[B4 ? CB : 1][4];
+                    XS bq[B4 ? CB : 1][UR];
                     if constexpr (B4) {
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb) {
                             const int col = 4 * cb + (lane & 3);
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) bq[cb][u] = (col < W) ? (double)xs[col * LDX + r0 + u] : 0.0;
+                            for (int u = 0; u < UR; ++u) bq[cb][u] = (col < W) ? xs[col * LDX + r0 + u] : XS(0);
                         }
                     } else {
 #pragma unroll
@@ -543,6 +551,31 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                     for (int m = 0; m < MT; ++m) {
                         if (m < ntiles) {
                             const int col = 16 * m + ci;
+                            if constexpr (UR == 8) {
+                                // the 8 pieces stay in float until their MFMA
+                                float af[8];
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) af[u] = 0.0f;
+                                if (col < a.red_rows) {
+                                    const float* qc = reinterpret_cast<const float*>(Qp) + (int64_t)col * a.ldqp + base + r0;
+                                    if (vec && full2) {
+                                        const float4 v0 = *reinterpret_cast<const float4*>(qc);
+                                        const float4 v1 = *reinterpret_cast<const float4*>(qc + 4);
+                                        af[0] = v0.x; af[1] = v0.y; af[2] = v0.z; af[3] = v0.w;
+                                        af[4] = v1.x; af[5] = v1.y; af[6] = v1.z; af[7] = v1.w;
+                                    } else {
+#pragma unroll
+                                        for (int u = 0; u < 8; ++u) af[u] = (base + r0 + u < n) ? qc[u] : 0.0f;
+                                    }
+                                }
+#pragma unroll
+                                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                                    for (int cb = 0; cb < CB; ++cb)
+                                        acc4[m * CB + cb] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                                            (double)af[u], (double)bq[cb][u], acc4[m * CB + cb], 0, 0, 0);
+                                continue;
+                            }
                             double av[4] = {0.0, 0.0, 0.0, 0.0};
                             if (col < a.red_rows) {
                                 if constexpr (RED == RED_PROJ)
@@ -555,8 +588,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int wg, const
                                 for (int u = 0; u < 4; ++u)
 #pragma unroll
                                     for (int cb = 0; cb < CB; ++cb)
-                                        acc4[m * CB + cb] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[u], bq[cb][u],
-                                                                                               acc4[m * CB + cb], 0, 0, 0);
+                                        acc4[m * CB + cb] = __builtin_amdgcn_mfma_f64_4x4x4f64(
+                                            av[u], (double)bq[cb][u], acc4[m * CB + cb], 0, 0, 0);
                             } else {
 #pragma unroll
                                 for (int u = 0; u < 4; ++u)
