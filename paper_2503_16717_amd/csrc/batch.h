@@ -10,6 +10,14 @@
 //     regions laid out one after another, so the offset is sys * region size.
 // Per-system scalars (row count, CSR operator, b, x, D^{-1}, sketch seed) come from the
 // system table.
+//
+// The relocation is by address range, so it relies on one invariant: every pointer argument
+// of a batched kernel is per-system data inside one of the four template regions, and data
+// shared by all systems (the system table, the active list, the flat launch's block starts)
+// travels in BatchReloc itself, never as a pointer argument.  batch_regions_disjoint checks
+// on the host that the template regions overlap neither each other nor those shared arrays,
+// so no shared datum can be taken for a template one.  Leading dimensions go through
+// batch_ld only for tall operands (basis columns), never for the small dense arrays.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -56,6 +64,24 @@ struct BatchReloc {
     int nblk;
     int chunk;
 };
+
+// Host check of the invariant above: the template regions of `br` are pairwise disjoint and
+// disjoint from each of the `nshared` byte ranges [shared[i], shared[i] + shared_bytes[i]).
+inline bool batch_regions_disjoint(const BatchReloc& br, const void* const* shared, const int64_t* shared_bytes,
+                                   int nshared) {
+    const char* lo[4] = {br.q0, br.ws0, br.part0, br.cnt0};
+    const int64_t len[4] = {br.q0_bytes, br.ws_bytes, br.part_bytes, br.cnt_bytes};
+    auto overlap = [](const char* a, int64_t na, const char* b, int64_t nb) {
+        return a && b && na > 0 && nb > 0 && a < b + nb && b < a + na;
+    };
+    for (int i = 0; i < 4; ++i) {
+        for (int j = i + 1; j < 4; ++j)
+            if (overlap(lo[i], len[i], lo[j], len[j])) return false;
+        for (int k = 0; k < nshared; ++k)
+            if (overlap(lo[i], len[i], static_cast<const char*>(shared[k]), shared_bytes[k])) return false;
+    }
+    return true;
+}
 
 #ifdef __HIPCC__
 // System served by this workgroup.

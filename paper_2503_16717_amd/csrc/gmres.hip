@@ -987,6 +987,13 @@ sko_status gmres_batched_impl(sko_ctx c, int32_t nsys, const sko_csr* A, const d
     br.cnt0 = nullptr;
     br.cnt_bytes = 0;
     br.blk0 = blk_d;
+    {
+        // the arena carves every region one after another, so this holds by construction
+        const void* shared[3] = {tbl_d, act_d, blk_d};
+        const int64_t shared_bytes[3] = {(int64_t)sizeof(BatchSys) * nsys, (int64_t)sizeof(int) * nsys,
+                                         (int64_t)sizeof(int) * (nsys + 1)};
+        if (!batch_regions_disjoint(br, shared, shared_bytes, 3)) return SKO_EINVAL;
+    }
     const int flat_unit = spmv_flat_unit(g.f32, g.avg_nnz);
     g.br = &br;
 
